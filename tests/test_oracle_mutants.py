@@ -1,0 +1,86 @@
+"""The pins must catch plausible mistakes in the oracle.
+
+Each case copies oracle.c, plants one mistake (a dropped term, a wrong index,
+sign or bias, a reversed order, a wrong rounding rule), builds the copy on the
+CPU and runs the pin suite against it in a subprocess: the suite must fail.
+"""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+ORACLE_C = os.path.join(ROOT, "oracle", "oracle.c")
+
+MUTANTS = {
+    "int_sum_drops_last_rank": (
+        "for (int r = 0; r < P; ++r) acc += (uint32_t)x[r][i];",
+        "for (int r = 0; r < P - 1; ++r) acc += (uint32_t)x[r][i];"),
+    "int_max_wrong_comparison": (
+        "int32_t m = x[0][i];\n    for (int r = 1; r < P; ++r)\n"
+        "      if (x[r][i] > m) m = x[r][i];",
+        "int32_t m = x[0][i];\n    for (int r = 1; r < P; ++r)\n"
+        "      if (x[r][i] < m) m = x[r][i];"),
+    "f64_sum_skips_rank0": (
+        "for (int r = 0; r < P; ++r) acc += (double)x[r][i];\n    y[i] = acc;"
+        "\n  }\n}\n\nvoid orc_sum_f32_f64_omp",
+        "for (int r = 1; r < P; ++r) acc += (double)x[r][i];\n    y[i] = acc;"
+        "\n  }\n}\n\nvoid orc_sum_f32_f64_omp"),
+    "f64_sum_wrong_index": (
+        "for (int r = 0; r < P; ++r) acc += (double)x[r][i];\n    y[i] = acc;"
+        "\n  }\n}\n\nvoid orc_sum_f32_f64_omp",
+        "for (int r = 0; r < P; ++r) acc += (double)x[r][i ^ 1];\n"
+        "    y[i] = acc;\n  }\n}\n\nvoid orc_sum_f32_f64_omp"),
+    "f32_sum_reversed_order": (
+        "float acc = v[0];\n    for (int r = 1; r < P; ++r) acc = acc + v[r];",
+        "float acc = v[P - 1];\n    for (int r = P - 2; r >= 0; --r) "
+        "acc = acc + v[r];"),
+    "twosum_sign_flip": (
+        "*e = (a - av) + (b - bv);", "*e = (a - av) - (b - bv);"),
+    "sum2_drops_correction": (
+        "return p + sigma;", "return p;"),
+    "bf16_decode_bias": (
+        "v = ldexp((double)(128 + f), e - 127 - 7);",
+        "v = ldexp((double)(128 + f), e - 128 - 7);"),
+    "bf16_encode_ties_away": (
+        "if (frac > 0.5 || (frac == 0.5 && fmod(lo, 2.0) != 0.0)) lo += 1.0;",
+        "if (frac >= 0.5) lo += 1.0;"),
+    "e4m3_decode_bias": (
+        "v = ldexp((double)(8 + f), e - 7 - 3);",
+        "v = ldexp((double)(8 + f), e - 8 - 3);"),
+    "e4m3_no_subnormals": (
+        "if (ufp < -6) ufp = -6; /* subnormals: quantum 2^-9 */",
+        "if (ufp < -7) ufp = -7;"),
+    "e4m3_scale_uses_240": (
+        "float s = amax / 448.0f;", "float s = amax / 240.0f;"),
+    "e4m3_sum_wrong_block": (
+        "acc += orc_e4m3_decode(q[r][i]) * (double)s[r][i / 256];",
+        "acc += orc_e4m3_decode(q[r][i]) * (double)s[r][i / 128];"),
+    "e4m3_mirror_transposed_scale": (
+        "v[r] = (float)orc_e4m3_decode(q[r][i]) * s[r][b];",
+        "v[r] = (float)orc_e4m3_decode(q[r][i]) * s[0][b];"),
+    "plan_floor_instead_of_ceil": (
+        "int64_t psize = (count + nparts - 1) / nparts;",
+        "int64_t psize = count / nparts + (count > 0);"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_mutant(name, tmp_path):
+    sys.path.insert(0, ROOT)
+    from oracle import build as obuild
+
+    old, new = MUTANTS[name]
+    src = open(ORACLE_C).read()
+    assert src.count(old) == 1, f"mutation site not unique/absent: {name}"
+    mut = tmp_path / "oracle_mutant.c"
+    mut.write_text(src.replace(old, new))
+    lib = str(tmp_path / "liboracle_mutant.so")
+    obuild.build(out=lib, src=str(mut))
+    env = dict(os.environ, ORACLE_LIB=lib)
+    r = subprocess.run(
+        [sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+         os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, f"pins did not catch mutant {name}:\n{r.stdout}"

@@ -1,0 +1,520 @@
+"""Pins of the CPU oracle to facts fixed outside it.
+
+Each test checks the oracle against something it cannot agree with by
+construction: hand-worked fixtures from the format definitions and from the
+chunk rule of Algorithm 1 (tests/golden), exact rational arithmetic
+(fractions.Fraction), Shewchuk's exactly rounded sum (math.fsum), library
+casts (torch bfloat16 / float8_e4m3fn), closed forms and invariants of sum and
+max, and published error bounds of recursive and compensated summation.
+"""
+import itertools
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import Oracle, get as get_oracle
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+U32 = 2.0 ** -24  # unit roundoff of binary32
+
+
+@pytest.fixture(scope="module")
+def orc():
+    # ORACLE_LIB points the pins at a deliberately broken copy of the oracle
+    # (see test_oracle_mutants.py); normally it is unset.
+    path = os.environ.get("ORACLE_LIB")
+    return Oracle(path) if path else get_oracle()
+
+
+def _rows(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                yield line
+
+
+def _num(tok):
+    return float.fromhex(tok) if tok.lower().startswith(("0x", "-0x")) \
+        else float(tok)
+
+
+def _gamma(k, u=U32):
+    return k * u / (1 - k * u)
+
+
+# --------------------------------------------------------------------------
+# partition plan: Algorithm 1 chunk rule
+# --------------------------------------------------------------------------
+def test_plan_matches_hand_worked_fixtures(orc):
+    for line in _rows("plan_alg1.txt"):
+        head, offs, lens = [s.split() for s in line.split("|")]
+        count, nparts, align = map(int, head)
+        _, off, ln = orc.plan(count, nparts, align)
+        assert off.tolist() == [int(v) for v in offs], line
+        assert ln.tolist() == [int(v) for v in lens], line
+
+
+def test_plan_brute_force_properties(orc):
+    """Disjoint, contiguous cover of [0, count); every chunk but the clipped
+    tail has the common length; the common length is the smallest multiple
+    of `align` whose nparts copies cover the message."""
+    for align in (1, 4, 8, 256):
+        for count in list(range(0, 130)) + [255, 256, 257, 299, 300]:
+            for nparts in (1, 2, 3, 5, 7, 8, 16, 64, 70):
+                ps, off, ln = orc.plan(count, nparts, align)
+                assert ps % align == 0
+                assert ps * nparts >= count
+                assert count == 0 or (ps - align) * nparts < count
+                assert int(ln.sum()) == count
+                pos = 0
+                for k in range(nparts):
+                    assert off[k] == pos
+                    assert 0 <= ln[k] <= ps
+                    pos += ln[k]
+                full = [k for k in range(nparts) if ln[k] == ps]
+                nonempty = [k for k in range(nparts) if ln[k] > 0]
+                # only the last non-empty chunk may be short
+                assert all(k in full for k in nonempty[:-1])
+
+
+def test_plan_rejects_bad_arguments(orc):
+    with pytest.raises(ValueError):
+        orc.plan(10, 0)
+    with pytest.raises(ValueError):
+        orc.plan(-1, 4)
+
+
+# --------------------------------------------------------------------------
+# int32 sum / max
+# --------------------------------------------------------------------------
+def _wrap32(v):
+    v &= 0xFFFFFFFF
+    return v - (1 << 32) if v >= (1 << 31) else v
+
+
+def test_int32_brute_force(orc):
+    rng = np.random.default_rng(1)
+    for P in (1, 2, 3, 5, 16):
+        for n in (0, 1, 2, 3, 7, 8, 9, 255, 256, 257):
+            xs = [rng.integers(-2**31, 2**31, n, dtype=np.int64)
+                  .astype(np.int32) for _ in range(P)]
+            ys = orc.sum_i32(xs)
+            ym = orc.max_i32(xs)
+            for i in range(n):
+                vals = [int(x[i]) for x in xs]
+                assert ys[i] == _wrap32(sum(vals))
+                assert ym[i] == max(vals)
+
+
+def test_int32_closed_forms(orc):
+    n = 1000
+    for P in (1, 2, 3, 8, 16):
+        ones = [np.ones(n, np.int32) for _ in range(P)]
+        assert (orc.sum_i32(ones) == P).all()
+        ramp = [np.full(n, r + 1, np.int32) for r in range(P)]
+        assert (orc.sum_i32(ramp) == P * (P + 1) // 2).all()
+        assert (orc.max_i32(ramp) == P).all()
+    x = np.arange(-500, 500, dtype=np.int32)
+    assert (orc.sum_i32([x, -x]) == 0).all()
+    big = np.full(4, 2**31 - 1, np.int32)
+    assert (orc.sum_i32([big, np.ones(4, np.int32)]) == -2**31).all()
+
+
+def test_int32_permutation_invariance(orc):
+    rng = np.random.default_rng(2)
+    P, n = 16, 4096
+    xs = [rng.integers(-2**20, 2**20 + 1, n).astype(np.int32)
+          for _ in range(P)]
+    ys, ym = orc.sum_i32(xs), orc.max_i32(xs)
+    for _ in range(20):
+        perm = rng.permutation(P)
+        zs = [xs[i] for i in perm]
+        assert np.array_equal(orc.sum_i32(zs), ys)
+        assert np.array_equal(orc.max_i32(zs), ym)
+    P = 4
+    for perm in itertools.permutations(range(P)):
+        zs = [xs[i] for i in perm]
+        assert np.array_equal(orc.sum_i32(zs), orc.sum_i32(xs[:P]))
+    stack = np.stack(xs)
+    assert (ym[None, :] >= stack).all()
+    assert ((stack == ym[None, :]).any(axis=0)).all()
+
+
+# --------------------------------------------------------------------------
+# float32 payload: FP64 reference and FP32 mirrors
+# --------------------------------------------------------------------------
+def test_f64_exact_on_grid_inputs(orc):
+    """Uniform draws on a 2^-24 grid in [-1, 1): their exact sum over <= 16
+    ranks has <= 29 significant bits, so the FP64 reference must equal the
+    exact rational sum."""
+    g = torch.Generator().manual_seed(3)
+    for P in (1, 2, 4, 8, 16):
+        xs = [(torch.rand(300, generator=g) * 2 - 1).numpy()
+              for _ in range(P)]
+        y = orc.sum_f32_f64(xs)
+        for i in range(300):
+            exact = sum(Fraction(float(x[i])) for x in xs)
+            assert Fraction(float(y[i])) == exact
+
+
+def test_f64_against_fsum_bound(orc):
+    rng = np.random.default_rng(4)
+    for P in (2, 8, 16):
+        xs = [(rng.standard_normal(2000) *
+               np.exp(rng.uniform(-20, 20, 2000))).astype(np.float32)
+              for _ in range(P)]
+        y = orc.sum_f32_f64(xs)
+        for i in range(0, 2000, 7):
+            vals = [float(x[i]) for x in xs]
+            ex = math.fsum(vals)
+            bound = _gamma(P - 1, 2.0 ** -53) * sum(abs(v) for v in vals)
+            assert abs(y[i] - ex) <= bound
+
+
+def test_f64_omp_variant_bitwise(orc):
+    rng = np.random.default_rng(5)
+    xs = [rng.standard_normal(100_003).astype(np.float32) for _ in range(8)]
+    assert np.array_equal(orc.sum_f32_f64(xs),
+                          orc.sum_f32_f64(xs, threads=True))
+
+
+def test_f32_order_is_left_to_right(orc):
+    a = [np.float32([1.0]), np.float32([2.0 ** -24]), np.float32([2.0 ** -24])]
+    # fl(fl(1 + 2^-24) + 2^-24) = 1 (two ties to even); any other order of
+    # accumulation gives 1 + 2^-23.
+    assert orc.sum_f32_f32(a)[0] == np.float32(1.0)
+    assert orc.sum_f32_f32(a[::-1])[0] == np.float32(1.0 + 2.0 ** -23)
+
+
+def test_f32_powers_of_two_exact(orc):
+    """Values with at most 20 significant bits: every partial sum k*x
+    (k <= 16) is representable, so P copies sum to P*x exactly."""
+    rng = np.random.default_rng(6)
+    x = (rng.integers(-2**19, 2**19, 5000) * 2.0 ** -10).astype(np.float32)
+    for P in (1, 2, 4, 8, 16):
+        for comp in (False, True):
+            y = orc.sum_f32_f32([x] * P, comp=comp)
+            assert np.array_equal(y, (x * np.float32(P)).astype(np.float32))
+
+
+def test_f32_recursive_summation_bound(orc):
+    """|y32 - S| <= gamma_{P-1} sum|x|: the forward error bound of recursive
+    summation (Higham, Accuracy and Stability, 2nd ed., eq. (4.4))."""
+    rng = np.random.default_rng(7)
+    for P in (2, 3, 8, 16):
+        xs = [rng.standard_normal(3000).astype(np.float32) for _ in range(P)]
+        y = orc.sum_f32_f32(xs)
+        for i in range(0, 3000, 11):
+            vals = [float(x[i]) for x in xs]
+            ex = math.fsum(vals)
+            assert abs(float(y[i]) - ex) <= _gamma(P - 1) * sum(map(abs, vals))
+
+
+def test_f32_integers_exact(orc):
+    xs = [np.arange(r, r + 1000, dtype=np.float32) for r in range(8)]
+    assert np.array_equal(orc.sum_f32_f32(xs),
+                          (8 * np.arange(1000) + 28).astype(np.float32))
+
+
+def test_sum2_special_case(orc):
+    a = [np.float32([1.0]), np.float32([2.0 ** -30]), np.float32([-1.0])]
+    assert orc.sum_f32_f32(a, comp=False)[0] == 0.0
+    assert orc.sum_f32_f32(a, comp=True)[0] == np.float32(2.0 ** -30)
+
+
+def test_sum2_two_terms_is_rounded_sum(orc):
+    rng = np.random.default_rng(8)
+    a, b = [rng.standard_normal(10000).astype(np.float32) for _ in range(2)]
+    assert np.array_equal(orc.sum_f32_f32([a, b], comp=True), a + b)
+
+
+def test_sum2_error_bound(orc):
+    """Ogita-Rump-Oishi (2005) Prop. 4.5: |res - S| <= u|S| +
+    gamma_{n-1}^2 sum|x|, checked against exact rational sums, on
+    ill-conditioned inputs where plain recursive summation fails it."""
+    rng = np.random.default_rng(9)
+    P, n = 16, 400
+    base = rng.standard_normal((P, n)) * np.exp(rng.uniform(-8, 8, (P, n)))
+    base[-1] = -base[:-1].sum(axis=0) + rng.standard_normal(n) * 1e-6
+    xs = [b.astype(np.float32) for b in base]
+    yc = orc.sum_f32_f32(xs, comp=True)
+    yp = orc.sum_f32_f32(xs, comp=False)
+    plain_violations = 0
+    for i in range(n):
+        vals = [Fraction(float(x[i])) for x in xs]
+        S = sum(vals)
+        absum = sum(abs(v) for v in vals)
+        bound = U32 * abs(S) + Fraction(_gamma(P - 1)) ** 2 * absum
+        assert abs(Fraction(float(yc[i])) - S) <= bound
+        plain_violations += abs(Fraction(float(yp[i])) - S) > bound
+    assert plain_violations > n // 4
+
+
+def test_max_f32(orc):
+    rng = np.random.default_rng(10)
+    xs = [rng.standard_normal(4000).astype(np.float32) for _ in range(5)]
+    y = orc.max_f32(xs)
+    st = np.stack(xs)
+    assert (y[None] >= st).all() and (st == y[None]).any(axis=0).all()
+    for perm in itertools.permutations(range(5)):
+        assert np.array_equal(orc.max_f32([xs[i] for i in perm]), y)
+
+
+# --------------------------------------------------------------------------
+# bfloat16 codec and sums
+# --------------------------------------------------------------------------
+def test_bf16_golden_values(orc):
+    for line in _rows("bf16_values.txt"):
+        code, val = line.split()
+        v = orc.bf16_decode(int(code, 16))
+        assert v == float(val) and math.copysign(1, v) == math.copysign(
+            1, float(val)), line
+        if not math.isinf(float(val)):
+            assert orc.bf16_encode(float(val)) == int(code, 16)
+
+
+def test_bf16_rounding_fixtures(orc):
+    for line in _rows("bf16_rounding.txt"):
+        val, code = line.split()
+        assert orc.bf16_encode(_num(val)) == int(code, 16), line
+
+
+def test_bf16_decode_table_vs_torch(orc):
+    table = orc.bf16_decode_table()
+    codes = torch.arange(-32768, 32768, dtype=torch.int32).to(torch.int16)
+    ref = codes.view(torch.bfloat16).to(torch.float64).numpy()
+    ref = np.concatenate([ref[32768:], ref[:32768]])  # code order 0..65535
+    nan = np.isnan(ref)
+    assert np.array_equal(np.isnan(table), nan)
+    assert np.array_equal(table[~nan], ref[~nan])
+
+
+def test_bf16_encode_vs_torch_cast(orc):
+    g = torch.Generator().manual_seed(11)
+    x = torch.randn(20000, generator=g) * torch.exp(
+        torch.empty(20000).uniform_(-80, 80, generator=g))
+    ties = (torch.randint(0, 1 << 16, (4000,), generator=g, dtype=torch.int32)
+            << 16 | 0x8000).view(torch.float32)
+    x = torch.cat([x, ties, torch.tensor([0.0, -0.0, 1e-45, -1e-45, 3e38])])
+    x = x[torch.isfinite(x)]
+    ref = x.to(torch.bfloat16).view(torch.int16).numpy().astype(np.uint16)
+    got = orc.bf16_encode_array(x.numpy())
+    assert np.array_equal(got, ref)
+
+
+def test_bf16_encode_is_nearest_even_brute_force(orc):
+    table = orc.bf16_decode_table()
+    pos = np.arange(0, 0x7f80)  # finite non-negative codes, increasing
+    vals = table[pos]
+    rng = np.random.default_rng(12)
+    for v in np.concatenate([rng.uniform(0, 4, 300),
+                             np.exp(rng.uniform(-95, 88, 300))]):
+        k = np.searchsorted(vals, v)
+        cands = [c for c in (k - 1, k) if 0 <= c < len(vals)]
+        best = min(cands, key=lambda c: (abs(vals[c] - v), pos[c] & 1))
+        assert orc.bf16_encode(v) == pos[best]
+
+
+def test_bf16_sums(orc):
+    rng = np.random.default_rng(13)
+    P, n = 8, 5000
+    xs32 = [rng.standard_normal(n).astype(np.float32) * 1e-3
+            for _ in range(P)]
+    xs = [torch.from_numpy(x).to(torch.bfloat16).view(torch.int16).numpy()
+          .view(np.uint16) for x in xs32]
+    y64 = orc.sum_bf16_f64(xs)
+    dec = [torch.from_numpy(x.view(np.int16)).view(torch.bfloat16)
+           .to(torch.float64).numpy() for x in xs]
+    for i in range(0, n, 13):
+        assert Fraction(float(y64[i])) == sum(Fraction(float(d[i]))
+                                              for d in dec)
+    for comp in (False, True):
+        yq, y32 = orc.sum_bf16_f32(xs, comp=comp)
+        ref = torch.from_numpy(y32).to(torch.bfloat16).view(torch.int16)
+        assert np.array_equal(yq, ref.numpy().view(np.uint16))
+        absum = np.sum(np.abs(np.stack(dec)), axis=0)
+        yv = np.array([orc.bf16_decode(c) for c in yq[:2000]])
+        e = np.abs(yv - y64[:2000]) / np.maximum(absum[:2000], 1e-38)
+        assert e.max() <= 4e-3
+    # identity and powers of two
+    assert np.array_equal(orc.sum_bf16_f32(xs[:1])[0], xs[0])
+    for P in (2, 4, 8, 16):
+        yq, _ = orc.sum_bf16_f32([xs[0]] * P)
+        twice = torch.from_numpy(xs[0].view(np.int16)).view(torch.bfloat16) \
+            .to(torch.float64) * P
+        assert np.array_equal(yq, twice.to(torch.bfloat16).view(torch.int16)
+                              .numpy().view(np.uint16))
+
+
+def test_bf16_max(orc):
+    rng = np.random.default_rng(14)
+    xs32 = [rng.standard_normal(3000).astype(np.float32) for _ in range(6)]
+    xs = [torch.from_numpy(x).to(torch.bfloat16).view(torch.int16).numpy()
+          .view(np.uint16) for x in xs32]
+    y = orc.max_bf16(xs)
+    dec = np.stack([torch.from_numpy(x.view(np.int16)).view(torch.bfloat16)
+                    .to(torch.float64).numpy() for x in xs])
+    yd = torch.from_numpy(y.view(np.int16)).view(torch.bfloat16) \
+        .to(torch.float64).numpy()
+    assert np.array_equal(yd, dec.max(axis=0))
+
+
+# --------------------------------------------------------------------------
+# e4m3 codec, block scaling and sums
+# --------------------------------------------------------------------------
+def test_e4m3_golden_values(orc):
+    for line in _rows("e4m3_ocp_values.txt"):
+        code, val = line.split()
+        v = orc.e4m3_decode(int(code, 16))
+        if val == "nan":
+            assert math.isnan(v)
+            continue
+        assert v == float(val) and math.copysign(1, v) == math.copysign(
+            1, float(val)), line
+        assert orc.e4m3_encode(float(val)) == int(code, 16), line
+
+
+def test_e4m3_rounding_fixtures(orc):
+    for line in _rows("e4m3_rounding.txt"):
+        val, code = line.split()
+        assert orc.e4m3_encode(_num(val)) == int(code, 16), line
+
+
+def test_e4m3_decode_table_vs_torch(orc):
+    table = orc.e4m3_decode_table()
+    ref = torch.arange(256, dtype=torch.int32).to(torch.uint8) \
+        .view(torch.float8_e4m3fn).to(torch.float64).numpy()
+    nan = np.isnan(ref)
+    assert nan.sum() == 2
+    assert np.array_equal(np.isnan(table), nan)
+    assert np.array_equal(table[~nan], ref[~nan])
+
+
+def test_e4m3_encode_vs_torch_cast(orc):
+    g = torch.Generator().manual_seed(15)
+    x = torch.randn(20000, generator=g) * torch.exp(
+        torch.empty(20000).uniform_(-12, 7, generator=g))
+    x = torch.cat([x, torch.tensor([0.0, -0.0, 448.0, -448.0, 2.0 ** -9,
+                                    2.0 ** -10, 3 * 2.0 ** -10])])
+    clamped = x.clamp(-448, 448)
+    ref = clamped.to(torch.float8_e4m3fn).view(torch.uint8).numpy()
+    got = np.array([orc.e4m3_encode(float(v)) for v in x], np.uint8)
+    assert np.array_equal(got, ref)
+
+
+def test_e4m3_encode_is_nearest_even_brute_force(orc):
+    table = orc.e4m3_decode_table()
+    pos = np.arange(0, 0x7f)
+    vals = table[pos]
+    rng = np.random.default_rng(16)
+    for v in np.concatenate([rng.uniform(0, 448, 500),
+                             np.exp(rng.uniform(-9, 6, 500)),
+                             vals[:-1] + np.diff(vals) / 2]):
+        k = np.searchsorted(vals, v)
+        cands = [c for c in (k - 1, k) if 0 <= c < len(vals)]
+        best = min(cands, key=lambda c: (abs(vals[c] - v), pos[c] & 1))
+        assert orc.e4m3_encode(v) == pos[best], v
+
+
+def test_e4m3_pack_properties(orc):
+    rng = np.random.default_rng(17)
+    n = 256 * 40 + 77  # ragged last block
+    x = (rng.standard_normal(n) * np.exp(rng.uniform(-6, 6, n))) \
+        .astype(np.float32)
+    x[256:512] = 0.0  # an all-zero block
+    q, s = orc.e4m3_pack(x)
+    table = orc.e4m3_decode_table()
+    assert len(s) == (n + 255) // 256
+    for b in range(len(s)):
+        blk = x[b * 256:(b + 1) * 256]
+        qb = q[b * 256:(b + 1) * 256]
+        amax = float(np.abs(blk).max())
+        if amax == 0.0:
+            assert s[b] == 1.0 and (qb & 0x7f == 0).all()
+            continue
+        assert s[b] == np.float32(np.float32(amax) / np.float32(448.0))
+        mags = np.abs(table[qb])
+        assert mags.max() == 448.0  # the largest element maps to +-448
+        # quantization error: half a quantum of the e4m3 grid, relative to
+        # the element (2^-4), plus the subnormal floor s * 2^-10, plus the
+        # binary32 rounding of x / s (2 ulp).
+        deq = table[qb] * float(s[b])
+        err = np.abs(deq - blk.astype(np.float64))
+        lim = np.abs(blk) * (2.0 ** -4 + 4 * U32) + float(s[b]) * 2.0 ** -10
+        assert (err <= lim).all()
+        assert (np.sign(table[qb]) * np.sign(blk) >= 0).all()
+
+
+def _pack_ranks(orc, xs32):
+    qs, ss = [], []
+    for x in xs32:
+        q, s = orc.e4m3_pack(x)
+        qs.append(q)
+        ss.append(s)
+    return qs, ss
+
+
+def test_e4m3_sum_reference_exact(orc):
+    rng = np.random.default_rng(18)
+    P, n = 8, 256 * 6 + 31
+    xs32 = [(rng.standard_normal(n) * 1e-2).astype(np.float32)
+            for _ in range(P)]
+    qs, ss = _pack_ranks(orc, xs32)
+    y64 = orc.sum_e4m3_f64(qs, ss)
+    table = orc.e4m3_decode_table()
+    for i in range(0, n, 5):
+        exact = sum(Fraction(float(table[qs[r][i]])) *
+                    Fraction(float(ss[r][i // 256])) for r in range(P))
+        assert Fraction(float(y64[i])) == exact
+
+
+def test_e4m3_sum_identity_and_powers_of_two(orc):
+    rng = np.random.default_rng(19)
+    n = 256 * 9 + 100
+    x = (rng.standard_normal(n) * 1e-2).astype(np.float32)
+    q, s = orc.e4m3_pack(x)
+    for comp in (False, True):
+        yq, ys, _ = orc.sum_e4m3_f32([q], [s], comp=comp)
+        assert np.array_equal(yq, q)
+        assert np.allclose(ys, s, rtol=2 * U32, atol=0)
+        for P in (2, 4, 8, 16):
+            zq, zs, _ = orc.sum_e4m3_f32([q] * P, [s] * P, comp=comp)
+            assert np.array_equal(zq, yq)
+            if comp:
+                # Sum2 is faithful on same-sign data, so the representable
+                # P * v comes out exactly and every step scales by P.
+                assert np.array_equal(zs, ys * np.float32(P))
+            else:
+                assert np.allclose(zs, ys * np.float32(P), rtol=4 * U32,
+                                   atol=0)
+
+
+def test_e4m3_sum_error_within_tolerance(orc):
+    """Workload-5 shaped inputs: N(0, 1e-2) with 1% outliers at 50x."""
+    rng = np.random.default_rng(20)
+    P, n = 8, 256 * 64
+    xs32 = []
+    for _ in range(P):
+        x = rng.standard_normal(n) * 1e-2
+        m = rng.uniform(size=n) < 0.01
+        x[m] *= 50
+        xs32.append(x.astype(np.float32))
+    qs, ss = _pack_ranks(orc, xs32)
+    y64 = orc.sum_e4m3_f64(qs, ss)
+    table = orc.e4m3_decode_table()
+    deq = np.stack([table[qs[r]] * np.repeat(ss[r].astype(np.float64),
+                                            256)[:n] for r in range(P)])
+    absum = np.abs(deq).sum(axis=0)
+    for comp in (False, True):
+        yq, ys, y32 = orc.sum_e4m3_f32(qs, ss, comp=comp)
+        yv = table[yq] * np.repeat(ys.astype(np.float64), 256)[:n]
+        tau = np.repeat(ys.astype(np.float64), 256)[:n] * 2.0 ** -6
+        e = np.abs(yv - y64) / np.maximum(absum, tau)
+        assert e.max() <= 6e-2
+        e32 = np.abs(y32 - y64) / np.maximum(absum, 1e-38)
+        assert e32.max() <= (_gamma(P - 1) + U32 if not comp else 3 * U32)
