@@ -1,0 +1,274 @@
+/*
+ * pcoll -- partitioned reduction of P rank contributions on one MI355X
+ * (gfx950).  C ABI of libpcoll.so.
+ *
+ * The operation.  A request reduces one message (or, batched, many
+ * messages called buckets) of `count` elements held by P ranks:
+ *   out[i] = in_0[i] (op) in_1[i] (op) ... (op) in_{P-1}[i],
+ * op = sum or max, each element in rank order 0..P-1.  The P rank buffers
+ * live in this GPU's memory (they stand for the contributions of P peer
+ * ranks).  The paper this library follows (Sojoodi et al., "Accelerating
+ * Intra-Node GPU-to-GPU Communication Through Multi-Path Transfers with CUDA
+ * Graphs") builds point-to-point multi-path copies and names Allreduce as
+ * future work (Section 6); the reduction arithmetic is the plain definition
+ * of elementwise sum / max.
+ *
+ * Partitions.  Each message is cut into `nparts` partitions by the chunk
+ * rule of Algorithm 1 (Section 4.3): every partition has the same length
+ * psize = ceil(count / nparts) rounded up to whole 16-byte vectors (to 256
+ * elements for PCOLL_FP8_E4M3, the scale block), offsets are fixed in
+ * advance as running sums, and the last partitions are clipped (possibly to
+ * zero length).  Destination regions are disjoint (Section 4.5, Ordering
+ * Guarantee): each partition of the output is written exactly once per
+ * epoch, whatever order partitions are readied in.
+ *
+ * Life cycle (persistent request, one epoch per start):
+ *   init -> bind -> { start -> pready(p)... -> parrived / test / wait }* -> free
+ * `start` launches one persistent kernel (or replays its cached graph) on
+ * the bound stream and returns at once.  `pready(p)` declares that every
+ * rank's contribution to partition p is in place; the kernel reduces
+ * partitions in the order they become ready.  `parrived(p)` tells whether
+ * partition p of the output is final.  `wait` returns once every partition
+ * has arrived (completion is signalled only after every chunk has landed,
+ * Section 4.5, Final Synchronization).
+ *
+ * Memory and ownership.  The caller owns every data buffer (device memory,
+ * e.g. torch tensors); the library keeps raw pointers only.  Rank buffers of
+ * partition p must stay unchanged from pready(p) until p has arrived; the
+ * output region of p must not be touched by others before that.  All device
+ * pointers must be 16-byte aligned.  The library owns its flags, counters,
+ * descriptor tables, graphs and events.
+ *
+ * Errors.  Every call returns PCOLL_SUCCESS (0) or a negative code; on
+ * error the request state is unchanged.  No C++ exception crosses this ABI.
+ * Calls on one request must come from one host thread at a time; separate
+ * requests may be used from separate threads and streams.
+ *
+ * Streams are hipStream_t values passed as void* (NULL = the null stream).
+ */
+#ifndef PCOLL_H
+#define PCOLL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pcoll_req_s *pcoll_req_t; /* opaque, library-owned */
+
+typedef enum {
+  PCOLL_INT32 = 0,     /* two's-complement wrap sum, max: bit-exact */
+  PCOLL_FLOAT32 = 1,   /* binary32 in and out, binary32 accumulation */
+  PCOLL_BFLOAT16 = 2,  /* bf16 in and out, binary32 accumulation, RNE out */
+  PCOLL_FP8_E4M3 = 3   /* OCP e4m3 codes + one binary32 scale per 256
+                          elements (value = code * scale), binary32
+                          accumulation, output re-quantized per 256 */
+} pcoll_dtype_t;
+
+typedef enum { PCOLL_SUM = 0, PCOLL_MAX = 1 } pcoll_op_t;
+
+enum {
+  PCOLL_SUCCESS = 0,
+  PCOLL_ERR_ARG = -1,         /* bad argument: null, range, alignment */
+  PCOLL_ERR_STATE = -2,       /* call not valid in the request's state */
+  PCOLL_ERR_UNSUPPORTED = -3, /* dtype/op/rank-count combination */
+  PCOLL_ERR_HIP = -4,         /* a HIP runtime call failed */
+  PCOLL_ERR_TIMEOUT = -5,     /* not every partition arrived in time */
+  PCOLL_ERR_NOMEM = -6,       /* host or device allocation failed */
+  PCOLL_ERR_ABORTED = -7      /* the kernel gave up on its own deadline */
+};
+
+#define PCOLL_MAX_RANKS 16
+#define PCOLL_VERSION 1
+
+/* ---------------------------------------------------------------- setup */
+
+/* Creates a request for one message of `count` elements (count >= 0) of
+ * `dtype`, reduced with `op` over `nranks` ranks (1..PCOLL_MAX_RANKS), split
+ * into `nparts` >= 1 partitions.  Allocates the request's flags (host-
+ * coherent pinned memory) and counters (device memory) on the current HIP
+ * device.  PCOLL_ERR_UNSUPPORTED for max on PCOLL_FP8_E4M3. */
+int pcoll_init(size_t count, int dtype, int op, int nparts, int nranks,
+               pcoll_req_t *out);
+
+/* Batched form: `nbuckets` >= 1 messages of counts[b] elements, each split
+ * into `nparts_per_bucket` partitions; partition k of bucket b has the
+ * global index b * nparts_per_bucket + k.  One start launches one
+ * persistent kernel for all buckets. */
+int pcoll_init_batch(int nbuckets, const size_t *counts, int dtype, int op,
+                     int nparts_per_bucket, int nranks, pcoll_req_t *out);
+
+/* Binds data buffers and the stream kernels are enqueued on.
+ *   rank_bufs  nbuckets * nranks device pointers, bucket-major:
+ *              rank_bufs[b * nranks + r] = contribution of rank r to b.
+ *   outs       nbuckets device pointers (may equal a rank buffer only if
+ *              the caller accepts that rank's input being overwritten
+ *              partition by partition).
+ *   rank_scales / out_scales: PCOLL_FP8_E4M3 only (else NULL): per-256
+ *              binary32 scales, laid out like rank_bufs / outs, with
+ *              ceil(count / 256) entries per bucket.
+ * Not allowed while an epoch is active.  A binding seen before (same
+ * pointers and stream) reuses its cached descriptor table and graph. */
+int pcoll_bind(pcoll_req_t req, const void *const *rank_bufs,
+               void *const *outs, const float *const *rank_scales,
+               float *const *out_scales, void *stream);
+
+/* --------------------------------------------------------------- epochs */
+
+/* Starts an epoch: asynchronously launches the persistent reduce kernel on
+ * the bound stream (or, in graph mode, replays the cached graph; the graph
+ * is captured and instantiated lazily on first use, after Algorithm 1's
+ * LaunchGraph).  PCOLL_ERR_STATE if unbound or an epoch is still active. */
+int pcoll_start(pcoll_req_t req);
+
+/* Marks partition `part` ready (host side, non-blocking, about a store to
+ * pinned memory).  PCOLL_ERR_STATE if no epoch is active or the partition
+ * was already readied this epoch; PCOLL_ERR_ARG if out of range. */
+int pcoll_pready(pcoll_req_t req, int part);
+
+/* Marks partitions first..last (inclusive) ready; all-or-nothing. */
+int pcoll_pready_range(pcoll_req_t req, int first, int last);
+
+/* Marks parts[0..n) ready; all-or-nothing (duplicates are an error). */
+int pcoll_pready_list(pcoll_req_t req, int n, const int *parts);
+
+/* Device-side ready signal: enqueues on `stream` a kernel that marks the
+ * partitions in the device array parts_dev[0..n) ready when it runs, so
+ * readiness can follow producer kernels in stream order (or be captured in
+ * a graph).  `stream` must not be the bound stream (the reduce kernel
+ * occupies it until every partition is ready).  Each partition must be
+ * readied once per epoch; ids out of range are ignored. */
+int pcoll_pready_on_stream(pcoll_req_t req, const int *parts_dev, int n,
+                           void *stream);
+
+/* Non-blocking test of one partition: *flag = 1 once its output is final in
+ * the current (or last completed) epoch.  PCOLL_ERR_STATE before the first
+ * start. */
+int pcoll_parrived(pcoll_req_t req, int part, int *flag);
+
+/* Non-blocking test of the whole epoch: *flag = 1 once every partition has
+ * arrived; completes the epoch like pcoll_wait when it does. */
+int pcoll_test(pcoll_req_t req, int *flag);
+
+/* Blocks until every partition has arrived and the epoch is complete.
+ * Returns PCOLL_ERR_ABORTED if the kernel gave up on its own deadline
+ * (configurable, default 10 s) because some partition was never readied.
+ * A request with no active epoch returns at once. */
+int pcoll_wait(pcoll_req_t req);
+
+/* As pcoll_wait, but gives up after `ms` milliseconds: the kernel is told
+ * to stop waiting for unready partitions, the call returns
+ * PCOLL_ERR_TIMEOUT once it has drained, and the epoch is over (partitions
+ * that had arrived are final; the others are undefined). */
+int pcoll_wait_timeout(pcoll_req_t req, int ms);
+
+/* Makes `stream` wait (on the device) for the end of the current epoch's
+ * kernel; does not block the host and does not complete the epoch (call
+ * pcoll_wait or pcoll_test before the next start). */
+int pcoll_wait_on_stream(pcoll_req_t req, void *stream);
+
+/* Releases the request (after waiting for its last kernel to retire).
+ * PCOLL_ERR_STATE while an epoch is active. */
+int pcoll_free(pcoll_req_t req);
+
+const char *pcoll_strerror(int code);
+
+/* Detail of the last PCOLL_ERR_HIP seen by the calling thread (the failing
+ * HIP call and its error name), or "". */
+const char *pcoll_last_error_detail(void);
+
+/* -------------------------------------------------------- configuration */
+
+typedef struct {
+  int tile_elems;    /* elements per tile (one wavefront's unit of work);
+                        a multiple of 1024 */
+  int groups;        /* workgroups of the persistent kernel (4 wavefronts
+                        each); 0 = groups_per_cu x compute units */
+  int groups_per_cu; /* used when groups = 0 */
+  int comp;          /* float sums: 1 = Sum2 compensated, 0 = plain */
+  int graph;         /* 1 = start replays a cached graph, 0 = direct launch */
+  int timeout_ms;    /* device-side deadline of one epoch */
+  int debug;         /* 1 = count tiles reduced per partition */
+} pcoll_config_t;
+
+/* Reads the request's configuration.  The defaults come from the tuned
+ * table (env PCOLL_TUNE_FILE, else the table shipped next to the library),
+ * then from environment overrides: PCOLL_TILE, PCOLL_GROUPS,
+ * PCOLL_GROUPS_PER_CU, PCOLL_COMP, PCOLL_GRAPH, PCOLL_TIMEOUT_MS,
+ * PCOLL_DEBUG. */
+int pcoll_get_config(pcoll_req_t req, pcoll_config_t *cfg);
+
+/* Replaces the configuration (not while an epoch is active).  Fields out of
+ * range give PCOLL_ERR_ARG and leave the request unchanged. */
+int pcoll_set_config(pcoll_req_t req, const pcoll_config_t *cfg);
+
+/* ----------------------------------------------------------- inspection */
+
+/* Partitions of the request (nbuckets * nparts). */
+int pcoll_num_parts(pcoll_req_t req, int *nparts_total);
+
+/* Bucket, first element and length of a global partition. */
+int pcoll_part_info(pcoll_req_t req, int part, int *bucket, size_t *offset,
+                    size_t *length);
+
+typedef struct {
+  uint64_t epochs;          /* starts */
+  uint64_t graph_launches;  /* starts served by a cached graph */
+  uint64_t graph_captures;  /* graphs captured and instantiated */
+  uint64_t cache_hits;      /* binds served by the binding cache */
+  uint64_t cache_misses;
+  uint64_t cache_evictions;
+  double last_capture_ms;     /* host time of the last capture */
+  double last_instantiate_ms; /* host time of the last instantiation */
+  float last_kernel_ms;       /* device time of the last epoch's kernel,
+                                 if debug timing was on, else -1 */
+  int groups;                 /* workgroups of the last launch */
+  int total_tiles;            /* tiles of one epoch */
+} pcoll_stats_t;
+
+int pcoll_get_stats(pcoll_req_t req, pcoll_stats_t *st);
+
+/* Debug mode only: tiles reduced per partition in the last epoch (must equal
+ * the partition's tile count: every tile exactly once). */
+int pcoll_debug_tile_hits(pcoll_req_t req, uint32_t *hits, int n);
+
+/* Host-only partition plan (no GPU needed): for a message of `count`
+ * elements of `dtype` split into `nparts` partitions, writes the common
+ * partition length to *psize and, if non-NULL, offsets/lengths of each. */
+int pcoll_plan(size_t count, int dtype, int nparts, size_t *psize,
+               size_t *offsets, size_t *lengths);
+
+/* ------------------------------------------------------ producer packing */
+
+/* dst[i] = bf16 of src[i], round to nearest even.  n elements; src, dst
+ * 16-byte aligned device pointers; enqueued on `stream`. */
+int pcoll_pack_bf16(const float *src, uint16_t *dst, size_t n, void *stream);
+
+/* e4m3 codes with one binary32 scale per block of 256 elements (the last
+ * block may be short): s = amax / 448 (1 if that is not a normal number),
+ * dst[i] = e4m3(src[i] * (1 / s)), saturating, round to nearest even. */
+int pcoll_pack_fp8(const float *src, uint8_t *dst, float *scales, size_t n,
+                   void *stream);
+
+/* --------------------------------------------------- measurement probes */
+
+/* Streaming copy of `bytes` (a multiple of 16) with 16-byte loads/stores:
+ * the attainable-bandwidth reference of the device. */
+int pcoll_probe_copy(void *dst, const void *src, size_t bytes, void *stream);
+
+/* Fills `bytes` (a multiple of 16) with a 32-bit pattern. */
+int pcoll_probe_fill(void *dst, size_t bytes, uint32_t value, void *stream);
+
+/* Device facts: compute units, wall-clock rate (kHz), gcn arch name. */
+int pcoll_device_info(int *compute_units, int *wall_clock_khz, char *arch,
+                      int arch_len);
+
+int pcoll_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PCOLL_H */

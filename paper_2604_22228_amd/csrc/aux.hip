@@ -1,0 +1,211 @@
+// Dispatch of the reduce kernel, and the small kernels around it: the
+// device-side ready signal, the producer-side packers (FP32 -> bf16,
+// FP32 -> e4m3 with per-256 scales), and the measurement probes.
+#include <hip/hip_runtime.h>
+
+#include "reduce_impl.hpp"
+
+namespace pcoll {
+
+hipError_t launch_reduce(const ReduceArgs& a, int dtype, int op, bool comp,
+                         int nranks, int groups, hipStream_t s) {
+  if (nranks < 1 || nranks > kMaxRanks || groups < 1)
+    return hipErrorInvalidValue;
+  switch (dtype) {
+    case kF32:
+      return launch_reduce_f32(a, op, comp, nranks, groups, s);
+    case kI32:
+      return launch_reduce_i32(a, op, nranks, groups, s);
+    case kBF16:
+      return launch_reduce_bf16(a, op, comp, nranks, groups, s);
+    case kE4M3:
+      if (op != kSum) return hipErrorInvalidValue;
+      return launch_reduce_e4m3(a, comp, nranks, groups, s);
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+// ------------------------------------------------------------ ready signal
+// Appends parts[0..n) to the device ready list with the running epoch.  One
+// workgroup reserves its slots with a single atomic; each slot is one
+// 64-bit store, so a reader sees either the old or the new entry.
+__global__ __launch_bounds__(256) void pready_kernel(PreadyArgs a) {
+  __shared__ uint32_t base;
+  const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+  const uint32_t first = blockIdx.x * 256u;
+  const uint32_t cnt = a.n - first < 256u ? a.n - first : 256u;
+  const uint32_t epoch = dev::ld_acq(&a.ctr->epoch);
+  if (threadIdx.x == 0)
+    base = __hip_atomic_fetch_add(&a.ctr->dreserve, cnt, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  if (i < a.n) {
+    const uint64_t v = ((uint64_t)epoch << 32) | (uint32_t)a.parts[i];
+    // slots beyond the list (more readies than partitions) are dropped
+    const uint32_t slot = base + threadIdx.x;
+    if (slot < a.capacity)
+      __hip_atomic_store(&a.dlist[slot], v, __ATOMIC_RELEASE,
+                         __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+hipError_t launch_pready(const PreadyArgs& a, hipStream_t s) {
+  if (a.n == 0) return hipSuccess;
+  hipLaunchKernelGGL(pready_kernel, dim3((a.n + 255u) / 256u), dim3(256), 0,
+                     s, a);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ packers
+__global__ __launch_bounds__(256) void pack_bf16_kernel(const float* src,
+                                                        uint16_t* dst,
+                                                        size_t n) {
+  const size_t nv = n / 8;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t v = (size_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv;
+       v += stride) {
+    const uint4 a = dev::ld_stream(reinterpret_cast<const uint4*>(src) + 2 * v);
+    const uint4 b =
+        dev::ld_stream(reinterpret_cast<const uint4*>(src) + 2 * v + 1);
+    uint4 o;
+    o.x = dev::f_to_bf16(__uint_as_float(a.x)) |
+          (dev::f_to_bf16(__uint_as_float(a.y)) << 16);
+    o.y = dev::f_to_bf16(__uint_as_float(a.z)) |
+          (dev::f_to_bf16(__uint_as_float(a.w)) << 16);
+    o.z = dev::f_to_bf16(__uint_as_float(b.x)) |
+          (dev::f_to_bf16(__uint_as_float(b.y)) << 16);
+    o.w = dev::f_to_bf16(__uint_as_float(b.z)) |
+          (dev::f_to_bf16(__uint_as_float(b.w)) << 16);
+    dev::st_stream(reinterpret_cast<uint4*>(dst) + v, o);
+  }
+  if (blockIdx.x == 0 && threadIdx.x < n - nv * 8) {
+    const size_t i = nv * 8 + threadIdx.x;
+    dst[i] = (uint16_t)dev::f_to_bf16(src[i]);
+  }
+}
+
+hipError_t launch_pack_bf16(const float* src, uint16_t* dst, size_t n,
+                            hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  size_t blocks = (n / 8 + 255) / 256;
+  if (blocks < 1) blocks = 1;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(pack_bf16_kernel, dim3((unsigned)blocks), dim3(256), 0,
+                     s, src, dst, n);
+  return hipGetLastError();
+}
+
+// One row of 16 lanes per block of 256 values, 16 values per lane.
+__global__ __launch_bounds__(256) void pack_e4m3_kernel(const float* src,
+                                                        uint8_t* dst,
+                                                        float* scales,
+                                                        size_t n) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const size_t wave = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+  const size_t nwaves = (size_t)gridDim.x * blockDim.x / 64;
+  for (size_t base = wave * 1024; base < n; base += nwaves * 1024) {
+    const size_t el = base + (size_t)lane * 16;
+    const uint32_t have = el < n ? (n - el < 16 ? (uint32_t)(n - el) : 16u) : 0u;
+    float x[16];
+    if (have == 16u) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint4 v = dev::ld_stream(reinterpret_cast<const uint4*>(src + el) + k);
+        x[4 * k + 0] = __uint_as_float(v.x);
+        x[4 * k + 1] = __uint_as_float(v.y);
+        x[4 * k + 2] = __uint_as_float(v.z);
+        x[4 * k + 3] = __uint_as_float(v.w);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) x[j] = (uint32_t)j < have ? src[el + j] : 0.0f;
+    }
+    float amax = 0.0f;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) amax = fmaxf(amax, fabsf(x[j]));
+    amax = fmaxf(amax, __shfl_xor(amax, 8, 16));
+    amax = fmaxf(amax, __shfl_xor(amax, 4, 16));
+    amax = fmaxf(amax, __shfl_xor(amax, 2, 16));
+    amax = fmaxf(amax, __shfl_xor(amax, 1, 16));
+    float so = amax / 448.0f;
+    if (!(so >= 0x1p-126f)) so = 1.0f;
+    const float inv = 1.0f / so;
+    uint32_t w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+      w[j >> 2] |= dev::f_to_e4m3(x[j] * inv) << (8 * (j & 3));
+    if (have == 16u) {
+      dev::st_stream(reinterpret_cast<uint4*>(dst + el),
+                     make_uint4(w[0], w[1], w[2], w[3]));
+    } else if (have) {
+      for (uint32_t j = 0; j < have; ++j)
+        dst[el + j] = (uint8_t)(w[j >> 2] >> (8 * (j & 3)));
+    }
+    if (have && (lane & 15u) == 0u) scales[el / 256] = so;
+  }
+}
+
+hipError_t launch_pack_e4m3(const float* src, uint8_t* dst, float* scales,
+                            size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  size_t blocks = (n + 4095) / 4096;  // 4 waves x 1024 values
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(pack_e4m3_kernel, dim3((unsigned)blocks), dim3(256), 0,
+                     s, src, dst, scales, n);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------- probes
+__global__ __launch_bounds__(256) void copy_kernel(const uint4* src, uint4* dst,
+                                                   size_t nv) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + 3 * stride < nv; i += 4 * stride) {
+    uint4 a = dev::ld_stream(src + i);
+    uint4 b = dev::ld_stream(src + i + stride);
+    uint4 c = dev::ld_stream(src + i + 2 * stride);
+    uint4 d = dev::ld_stream(src + i + 3 * stride);
+    dev::st_stream(dst + i, a);
+    dev::st_stream(dst + i + stride, b);
+    dev::st_stream(dst + i + 2 * stride, c);
+    dev::st_stream(dst + i + 3 * stride, d);
+  }
+  for (; i < nv; i += stride) dev::st_stream(dst + i, dev::ld_stream(src + i));
+}
+
+__global__ __launch_bounds__(256) void fill_kernel(uint4* dst, size_t nv,
+                                                   uint32_t v) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  const uint4 val = make_uint4(v, v, v, v);
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv;
+       i += stride)
+    dev::st_stream(dst + i, val);
+}
+
+static unsigned probe_blocks(size_t nv) {
+  size_t b = (nv + 255) / 256;
+  if (b > 16384) b = 16384;
+  return (unsigned)(b ? b : 1);
+}
+
+hipError_t launch_copy(void* dst, const void* src, size_t bytes,
+                       hipStream_t s) {
+  const size_t nv = bytes / 16;
+  if (nv == 0) return hipSuccess;
+  hipLaunchKernelGGL(copy_kernel, dim3(probe_blocks(nv)), dim3(256), 0, s,
+                     static_cast<const uint4*>(src), static_cast<uint4*>(dst),
+                     nv);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(void* dst, size_t bytes, uint32_t value,
+                       hipStream_t s) {
+  const size_t nv = bytes / 16;
+  if (nv == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_kernel, dim3(probe_blocks(nv)), dim3(256), 0, s,
+                     static_cast<uint4*>(dst), nv, value);
+  return hipGetLastError();
+}
+
+}  // namespace pcoll

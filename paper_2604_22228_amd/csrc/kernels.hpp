@@ -1,0 +1,44 @@
+// Launch entry points of the gfx950 kernels, called by the host runtime.
+#pragma once
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#include "layout.hpp"
+
+namespace pcoll {
+
+// Wavefronts per workgroup of the persistent reduce kernel (256 threads).
+constexpr int kWavesPerGroup = 4;
+
+// Dtype / op codes, equal to the public enums of pcoll.h.
+enum Dtype : int { kI32 = 0, kF32 = 1, kBF16 = 2, kE4M3 = 3 };
+enum Op : int { kSum = 0, kMax = 1 };
+
+// Elements per 16-byte vector and alignment unit of partitions.
+inline int elem_bytes(int dtype) {
+  return dtype == kBF16 ? 2 : (dtype == kE4M3 ? 1 : 4);
+}
+
+// The persistent partitioned-reduce kernel: `groups` workgroups of
+// kWavesPerGroup wavefronts.  Returns hipErrorInvalidValue for an
+// unsupported (dtype, op, comp, nranks) combination.
+hipError_t launch_reduce(const ReduceArgs& a, int dtype, int op, bool comp,
+                         int nranks, int groups, hipStream_t s);
+// Device-side readiness: appends `a.n` partition ids to the device ready
+// list, stamped with the running epoch.
+hipError_t launch_pready(const PreadyArgs& a, hipStream_t s);
+// Producer-side packing: FP32 -> bfloat16 (RNE), FP32 -> e4m3 + per-256
+// FP32 scales.
+hipError_t launch_pack_bf16(const float* src, uint16_t* dst, size_t n,
+                            hipStream_t s);
+hipError_t launch_pack_e4m3(const float* src, uint8_t* dst, float* scales,
+                            size_t n, hipStream_t s);
+// Measurement probes: a dwordx4 streaming copy and a fill.
+hipError_t launch_copy(void* dst, const void* src, size_t bytes,
+                       hipStream_t s);
+hipError_t launch_fill(void* dst, size_t bytes, uint32_t value,
+                       hipStream_t s);
+
+}  // namespace pcoll

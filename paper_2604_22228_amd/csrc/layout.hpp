@@ -1,0 +1,114 @@
+// Memory layout shared by the host runtime (C++17, g++) and the gfx950
+// kernels (HIP).  Plain structs only: no HIP types, no methods.
+//
+// One request reduces `nbuckets` messages ("buckets") of P rank
+// contributions each.  Bucket b is split into nparts partitions by the chunk
+// rule of Algorithm 1 (Section 4.3): equal lengths fixed in advance, running
+// offsets, the last one clipped.  Global partition g = b * nparts + k.  A
+// partition is further cut into tiles of `tile_elems` elements; a tile is the
+// unit one wavefront reduces.  Destination regions of partitions and tiles
+// are disjoint (Section 4.5, Ordering Guarantee), so each is written once.
+#pragma once
+#include <stdint.h>
+
+namespace pcoll {
+
+constexpr int kMaxRanks = 16;
+
+// Per bucket, in device memory; written once at bind time, read-only to the
+// kernels.
+struct BucketDesc {
+  const void* in[kMaxRanks];        // rank contributions (device pointers)
+  const float* in_scale[kMaxRanks]; // e4m3 only: per-256 block scales
+  void* out;                        // reduced message
+  float* out_scale;                 // e4m3 only: per-256 output scales
+  uint64_t count;                   // elements in the bucket
+  uint64_t reserved;
+};
+
+// Per global partition, in device memory; read-only to the kernels.
+struct PartDesc {
+  uint64_t off;     // first element, relative to the bucket start
+  uint64_t len;     // elements (0 for empty partitions)
+  uint32_t bucket;  // owning bucket
+  uint32_t ntiles;  // max(1, ceil(len / tile_elems)); empty parts get one
+  uint64_t reserved;
+};
+
+// One entry of the device work queue: partitions in the order they were
+// found ready, with the running total of their tiles.
+struct QEntry {
+  uint32_t part;
+  uint32_t cum_end;  // tiles of all entries up to and including this one
+};
+
+// Host-coherent pinned memory shared with the host thread.  Followed in the
+// same allocation by hlist[nparts] and arrived[nparts] (uint32 each).
+struct HostShared {
+  uint32_t epoch;       // host: stamp of the running epoch (informational)
+  uint32_t hcount;      // host: entries in hlist this epoch (store-release)
+  uint32_t abort;       // host: == epoch asks the kernel to give up
+  uint32_t done_epoch;  // device: last epoch whose kernel has drained
+  uint32_t status;      // device: 0, or an error code for done_epoch
+  uint32_t reserved[27];
+};
+
+// Device-memory counters of one request; each group on its own 128-B line
+// so that polling one does not contend with atomics on another.
+struct DevCounters {
+  uint32_t claim;                 // next global tile index to hand out
+  uint32_t pad0[31];
+  uint64_t qstate;                // (queue entries << 32) | queued tiles
+  uint32_t pad1[30];
+  uint32_t ilock;                 // ingest lock (0 free, 1 held)
+  uint32_t hconsumed;             // host ready entries already queued
+  uint32_t dconsumed;             // device ready entries already queued
+  uint32_t pad2[29];
+  uint32_t exit_count;            // wavefronts that have left the kernel
+  uint32_t error;                 // first error seen this epoch
+  uint32_t pad3[30];
+  uint32_t dreserve;              // slots reserved in the device ready list
+  uint32_t pad4[31];
+  uint32_t epoch;                 // epoch of the next (or running) launch:
+                                  // 1 at creation, +1 by each launch's last
+                                  // wavefront, so it always equals the
+                                  // host's count of starts while one runs
+  uint32_t pad5[31];
+};
+
+// Error codes a kernel can leave in HostShared::status.
+enum KernelStatus : uint32_t {
+  kStatusOk = 0,
+  kStatusTimeout = 1,  // its own deadline passed before all parts were ready
+  kStatusAborted = 2,  // the host asked it to give up
+};
+
+// Kernel arguments (passed by value).
+struct ReduceArgs {
+  const BucketDesc* buckets;
+  const PartDesc* parts;
+  QEntry* queue;          // [nparts_total]
+  uint32_t* done;         // [nparts_total] finished tiles per partition
+  uint32_t* queued;       // [nparts_total] epoch stamp once queued
+  uint32_t* tile_hits;    // [nparts_total] debug: tiles reduced, or null
+  uint64_t* dlist;        // [nparts_total] device ready list
+  DevCounters* ctr;
+  HostShared* host;       // device-visible address of the host struct
+  const uint32_t* hlist;  // device-visible host ready list
+  uint32_t* arrived;      // device-visible arrived stamps
+  uint32_t nparts_total;
+  uint32_t total_tiles;
+  uint32_t tile_elems;
+  uint32_t total_waves;
+  uint64_t timeout_ticks; // device wall-clock ticks before giving up
+};
+
+struct PreadyArgs {
+  const int32_t* parts;   // device array of partition ids
+  uint32_t n;
+  uint32_t capacity;      // slots in dlist (= partitions of the request)
+  uint64_t* dlist;
+  DevCounters* ctr;
+};
+
+}  // namespace pcoll

@@ -1,0 +1,376 @@
+// Device side of the persistent partitioned reduction (gfx950, wave64).
+//
+// One launch serves one epoch of a request.  Every wavefront is an
+// independent worker; no wavefront ever waits for another one, so the
+// launch needs no co-residency and drains even if it is larger than the
+// machine.  A worker loops:
+//
+//   1. claim the next global tile index t with one atomic add (the claim of
+//      the following tile is issued before the current tile is reduced, so
+//      its latency hides behind the tile);
+//   2. wait until t is covered by the work queue.  While starved, the worker
+//      tries to move newly readied partitions into the queue: it takes a
+//      try-lock, reads the host ready list (host-coherent memory, written by
+//      pready) and the device ready list (written by the pready kernel), and
+//      appends each partition not yet queued this epoch together with the
+//      running total of its tiles.  Partitions are thus reduced in the order
+//      they became ready (the 2-D pipelining of Section 4.3: the message is
+//      cut into chunks that proceed as soon as they can);
+//   3. find the queue entry covering t (64 entries per wave-wide probe),
+//      giving the partition and the tile inside it;
+//   4. reduce the tile (rank order 0..P-1 per element), store the result;
+//   5. publish: fence, then one lane adds 1 to the partition's done
+//      counter; the lane that completes the partition stores the epoch into
+//      its arrived flag in host-coherent memory (completion is signalled
+//      only after every chunk of the partition has landed, Section 4.5).
+//
+// Exit: t >= total tiles.  A worker that starves past the deadline, or sees
+// the host's abort word, records the reason and leaves; the others follow.
+// The last worker out resets the counters for the next epoch and stores the
+// epoch into done_epoch, which the host's wait polls.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "layout.hpp"
+
+namespace pcoll {
+namespace dev {
+
+// ---------------------------------------------------------------- atomics
+__device__ __forceinline__ uint32_t ld_acq_sys(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ uint32_t ld_rlx_sys(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ uint32_t ld_acq(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t ld_rlx(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t ld_acq64(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t ld_rlx64(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_rlx(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_rel(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_rlx64(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_rel64(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_rel_sys(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Pointer into the constant address space: uniform loads through it become
+// scalar loads.  Only for tables no kernel writes during the launch.
+template <class T>
+using const_ptr = __attribute__((address_space(4))) const T*;
+
+// ---------------------------------------------------------- wave helpers
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+__device__ __forceinline__ uint32_t uni(uint32_t v) {
+  return __builtin_amdgcn_readfirstlane(v);
+}
+__device__ __forceinline__ uint64_t uni64(uint64_t v) {
+  uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+  const uint32_t lane = lane_id();
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    uint32_t y = __shfl_up(x, d);
+    if (lane >= (uint32_t)d) x += y;
+  }
+  return x;
+}
+
+// ------------------------------------------------------------- the queue
+
+// Appends the partitions held by the lanes with `valid` set.  Caller holds
+// the ingest lock; qcount / qtiles are wave-uniform and updated in place.
+__device__ __forceinline__ void queue_append(const ReduceArgs& a,
+                                             uint32_t epoch, bool valid,
+                                             uint32_t part, uint32_t& qcount,
+                                             uint32_t& qtiles) {
+  const uint32_t lane = lane_id();
+  valid = valid && part < a.nparts_total;
+  if (valid) {
+    // exactly once per epoch, whatever the number of pready calls
+    uint32_t old = __hip_atomic_exchange(&a.queued[part], epoch,
+                                         __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+    valid = old != epoch;
+  }
+  uint32_t nt = valid ? a.parts[part].ntiles : 0u;
+  uint32_t incl = wave_incl_scan(nt);
+  uint64_t vm = __ballot(valid);
+  uint32_t rank = __popcll(vm & ((1ull << lane) - 1ull));
+  uint32_t slot = qcount + rank;
+  if (valid && slot < a.nparts_total) {
+    uint64_t e = ((uint64_t)(qtiles + incl) << 32) | part;
+    st_rlx64(reinterpret_cast<uint64_t*>(&a.queue[slot]), e);
+  }
+  qcount += (uint32_t)__popcll(vm);
+  qtiles += uni(__shfl(incl, 63));
+}
+
+// Moves newly readied partitions into the queue.  Returns true if it queued
+// any tile.  Wave-wide.  The lock is taken before the host list is read, so
+// at most one wavefront at a time reads host memory over the bus.
+__device__ __forceinline__ bool try_ingest(const ReduceArgs& a, uint32_t epoch) {
+  const uint32_t lane = lane_id();
+  DevCounters* c = a.ctr;
+  uint32_t got = 0;
+  if (lane == 0) {
+    uint32_t expect = 0;
+    got = __hip_atomic_compare_exchange_strong(
+        &c->ilock, &expect, 1u, __ATOMIC_ACQUIRE, __ATOMIC_RELAXED,
+        __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if (!uni(got)) return false;
+
+  uint32_t hcons = uni(ld_rlx(&c->hconsumed));
+  uint32_t dcons = uni(ld_rlx(&c->dconsumed));
+  uint32_t hc = uni(ld_acq_sys(&a.host->hcount));
+  uint32_t dr = uni(ld_acq(&c->dreserve));
+  uint64_t qs = uni64(ld_rlx64(&c->qstate));
+  uint32_t qcount = (uint32_t)(qs >> 32), qtiles = (uint32_t)qs;
+  const uint32_t qtiles0 = qtiles;
+  if (hc > a.nparts_total) hc = a.nparts_total;
+  if (hc <= hcons && dr <= dcons) {
+    if (lane == 0) st_rel(&c->ilock, 0u);
+    return false;
+  }
+
+  // host ready list: hlist[hcons .. hc)
+  for (uint32_t base = hcons; base < hc; base += 64) {
+    uint32_t i = base + lane;
+    bool in = i < hc;
+    uint32_t p = in ? ld_rlx_sys(&a.hlist[i]) : 0u;
+    queue_append(a, epoch, in, p, qcount, qtiles);
+  }
+  hcons = hc > hcons ? hc : hcons;
+
+  // device ready list: entries are (epoch << 32) | part; stop at the first
+  // reserved slot whose writer has not stored it yet
+  uint32_t dend = dr < a.nparts_total ? dr : a.nparts_total;
+  for (uint32_t base = dcons; base < dend; base += 64) {
+    uint32_t i = base + lane;
+    bool in = i < dend;
+    uint64_t v = in ? ld_rlx64(&a.dlist[i]) : 0ull;
+    bool ok = in && (uint32_t)(v >> 32) == epoch;
+    uint64_t pending = __ballot(in && !ok);
+    uint32_t lim = pending ? (uint32_t)(__ffsll((long long)pending) - 1) : 64u;
+    queue_append(a, epoch, ok && lane < lim, (uint32_t)v, qcount, qtiles);
+    uint32_t avail = dend - base < 64u ? dend - base : 64u;
+    dcons = base + (lim < avail ? lim : avail);
+    if (pending) break;
+  }
+
+  st_rlx(&c->hconsumed, hcons);
+  st_rlx(&c->dconsumed, dcons);
+  st_rel64(&c->qstate, ((uint64_t)qcount << 32) | qtiles);
+  if (lane == 0) st_rel(&c->ilock, 0u);
+  return qtiles != qtiles0;
+}
+
+__device__ __forceinline__ void set_error(const ReduceArgs& a, uint32_t code) {
+  if (lane_id() == 0) {
+    uint32_t expect = 0;
+    __hip_atomic_compare_exchange_strong(&a.ctr->error, &expect, code,
+                                         __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// Waits until tile t is queued.  Returns the queue state, or 0 if the
+// worker must give up (deadline, host abort, or another worker's error).
+// Only the few workers at the front of the claim order (t within 8 tiles of
+// the queued total) poll the ready lists and the host's abort word; the rest
+// re-read the device-side queue state at a slower pace.
+__device__ __forceinline__ uint64_t wait_queued(const ReduceArgs& a,
+                                                uint32_t t, uint32_t epoch,
+                                                uint64_t t0) {
+  for (uint32_t spins = 0;; ++spins) {
+    uint64_t qs = uni64(ld_acq64(&a.ctr->qstate));
+    const uint32_t qt = (uint32_t)qs;
+    if (qt > t) return qs;
+    const bool front = t - qt < 8u;
+    if (front && try_ingest(a, epoch)) continue;
+    if (uni(ld_rlx(&a.ctr->error)) != 0u) return 0;
+    if ((spins & 7u) == 7u) {
+      if (front && uni(ld_acq_sys(&a.host->abort)) == epoch) {
+        set_error(a, kStatusAborted);
+        return 0;
+      }
+      if (wall_clock64() - t0 > a.timeout_ticks) {
+        set_error(a, kStatusTimeout);
+        return 0;
+      }
+    }
+    if (front)
+      __builtin_amdgcn_s_sleep(2);
+    else
+      __builtin_amdgcn_s_sleep(32);
+  }
+}
+
+// Finds the queue entry covering tile t among entries [cursor, qcount).
+// cursor / prev_end (cum_end of entry cursor-1) only move forward, since a
+// worker's claims increase.
+__device__ __forceinline__ void locate(const ReduceArgs& a, uint32_t t,
+                                       uint32_t qcount, uint32_t& cursor,
+                                       uint32_t& prev_end, uint32_t& part) {
+  const uint32_t lane = lane_id();
+  for (;;) {
+    uint32_t i = cursor + lane;
+    uint64_t e = i < qcount
+                     ? ld_rlx64(reinterpret_cast<const uint64_t*>(&a.queue[i]))
+                     : ~0ull;
+    uint32_t ce = (uint32_t)(e >> 32);
+    uint64_t m = __ballot(ce > t);
+    if (m) {
+      uint32_t k = (uint32_t)(__ffsll((long long)m) - 1);
+      uint32_t before = uni(__shfl(ce, k == 0 ? 0 : k - 1));
+      if (k != 0) prev_end = before;
+      cursor += k;
+      part = uni(__shfl((uint32_t)e, k));
+      return;
+    }
+    prev_end = uni(__shfl(ce, 63));
+    cursor += 64;
+  }
+}
+
+// Publishes one finished tile of `part`: one release add on the
+// partition's done counter (the release covers this wavefront's stores);
+// the wavefront whose add completes the partition acquires the other
+// wavefronts' tiles and stores the epoch into the host-visible arrived flag.
+__device__ __forceinline__ void finish_tile(const ReduceArgs& a, uint32_t part,
+                                            uint32_t ntiles, uint32_t epoch) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  if (lane_id() == 0) {
+    if (a.tile_hits)
+      __hip_atomic_fetch_add(&a.tile_hits[part], 1u, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t old = __hip_atomic_fetch_add(&a.done[part], 1u, __ATOMIC_RELEASE,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+    if (old + 1u == ntiles) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      st_rlx(&a.done[part], 0u);
+      __threadfence_system();
+      st_rel_sys(&a.arrived[part], epoch);
+    }
+  }
+}
+
+// Leaves the kernel; the last wavefront resets the epoch state.
+__device__ __forceinline__ void leave(const ReduceArgs& a, uint32_t epoch) {
+  const uint32_t lane = lane_id();
+  DevCounters* c = a.ctr;
+  uint32_t last = 0;
+  if (lane == 0)
+    last = __hip_atomic_fetch_add(&c->exit_count, 1u, __ATOMIC_ACQ_REL,
+                                  __HIP_MEMORY_SCOPE_AGENT) +
+               1u ==
+           a.total_waves;
+  if (!uni(last)) return;
+  uint32_t err = uni(ld_acq(&c->error));
+  if (err != 0u) {
+    // an abandoned epoch can leave partial done counts behind
+    for (uint32_t p = lane; p < a.nparts_total; p += 64) st_rlx(&a.done[p], 0u);
+  }
+  if (lane == 0) {
+    st_rlx(&c->claim, 0u);
+    st_rlx64(&c->qstate, 0ull);
+    st_rlx(&c->hconsumed, 0u);
+    st_rlx(&c->dconsumed, 0u);
+    st_rlx(&c->dreserve, 0u);
+    st_rlx(&c->error, 0u);
+    st_rlx(&c->ilock, 0u);
+    st_rlx(&c->exit_count, 0u);
+    st_rlx(&c->epoch, epoch + 1u);
+    __threadfence_system();
+    __hip_atomic_store(&a.host->status, err, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_SYSTEM);
+    st_rel_sys(&a.host->done_epoch, epoch);
+  }
+}
+
+__device__ __forceinline__ uint32_t claim(const ReduceArgs& a) {
+  uint32_t t = 0;
+  if (lane_id() == 0)
+    t = __hip_atomic_fetch_add(&a.ctr->claim, 1u, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+  return t;  // valid in lane 0; broadcast by the caller when needed
+}
+
+// The worker loop.  Tile::run<P>(bucket, first element, length) reduces one
+// tile with the whole wavefront.
+template <class Tile, int P>
+__device__ __forceinline__ void persistent_loop(const ReduceArgs& a) {
+  const uint32_t epoch = uni(ld_acq(&a.ctr->epoch));
+  const uint64_t t0 = wall_clock64();
+  uint32_t cursor = 0, prev_end = 0;
+  uint32_t t = uni(claim(a));
+  while (t < a.total_tiles) {
+    uint64_t qs = wait_queued(a, t, epoch, t0);
+    if (qs == 0) break;
+    uint32_t part;
+    locate(a, t, (uint32_t)(qs >> 32), cursor, prev_end, part);
+    // descriptor tables are read-only for the whole launch: scalar loads
+    const const_ptr<PartDesc> pd = (const_ptr<PartDesc>)(a.parts) + part;
+    const uint64_t poff = pd->off, plen = pd->len;
+    const uint32_t pnt = pd->ntiles;
+    const const_ptr<BucketDesc> bd =
+        (const_ptr<BucketDesc>)(a.buckets) + pd->bucket;
+    const uint32_t lt = t - prev_end;
+    const uint64_t skip = (uint64_t)lt * a.tile_elems;
+    const uint64_t rest = plen > skip ? plen - skip : 0;
+    const uint32_t n = (uint32_t)(rest < a.tile_elems ? rest : a.tile_elems);
+    uint32_t next = claim(a);  // in flight while the tile is reduced
+    Tile::template run<P>(bd, poff + skip, n);
+    finish_tile(a, part, pnt, epoch);
+    t = uni(next);
+  }
+  leave(a, epoch);
+}
+
+// ------------------------------------------------------ memory streaming
+// 16-byte streaming access through the global address space (global_load /
+// global_store with the nontemporal hint, never the generic flat path).
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) const u32x4* gload_ptr;
+typedef __attribute__((address_space(1))) u32x4* gstore_ptr;
+__device__ __forceinline__ uint4 ld_stream(const uint4* p) {
+  const u32x4 v = __builtin_nontemporal_load((gload_ptr)(p));
+  return make_uint4(v[0], v[1], v[2], v[3]);
+}
+__device__ __forceinline__ void st_stream(uint4* p, uint4 v) {
+  const u32x4 w = {v.x, v.y, v.z, v.w};
+  __builtin_nontemporal_store(w, (gstore_ptr)(p));
+}
+
+// Knuth's TwoSum: s = fl(a + b), e = a + b - s exactly.
+__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
+  s = a + b;
+  float bv = s - a;
+  float av = s - bv;
+  e = (a - av) + (b - bv);
+}
+
+}  // namespace dev
+}  // namespace pcoll

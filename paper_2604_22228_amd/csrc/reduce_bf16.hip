@@ -1,0 +1,12 @@
+// bfloat16 payloads, binary32 accumulation: sum (plain or Sum2) and max.
+#include "reduce_impl.hpp"
+
+namespace pcoll {
+hipError_t launch_reduce_bf16(const ReduceArgs& a, int op, bool comp,
+                              int nranks, int groups, hipStream_t s) {
+  using namespace dev;
+  if (op == kMax) return launch_ranks<VecTile<FMax, 2>>(a, nranks, groups, s);
+  if (comp) return launch_ranks<VecTile<FSum<true>, 2>>(a, nranks, groups, s);
+  return launch_ranks<VecTile<FSum<false>, 2>>(a, nranks, groups, s);
+}
+}  // namespace pcoll

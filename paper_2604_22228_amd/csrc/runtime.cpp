@@ -1,0 +1,893 @@
+// Host runtime of libpcoll: requests, epochs, readiness, completion, the
+// binding/graph cache, and the C ABI declared in include/pcoll.h.
+//
+// Host C++17 over the HIP runtime API; kernels are launched through the
+// entry points of kernels.hpp.  Per request:
+//   * host-coherent pinned memory (HostShared + ready list + arrived flags)
+//     is the channel between the host thread and the running kernel:
+//     pready appends to the ready list and publishes its length with a
+//     store-release; the kernel stores arrived[p] = epoch and, at the end,
+//     done_epoch = epoch;
+//   * device memory holds the partition table, the work queue and the
+//     counters the kernel's wavefronts share;
+//   * an LRU cache (Section 4.2's graph cache) maps each binding to its
+//     descriptor table and, in graph mode, to the instantiated graph of the
+//     persistent launch, created lazily on first start (Algorithm 1,
+//     LaunchGraph: look up, create on a miss, launch, record an event).
+#include <dlfcn.h>
+#include <immintrin.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include <hip/hip_runtime_api.h>
+
+#include "kernels.hpp"
+#include "layout.hpp"
+#include "lru_cache.hpp"
+#include "pcoll.h"
+#include "tuning.hpp"
+
+using namespace pcoll;
+
+namespace {
+
+thread_local std::string g_detail;
+
+int hip_fail(hipError_t e, const char* what) {
+  g_detail = std::string(what) + ": " + hipGetErrorName(e) + " (" +
+             hipGetErrorString(e) + ")";
+  return PCOLL_ERR_HIP;
+}
+
+#define HIP_TRY(call)                                    \
+  do {                                                   \
+    hipError_t e_ = (call);                              \
+    if (e_ != hipSuccess) return hip_fail(e_, #call);    \
+  } while (0)
+
+int env_int(const char* name, int dflt) {
+  const char* v = std::getenv(name);
+  if (!v || !*v) return dflt;
+  char* end = nullptr;
+  long x = std::strtol(v, &end, 10);
+  return (end && *end == '\0') ? (int)x : dflt;
+}
+
+std::string lib_dir() {
+  Dl_info info;
+  if (dladdr(reinterpret_cast<void*>(&lib_dir), &info) && info.dli_fname) {
+    std::string p = info.dli_fname;
+    auto s = p.rfind('/');
+    if (s != std::string::npos) return p.substr(0, s);
+  }
+  return ".";
+}
+
+const std::vector<TuneRow>& tune_rows() {
+  static std::once_flag once;
+  static std::vector<TuneRow> rows;
+  std::call_once(once, [] {
+    const char* f = std::getenv("PCOLL_TUNE_FILE");
+    std::string path = f && *f ? std::string(f) : lib_dir() + "/tuned_mi355x.txt";
+    std::ifstream in(path);
+    if (!in) return;
+    std::stringstream ss;
+    ss << in.rdbuf();
+    rows = parse_tune_table(ss.str());
+  });
+  return rows;
+}
+
+bool valid_dtype(int d) { return d >= PCOLL_INT32 && d <= PCOLL_FP8_E4M3; }
+bool valid_op(int o) { return o == PCOLL_SUM || o == PCOLL_MAX; }
+
+// Partition alignment in elements: whole 16-byte vectors, 256 for e4m3.
+uint64_t part_align(int dtype) {
+  return dtype == PCOLL_FP8_E4M3 ? 256u : 16u / (uint64_t)elem_bytes(dtype);
+}
+
+// Algorithm 1's chunk rule with the alignment above.
+uint64_t plan_psize(uint64_t count, uint64_t nparts, uint64_t align) {
+  uint64_t ps = (count + nparts - 1) / nparts;
+  return (ps + align - 1) / align * align;
+}
+
+struct BindKey {
+  std::vector<uintptr_t> v;
+  bool operator==(const BindKey& o) const { return v == o.v; }
+};
+struct BindKeyHash {
+  size_t operator()(const BindKey& k) const {
+    uint64_t h = 1469598103934665603ull;  // FNV-1a over the words
+    for (uintptr_t x : k.v) {
+      h ^= (uint64_t)x;
+      h *= 1099511628211ull;
+    }
+    return (size_t)h;
+  }
+};
+
+struct Binding {
+  BucketDesc* table = nullptr;   // device copy of the bucket descriptors
+  hipGraphExec_t exec = nullptr; // persistent launch, captured lazily
+  uint64_t exec_sig = 0;         // launch signature the graph was made for
+};
+
+}  // namespace
+
+struct pcoll_req_s {
+  int device = 0;
+  int dtype = 0, op = 0, nranks = 0, nparts_per_bucket = 0, nbuckets = 0;
+  std::vector<uint64_t> counts;
+  uint32_t nparts_total = 0;
+  std::vector<PartDesc> parts;
+  pcoll_config_t cfg{};
+  uint32_t total_tiles = 0;
+  int groups = 0;
+  int cus = 0;
+  int clock_khz = 0;
+
+  HostShared* host = nullptr;      // host address of the pinned block
+  HostShared* host_dev = nullptr;  // device address of the same block
+  uint32_t* hlist = nullptr;
+  uint32_t* arrived = nullptr;
+
+  void* arena = nullptr;
+  PartDesc* d_parts = nullptr;
+  QEntry* d_queue = nullptr;
+  uint32_t* d_done = nullptr;
+  uint32_t* d_queued = nullptr;
+  uint32_t* d_hits = nullptr;
+  uint64_t* d_dlist = nullptr;
+  DevCounters* d_ctr = nullptr;
+
+  hipStream_t stream = nullptr;
+  bool bound = false;
+  Binding* cur = nullptr;
+  std::unique_ptr<LruCache<BindKey, Binding, BindKeyHash>> cache;
+  hipStream_t capture_stream = nullptr;
+  hipEvent_t ev_start = nullptr, ev_end = nullptr;
+  bool ev_end_recorded = false;
+  bool ev_start_recorded = false;
+
+  uint32_t epoch = 0;
+  bool active = false;
+  uint32_t hcount = 0;
+  std::vector<uint32_t> stamp;  // epoch in which each partition was readied
+  pcoll_stats_t stats{};
+  uint64_t sig = 0;             // launch signature (config-dependent args)
+};
+
+namespace {
+
+// Waits until the kernel of the last launch has fully retired.
+int drain(pcoll_req_t r) {
+  if (r->ev_end_recorded) HIP_TRY(hipEventSynchronize(r->ev_end));
+  return PCOLL_SUCCESS;
+}
+
+void dispose_binding(Binding& b) {
+  if (b.exec) (void)hipGraphExecDestroy(b.exec);
+  if (b.table) (void)hipFree(b.table);
+  b.exec = nullptr;
+  b.table = nullptr;
+}
+
+uint64_t launch_signature(const pcoll_req_s* r) {
+  uint64_t h = 1469598103934665603ull;
+  const uint64_t v[] = {(uint64_t)r->cfg.tile_elems, (uint64_t)r->groups,
+                        (uint64_t)r->cfg.comp, (uint64_t)r->cfg.debug,
+                        (uint64_t)r->cfg.timeout_ms, r->total_tiles};
+  for (uint64_t x : v) {
+    h ^= x;
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+int validate_config(const pcoll_req_s* r, const pcoll_config_t& c) {
+  if (c.tile_elems < 1024 || c.tile_elems % 1024 != 0 ||
+      c.tile_elems > (1 << 26))
+    return PCOLL_ERR_ARG;
+  if (c.groups < 0 || c.groups > (1 << 20)) return PCOLL_ERR_ARG;
+  if (c.groups == 0 && (c.groups_per_cu < 1 || c.groups_per_cu > 64))
+    return PCOLL_ERR_ARG;
+  if (c.comp != 0 && c.comp != 1) return PCOLL_ERR_ARG;
+  if (c.comp == 1 && (r->dtype == PCOLL_INT32 || r->op == PCOLL_MAX))
+    return PCOLL_ERR_ARG;
+  if (c.graph != 0 && c.graph != 1) return PCOLL_ERR_ARG;
+  if (c.timeout_ms < 1 || c.timeout_ms > 3600 * 1000) return PCOLL_ERR_ARG;
+  if (c.debug != 0 && c.debug != 1) return PCOLL_ERR_ARG;
+  return PCOLL_SUCCESS;
+}
+
+// Recomputes tiles for the configuration and uploads the partition table.
+int apply_config(pcoll_req_t r, const pcoll_config_t& c) {
+  int rc = validate_config(r, c);
+  if (rc) return rc;
+  uint64_t total = 0;
+  std::vector<PartDesc> parts = r->parts;
+  for (auto& p : parts) {
+    uint64_t nt = (p.len + (uint64_t)c.tile_elems - 1) / (uint64_t)c.tile_elems;
+    p.ntiles = (uint32_t)(nt ? nt : 1);
+    total += p.ntiles;
+  }
+  if (total >= (1ull << 31)) return PCOLL_ERR_UNSUPPORTED;
+  int groups = c.groups ? c.groups : c.groups_per_cu * r->cus;
+  if (groups < 1) groups = 1;
+  rc = drain(r);
+  if (rc) return rc;
+  HIP_TRY(hipSetDevice(r->device));
+  HIP_TRY(hipMemcpy(r->d_parts, parts.data(), parts.size() * sizeof(PartDesc),
+                    hipMemcpyHostToDevice));
+  r->parts = std::move(parts);
+  r->cfg = c;
+  r->total_tiles = (uint32_t)total;
+  r->groups = groups;
+  r->sig = launch_signature(r);
+  if (r->cache)  // graphs captured with the old arguments are stale
+    r->cache->for_each([](const BindKey&, Binding& b) {
+      if (b.exec) (void)hipGraphExecDestroy(b.exec);
+      b.exec = nullptr;
+    });
+  return PCOLL_SUCCESS;
+}
+
+pcoll_config_t default_config(const pcoll_req_s* r) {
+  uint64_t bytes = 0;
+  for (uint64_t c : r->counts) bytes += c * (uint64_t)elem_bytes(r->dtype);
+  pcoll_config_t c{};
+  c.graph = env_int("PCOLL_GRAPH", r->nbuckets > 1 ? 1 : 0) ? 1 : 0;
+  TuneChoice t = tune_lookup(tune_rows(), r->dtype, r->op, r->nranks, c.graph,
+                             bytes);
+  c.tile_elems = env_int("PCOLL_TILE", t.tile_elems);
+  c.groups = env_int("PCOLL_GROUPS", 0);
+  c.groups_per_cu = env_int("PCOLL_GROUPS_PER_CU", t.groups_per_cu);
+  const bool float_sum = r->op == PCOLL_SUM && r->dtype != PCOLL_INT32;
+  // compensated accumulation: on for e4m3 and for 16 ranks or more
+  int comp = float_sum && (r->dtype == PCOLL_FP8_E4M3 || r->nranks >= 16);
+  comp = env_int("PCOLL_COMP", comp);
+  c.comp = float_sum && comp ? 1 : 0;
+  c.timeout_ms = env_int("PCOLL_TIMEOUT_MS", 10000);
+  c.debug = env_int("PCOLL_DEBUG", 0) ? 1 : 0;
+  return c;
+}
+
+void destroy(pcoll_req_t r) {
+  if (!r) return;
+  (void)hipSetDevice(r->device);
+  (void)drain(r);
+  r->cache.reset();
+  if (r->capture_stream) (void)hipStreamDestroy(r->capture_stream);
+  if (r->ev_start) (void)hipEventDestroy(r->ev_start);
+  if (r->ev_end) (void)hipEventDestroy(r->ev_end);
+  if (r->arena) (void)hipFree(r->arena);
+  if (r->host) (void)hipHostFree(r->host);
+  delete r;
+}
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+int create(const std::vector<uint64_t>& counts, int dtype, int op,
+           int nparts, int nranks, pcoll_req_t* out) {
+  if (!out) return PCOLL_ERR_ARG;
+  *out = nullptr;
+  if (!valid_dtype(dtype) || !valid_op(op)) return PCOLL_ERR_ARG;
+  if (nparts < 1 || nranks < 1) return PCOLL_ERR_ARG;
+  if (nranks > PCOLL_MAX_RANKS) return PCOLL_ERR_UNSUPPORTED;
+  if (dtype == PCOLL_FP8_E4M3 && op == PCOLL_MAX) return PCOLL_ERR_UNSUPPORTED;
+  const uint64_t np_total = (uint64_t)nparts * counts.size();
+  if (np_total > (1u << 24)) return PCOLL_ERR_UNSUPPORTED;
+  for (uint64_t c : counts)
+    if (c > (1ull << 40)) return PCOLL_ERR_UNSUPPORTED;
+
+  std::unique_ptr<pcoll_req_s, void (*)(pcoll_req_t)> r(new pcoll_req_s,
+                                                        destroy);
+  r->dtype = dtype;
+  r->op = op;
+  r->nranks = nranks;
+  r->nparts_per_bucket = nparts;
+  r->nbuckets = (int)counts.size();
+  r->counts = counts;
+  r->nparts_total = (uint32_t)np_total;
+  const uint64_t align = part_align(dtype);
+  for (size_t b = 0; b < counts.size(); ++b) {
+    const uint64_t ps = plan_psize(counts[b], (uint64_t)nparts, align);
+    for (int k = 0; k < nparts; ++k) {
+      PartDesc p{};
+      const uint64_t off = std::min<uint64_t>((uint64_t)k * ps, counts[b]);
+      p.off = off;
+      p.len = std::min<uint64_t>(ps, counts[b] - off);
+      p.bucket = (uint32_t)b;
+      p.ntiles = 1;
+      r->parts.push_back(p);
+    }
+  }
+  r->stamp.assign(r->nparts_total, 0u);
+
+  HIP_TRY(hipGetDevice(&r->device));
+  HIP_TRY(hipDeviceGetAttribute(&r->cus, hipDeviceAttributeMultiprocessorCount,
+                                r->device));
+  HIP_TRY(hipDeviceGetAttribute(&r->clock_khz, hipDeviceAttributeWallClockRate,
+                                r->device));
+  if (r->clock_khz <= 0) r->clock_khz = 100000;
+
+  // host-coherent block: header, ready list, arrived flags
+  const size_t hbytes = sizeof(HostShared) + 2 * sizeof(uint32_t) * np_total;
+  void* hp = nullptr;
+  hipError_t e = hipHostMalloc(&hp, hbytes,
+                               hipHostMallocCoherent | hipHostMallocMapped);
+  if (e != hipSuccess) return e == hipErrorOutOfMemory ? PCOLL_ERR_NOMEM
+                                                       : hip_fail(e, "hipHostMalloc");
+  std::memset(hp, 0, hbytes);
+  r->host = static_cast<HostShared*>(hp);
+  r->hlist = reinterpret_cast<uint32_t*>(r->host + 1);
+  r->arrived = r->hlist + np_total;
+  void* dp = nullptr;
+  HIP_TRY(hipHostGetDevicePointer(&dp, hp, 0));
+  r->host_dev = static_cast<HostShared*>(dp);
+
+  // device arena
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + bytes, 256);
+    return o;
+  };
+  const size_t o_parts = take(sizeof(PartDesc) * np_total);
+  const size_t o_queue = take(sizeof(QEntry) * np_total);
+  const size_t o_done = take(sizeof(uint32_t) * np_total);
+  const size_t o_queued = take(sizeof(uint32_t) * np_total);
+  const size_t o_hits = take(sizeof(uint32_t) * np_total);
+  const size_t o_dlist = take(sizeof(uint64_t) * np_total);
+  const size_t o_ctr = take(sizeof(DevCounters));
+  e = hipMalloc(&r->arena, off);
+  if (e != hipSuccess) return e == hipErrorOutOfMemory ? PCOLL_ERR_NOMEM
+                                                       : hip_fail(e, "hipMalloc");
+  HIP_TRY(hipMemset(r->arena, 0, off));
+  const uint32_t first_epoch = 1;  // the device-side epoch of the first start
+  HIP_TRY(hipMemcpy(&reinterpret_cast<DevCounters*>(
+                         static_cast<char*>(r->arena) + o_ctr)->epoch,
+                    &first_epoch, sizeof(first_epoch), hipMemcpyHostToDevice));
+  char* base = static_cast<char*>(r->arena);
+  r->d_parts = reinterpret_cast<PartDesc*>(base + o_parts);
+  r->d_queue = reinterpret_cast<QEntry*>(base + o_queue);
+  r->d_done = reinterpret_cast<uint32_t*>(base + o_done);
+  r->d_queued = reinterpret_cast<uint32_t*>(base + o_queued);
+  r->d_hits = reinterpret_cast<uint32_t*>(base + o_hits);
+  r->d_dlist = reinterpret_cast<uint64_t*>(base + o_dlist);
+  r->d_ctr = reinterpret_cast<DevCounters*>(base + o_ctr);
+
+  HIP_TRY(hipStreamCreateWithFlags(&r->capture_stream, hipStreamNonBlocking));
+  HIP_TRY(hipEventCreateWithFlags(&r->ev_end, hipEventDefault));
+  HIP_TRY(hipEventCreateWithFlags(&r->ev_start, hipEventDefault));
+  const int cap = std::max(1, env_int("PCOLL_GRAPH_CACHE", 8));
+  r->cache.reset(new LruCache<BindKey, Binding, BindKeyHash>(
+      (size_t)cap, [](const BindKey&, Binding& b) { dispose_binding(b); }));
+
+  int rc = apply_config(r.get(), default_config(r.get()));
+  if (rc) return rc;
+  r->stats.last_kernel_ms = -1.0f;
+  *out = r.release();
+  return PCOLL_SUCCESS;
+}
+
+ReduceArgs make_args(const pcoll_req_s* r) {
+  ReduceArgs a{};
+  a.buckets = r->cur->table;
+  a.parts = r->d_parts;
+  a.queue = r->d_queue;
+  a.done = r->d_done;
+  a.queued = r->d_queued;
+  a.tile_hits = r->cfg.debug ? r->d_hits : nullptr;
+  a.dlist = r->d_dlist;
+  a.ctr = r->d_ctr;
+  a.host = r->host_dev;
+  a.hlist = reinterpret_cast<const uint32_t*>(r->host_dev + 1);
+  a.arrived = const_cast<uint32_t*>(a.hlist) + r->nparts_total;
+  a.nparts_total = r->nparts_total;
+  a.total_tiles = r->total_tiles;
+  a.tile_elems = (uint32_t)r->cfg.tile_elems;
+  a.total_waves = (uint32_t)r->groups * kWavesPerGroup;
+  a.timeout_ticks = (uint64_t)r->cfg.timeout_ms * (uint64_t)r->clock_khz;
+  return a;
+}
+
+int launch_direct(pcoll_req_t r, hipStream_t s) {
+  const ReduceArgs a = make_args(r);
+  HIP_TRY(launch_reduce(a, r->dtype, r->op, r->cfg.comp != 0, r->nranks,
+                        r->groups, s));
+  return PCOLL_SUCCESS;
+}
+
+double ms_since(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(
+             std::chrono::steady_clock::now() - t0)
+      .count();
+}
+
+// Graph mode: capture the persistent launch once per binding and
+// configuration, instantiate, then replay.
+int launch_graph(pcoll_req_t r) {
+  Binding* b = r->cur;
+  if (!b->exec || b->exec_sig != r->sig) {
+    if (b->exec) {
+      (void)hipGraphExecDestroy(b->exec);
+      b->exec = nullptr;
+    }
+    auto t0 = std::chrono::steady_clock::now();
+    HIP_TRY(hipStreamBeginCapture(r->capture_stream,
+                                  hipStreamCaptureModeThreadLocal));
+    int rc = launch_direct(r, r->capture_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(r->capture_stream, &g);
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    r->stats.last_capture_ms = ms_since(t0);
+    auto t1 = std::chrono::steady_clock::now();
+    e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      b->exec = nullptr;
+      return hip_fail(e, "hipGraphInstantiate");
+    }
+    r->stats.last_instantiate_ms = ms_since(t1);
+    b->exec_sig = r->sig;
+    r->stats.graph_captures++;
+  }
+  HIP_TRY(hipGraphLaunch(b->exec, r->stream));
+  r->stats.graph_launches++;
+  return PCOLL_SUCCESS;
+}
+
+// Completes the epoch once done_epoch == epoch.
+int finish_epoch(pcoll_req_t r) {
+  r->active = false;
+  const uint32_t st = __atomic_load_n(&r->host->status, __ATOMIC_ACQUIRE);
+  if (r->cfg.debug && r->ev_start_recorded) {
+    float ms = -1.0f;
+    if (hipEventSynchronize(r->ev_end) == hipSuccess &&
+        hipEventElapsedTime(&ms, r->ev_start, r->ev_end) == hipSuccess)
+      r->stats.last_kernel_ms = ms;
+  }
+  if (st == kStatusTimeout) return PCOLL_ERR_ABORTED;
+  if (st == kStatusAborted) return PCOLL_ERR_TIMEOUT;
+  return PCOLL_SUCCESS;
+}
+
+bool epoch_done(const pcoll_req_s* r) {
+  return __atomic_load_n(&r->host->done_epoch, __ATOMIC_ACQUIRE) == r->epoch;
+}
+
+// Spins until the epoch drains.  With limit_ms >= 0, asks the kernel to
+// stop waiting after that long.  A kernel that never reports (it cannot
+// without a fault: it has its own deadline) is detected through its event.
+int spin_wait(pcoll_req_t r, int limit_ms) {
+  auto t0 = std::chrono::steady_clock::now();
+  bool aborted = false;
+  for (uint64_t it = 0; !epoch_done(r); ++it) {
+    _mm_pause();
+    if ((it & 1023) != 1023) continue;
+    const double el = ms_since(t0);
+    if (!aborted && limit_ms >= 0 && el >= limit_ms) {
+      __atomic_store_n(&r->host->abort, r->epoch, __ATOMIC_RELEASE);
+      aborted = true;
+    }
+    hipError_t q = hipEventQuery(r->ev_end);
+    if (q == hipSuccess) {
+      if (epoch_done(r)) break;
+      r->active = false;
+      g_detail = "kernel retired without reporting completion";
+      return PCOLL_ERR_HIP;
+    }
+    if (q != hipErrorNotReady) {
+      r->active = false;
+      return hip_fail(q, "hipEventQuery");
+    }
+  }
+  return finish_epoch(r);
+}
+
+int check_req(pcoll_req_t r) { return r ? PCOLL_SUCCESS : PCOLL_ERR_ARG; }
+
+}  // namespace
+
+// ===================================================================== ABI
+extern "C" {
+
+int pcoll_version(void) { return PCOLL_VERSION; }
+
+const char* pcoll_strerror(int code) {
+  switch (code) {
+    case PCOLL_SUCCESS: return "success";
+    case PCOLL_ERR_ARG: return "invalid argument";
+    case PCOLL_ERR_STATE: return "call not valid in the request's state";
+    case PCOLL_ERR_UNSUPPORTED: return "unsupported dtype/op/rank count";
+    case PCOLL_ERR_HIP: return g_detail.empty() ? "HIP runtime error" : g_detail.c_str();
+    case PCOLL_ERR_TIMEOUT: return "timed out before every partition arrived";
+    case PCOLL_ERR_NOMEM: return "out of memory";
+    case PCOLL_ERR_ABORTED: return "kernel deadline passed with partitions not ready";
+    default: return "unknown error";
+  }
+}
+
+int pcoll_plan(size_t count, int dtype, int nparts, size_t* psize,
+               size_t* offsets, size_t* lengths) {
+  if (!valid_dtype(dtype) || nparts < 1 || !psize) return PCOLL_ERR_ARG;
+  const uint64_t ps = plan_psize(count, (uint64_t)nparts, part_align(dtype));
+  *psize = (size_t)ps;
+  for (int k = 0; k < nparts; ++k) {
+    const uint64_t off = std::min<uint64_t>((uint64_t)k * ps, count);
+    if (offsets) offsets[k] = (size_t)off;
+    if (lengths) lengths[k] = (size_t)std::min<uint64_t>(ps, count - off);
+  }
+  return PCOLL_SUCCESS;
+}
+
+int pcoll_init(size_t count, int dtype, int op, int nparts, int nranks,
+               pcoll_req_t* out) {
+  try {
+    return create({(uint64_t)count}, dtype, op, nparts, nranks, out);
+  } catch (const std::bad_alloc&) {
+    return PCOLL_ERR_NOMEM;
+  } catch (...) {
+    return PCOLL_ERR_HIP;
+  }
+}
+
+int pcoll_init_batch(int nbuckets, const size_t* counts, int dtype, int op,
+                     int nparts_per_bucket, int nranks, pcoll_req_t* out) {
+  if (nbuckets < 1 || !counts) return PCOLL_ERR_ARG;
+  try {
+    std::vector<uint64_t> c(counts, counts + nbuckets);
+    return create(c, dtype, op, nparts_per_bucket, nranks, out);
+  } catch (const std::bad_alloc&) {
+    return PCOLL_ERR_NOMEM;
+  } catch (...) {
+    return PCOLL_ERR_HIP;
+  }
+}
+
+int pcoll_bind(pcoll_req_t r, const void* const* rank_bufs, void* const* outs,
+               const float* const* rank_scales, float* const* out_scales,
+               void* stream) {
+  if (check_req(r)) return PCOLL_ERR_ARG;
+  if (!rank_bufs || !outs) return PCOLL_ERR_ARG;
+  const bool fp8 = r->dtype == PCOLL_FP8_E4M3;
+  if (fp8 != (rank_scales != nullptr) || fp8 != (out_scales != nullptr))
+    return PCOLL_ERR_ARG;
+  const int nb = r->nbuckets, P = r->nranks;
+  // null is allowed only for empty buckets (never dereferenced)
+  auto bad = [&](const void* p, int b, uintptr_t align) {
+    return p ? ((uintptr_t)p & (align - 1)) != 0 : r->counts[(size_t)b] != 0;
+  };
+  for (int i = 0; i < nb * P; ++i)
+    if (bad(rank_bufs[i], i / P, 16)) return PCOLL_ERR_ARG;
+  for (int b = 0; b < nb; ++b)
+    if (bad(outs[b], b, 16)) return PCOLL_ERR_ARG;
+  if (fp8) {
+    for (int i = 0; i < nb * P; ++i)
+      if (bad(rank_scales[i], i / P, 4)) return PCOLL_ERR_ARG;
+    for (int b = 0; b < nb; ++b)
+      if (bad(out_scales[b], b, 4)) return PCOLL_ERR_ARG;
+  }
+  if (r->active) return PCOLL_ERR_STATE;
+  try {
+    BindKey key;
+    key.v.reserve((size_t)nb * (2 * P + 2) + 1);
+    for (int i = 0; i < nb * P; ++i) key.v.push_back((uintptr_t)rank_bufs[i]);
+    for (int b = 0; b < nb; ++b) key.v.push_back((uintptr_t)outs[b]);
+    if (fp8) {
+      for (int i = 0; i < nb * P; ++i) key.v.push_back((uintptr_t)rank_scales[i]);
+      for (int b = 0; b < nb; ++b) key.v.push_back((uintptr_t)out_scales[b]);
+    }
+    key.v.push_back((uintptr_t)stream);
+    HIP_TRY(hipSetDevice(r->device));
+    Binding* hit = r->cache->get(key);
+    if (hit) {
+      r->stats.cache_hits++;
+    } else {
+      r->stats.cache_misses++;
+      std::vector<BucketDesc> tab((size_t)nb);
+      for (int b = 0; b < nb; ++b) {
+        BucketDesc& d = tab[(size_t)b];
+        std::memset(&d, 0, sizeof(d));
+        for (int q = 0; q < P; ++q) {
+          d.in[q] = rank_bufs[b * P + q];
+          d.in_scale[q] = fp8 ? rank_scales[b * P + q] : nullptr;
+        }
+        d.out = outs[b];
+        d.out_scale = fp8 ? out_scales[b] : nullptr;
+        d.count = r->counts[(size_t)b];
+      }
+      Binding nb_{};
+      HIP_TRY(hipMalloc(&nb_.table, sizeof(BucketDesc) * tab.size()));
+      hipError_t e = hipMemcpy(nb_.table, tab.data(),
+                               sizeof(BucketDesc) * tab.size(),
+                               hipMemcpyHostToDevice);
+      if (e != hipSuccess) {
+        (void)hipFree(nb_.table);
+        return hip_fail(e, "hipMemcpy(bucket table)");
+      }
+      // an eviction may free a table or graph the last kernel used
+      int rc = drain(r);
+      if (rc) {
+        (void)hipFree(nb_.table);
+        return rc;
+      }
+      const size_t ev0 = r->cache->evictions();
+      hit = &r->cache->put(key, nb_);
+      r->stats.cache_evictions += r->cache->evictions() - ev0;
+    }
+    r->cur = hit;
+    r->stream = static_cast<hipStream_t>(stream);
+    r->bound = true;
+    return PCOLL_SUCCESS;
+  } catch (const std::bad_alloc&) {
+    return PCOLL_ERR_NOMEM;
+  }
+}
+
+int pcoll_start(pcoll_req_t r) {
+  if (check_req(r)) return PCOLL_ERR_ARG;
+  if (!r->bound || r->active) return PCOLL_ERR_STATE;
+  HIP_TRY(hipSetDevice(r->device));
+  const uint32_t e = r->epoch + 1;
+  // no kernel of this request runs now: the host owns the shared words
+  r->host->hcount = 0;
+  r->host->abort = 0;
+  r->host->status = 0;
+  __atomic_store_n(&r->host->epoch, e, __ATOMIC_RELEASE);
+  r->hcount = 0;
+  if (r->cfg.debug) {
+    HIP_TRY(hipMemsetAsync(r->d_hits, 0, sizeof(uint32_t) * r->nparts_total,
+                           r->stream));
+    HIP_TRY(hipEventRecord(r->ev_start, r->stream));
+    r->ev_start_recorded = true;
+  }
+  int rc = r->cfg.graph ? launch_graph(r) : launch_direct(r, r->stream);
+  if (rc) return rc;
+  HIP_TRY(hipEventRecord(r->ev_end, r->stream));
+  r->ev_end_recorded = true;
+  r->epoch = e;
+  r->active = true;
+  r->stats.epochs++;
+  r->stats.groups = r->groups;
+  r->stats.total_tiles = (int)r->total_tiles;
+  return PCOLL_SUCCESS;
+}
+
+static int publish_ready(pcoll_req_t r, const int* parts, int n, int first) {
+  // validate everything first: all-or-nothing
+  for (int i = 0; i < n; ++i) {
+    const int p = parts ? parts[i] : first + i;
+    if (p < 0 || (uint32_t)p >= r->nparts_total) return PCOLL_ERR_ARG;
+    if (r->stamp[(size_t)p] == r->epoch) return PCOLL_ERR_STATE;
+  }
+  if (parts && n > 1) {  // duplicates within one list
+    std::vector<int> sorted(parts, parts + n);
+    std::sort(sorted.begin(), sorted.end());
+    if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+      return PCOLL_ERR_ARG;
+  }
+  for (int i = 0; i < n; ++i) {
+    const int p = parts ? parts[i] : first + i;
+    r->stamp[(size_t)p] = r->epoch;
+    r->hlist[r->hcount++] = (uint32_t)p;
+  }
+  // the kernel reads the list up to the published length
+  __atomic_store_n(&r->host->hcount, r->hcount, __ATOMIC_RELEASE);
+  return PCOLL_SUCCESS;
+}
+
+int pcoll_pready(pcoll_req_t r, int part) {
+  if (check_req(r)) return PCOLL_ERR_ARG;
+  if (!r->active) return PCOLL_ERR_STATE;
+  return publish_ready(r, &part, 1, 0);
+}
+
+int pcoll_pready_range(pcoll_req_t r, int first, int last) {
+  if (check_req(r)) return PCOLL_ERR_ARG;
+  if (!r->active) return PCOLL_ERR_STATE;
+  if (last < first) return PCOLL_ERR_ARG;
+  return publish_ready(r, nullptr, last - first + 1, first);
+}
+
+int pcoll_pready_list(pcoll_req_t r, int n, const int* parts) {
+  if (check_req(r)) return PCOLL_ERR_ARG;
+  if (n < 0 || (n > 0 && !parts)) return PCOLL_ERR_ARG;
+  if (!r->active) return PCOLL_ERR_STATE;
+  try {
+    return publish_ready(r, parts, n, 0);
+  } catch (const std::bad_alloc&) {
+    return PCOLL_ERR_NOMEM;
+  }
+}
+
+int pcoll_pready_on_stream(pcoll_req_t r, const int* parts_dev, int n,
+                           void* stream) {
+  if (check_req(r)) return PCOLL_ERR_ARG;
+  if (n < 0 || (n > 0 && !parts_dev)) return PCOLL_ERR_ARG;
+  if (!r->active) return PCOLL_ERR_STATE;
+  if (static_cast<hipStream_t>(stream) == r->stream) return PCOLL_ERR_ARG;
+  HIP_TRY(hipSetDevice(r->device));
+  PreadyArgs a{};
+  a.parts = parts_dev;
+  a.n = (uint32_t)n;
+  a.capacity = r->nparts_total;
+  a.dlist = r->d_dlist;
+  a.ctr = r->d_ctr;
+  HIP_TRY(launch_pready(a, static_cast<hipStream_t>(stream)));
+  return PCOLL_SUCCESS;
+}
+
+int pcoll_parrived(pcoll_req_t r, int part, int* flag) {
+  if (check_req(r) || !flag) return PCOLL_ERR_ARG;
+  if (part < 0 || (uint32_t)part >= r->nparts_total) return PCOLL_ERR_ARG;
+  if (r->epoch == 0) return PCOLL_ERR_STATE;
+  *flag = __atomic_load_n(&r->arrived[part], __ATOMIC_ACQUIRE) == r->epoch;
+  return PCOLL_SUCCESS;
+}
+
+int pcoll_test(pcoll_req_t r, int* flag) {
+  if (check_req(r) || !flag) return PCOLL_ERR_ARG;
+  if (!r->active) {
+    *flag = 1;
+    return PCOLL_SUCCESS;
+  }
+  if (!epoch_done(r)) {
+    hipError_t q = hipEventQuery(r->ev_end);
+    if (q != hipSuccess && q != hipErrorNotReady) {
+      r->active = false;
+      return hip_fail(q, "hipEventQuery");
+    }
+    *flag = 0;
+    return PCOLL_SUCCESS;
+  }
+  *flag = 1;
+  return finish_epoch(r);
+}
+
+int pcoll_wait(pcoll_req_t r) {
+  if (check_req(r)) return PCOLL_ERR_ARG;
+  if (!r->active) return PCOLL_SUCCESS;
+  return spin_wait(r, -1);
+}
+
+int pcoll_wait_timeout(pcoll_req_t r, int ms) {
+  if (check_req(r) || ms < 0) return PCOLL_ERR_ARG;
+  if (!r->active) return PCOLL_SUCCESS;
+  return spin_wait(r, ms);
+}
+
+int pcoll_wait_on_stream(pcoll_req_t r, void* stream) {
+  if (check_req(r)) return PCOLL_ERR_ARG;
+  if (!r->active) return PCOLL_ERR_STATE;
+  HIP_TRY(hipStreamWaitEvent(static_cast<hipStream_t>(stream), r->ev_end, 0));
+  return PCOLL_SUCCESS;
+}
+
+int pcoll_free(pcoll_req_t r) {
+  if (check_req(r)) return PCOLL_ERR_ARG;
+  if (r->active) return PCOLL_ERR_STATE;
+  destroy(r);
+  return PCOLL_SUCCESS;
+}
+
+int pcoll_get_config(pcoll_req_t r, pcoll_config_t* cfg) {
+  if (check_req(r) || !cfg) return PCOLL_ERR_ARG;
+  *cfg = r->cfg;
+  return PCOLL_SUCCESS;
+}
+
+int pcoll_set_config(pcoll_req_t r, const pcoll_config_t* cfg) {
+  if (check_req(r) || !cfg) return PCOLL_ERR_ARG;
+  if (r->active) return PCOLL_ERR_STATE;
+  try {
+    return apply_config(r, *cfg);
+  } catch (const std::bad_alloc&) {
+    return PCOLL_ERR_NOMEM;
+  }
+}
+
+int pcoll_num_parts(pcoll_req_t r, int* n) {
+  if (check_req(r) || !n) return PCOLL_ERR_ARG;
+  *n = (int)r->nparts_total;
+  return PCOLL_SUCCESS;
+}
+
+int pcoll_part_info(pcoll_req_t r, int part, int* bucket, size_t* offset,
+                    size_t* length) {
+  if (check_req(r)) return PCOLL_ERR_ARG;
+  if (part < 0 || (uint32_t)part >= r->nparts_total) return PCOLL_ERR_ARG;
+  const PartDesc& p = r->parts[(size_t)part];
+  if (bucket) *bucket = (int)p.bucket;
+  if (offset) *offset = (size_t)p.off;
+  if (length) *length = (size_t)p.len;
+  return PCOLL_SUCCESS;
+}
+
+int pcoll_get_stats(pcoll_req_t r, pcoll_stats_t* st) {
+  if (check_req(r) || !st) return PCOLL_ERR_ARG;
+  *st = r->stats;
+  return PCOLL_SUCCESS;
+}
+
+int pcoll_debug_tile_hits(pcoll_req_t r, uint32_t* hits, int n) {
+  if (check_req(r) || !hits || n < (int)r->nparts_total) return PCOLL_ERR_ARG;
+  if (!r->cfg.debug || r->active) return PCOLL_ERR_STATE;
+  HIP_TRY(hipSetDevice(r->device));
+  int rc = drain(r);
+  if (rc) return rc;
+  HIP_TRY(hipMemcpy(hits, r->d_hits, sizeof(uint32_t) * r->nparts_total,
+                    hipMemcpyDeviceToHost));
+  return PCOLL_SUCCESS;
+}
+
+int pcoll_pack_bf16(const float* src, uint16_t* dst, size_t n, void* stream) {
+  if (n && (!src || !dst || ((uintptr_t)src & 15u) || ((uintptr_t)dst & 15u)))
+    return PCOLL_ERR_ARG;
+  HIP_TRY(launch_pack_bf16(src, dst, n, static_cast<hipStream_t>(stream)));
+  return PCOLL_SUCCESS;
+}
+
+int pcoll_pack_fp8(const float* src, uint8_t* dst, float* scales, size_t n,
+                   void* stream) {
+  if (n && (!src || !dst || !scales || ((uintptr_t)src & 15u) ||
+            ((uintptr_t)dst & 15u) || ((uintptr_t)scales & 3u)))
+    return PCOLL_ERR_ARG;
+  HIP_TRY(launch_pack_e4m3(src, dst, scales, n,
+                           static_cast<hipStream_t>(stream)));
+  return PCOLL_SUCCESS;
+}
+
+int pcoll_probe_copy(void* dst, const void* src, size_t bytes, void* stream) {
+  if (bytes % 16 || (bytes && (!src || !dst || ((uintptr_t)src & 15u) ||
+                               ((uintptr_t)dst & 15u))))
+    return PCOLL_ERR_ARG;
+  HIP_TRY(launch_copy(dst, src, bytes, static_cast<hipStream_t>(stream)));
+  return PCOLL_SUCCESS;
+}
+
+int pcoll_probe_fill(void* dst, size_t bytes, uint32_t value, void* stream) {
+  if (bytes % 16 || (bytes && (!dst || ((uintptr_t)dst & 15u))))
+    return PCOLL_ERR_ARG;
+  HIP_TRY(launch_fill(dst, bytes, value, static_cast<hipStream_t>(stream)));
+  return PCOLL_SUCCESS;
+}
+
+int pcoll_device_info(int* cus, int* wall_clock_khz, char* arch,
+                      int arch_len) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (cus)
+    HIP_TRY(hipDeviceGetAttribute(cus, hipDeviceAttributeMultiprocessorCount,
+                                  dev));
+  if (wall_clock_khz)
+    HIP_TRY(hipDeviceGetAttribute(wall_clock_khz,
+                                  hipDeviceAttributeWallClockRate, dev));
+  if (arch && arch_len > 0) {
+    hipDeviceProp_t p;
+    HIP_TRY(hipGetDeviceProperties(&p, dev));
+    std::snprintf(arch, (size_t)arch_len, "%s", p.gcnArchName);
+  }
+  return PCOLL_SUCCESS;
+}
+
+const char* pcoll_last_error_detail(void) { return g_detail.c_str(); }
+
+}  // extern "C"

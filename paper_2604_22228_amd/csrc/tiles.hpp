@@ -1,0 +1,345 @@
+// Tile reducers: one wavefront reduces `n` consecutive elements of one
+// bucket, starting at element `e0`, over the P rank contributions, in rank
+// order 0..P-1 per element (the operation is elementwise, so any split into
+// tiles gives the same result, which is why partitions may be reduced in
+// any arrival order).
+//
+// Layout: every rank buffer and output is 16-byte aligned and every tile
+// starts on a 16-byte boundary (partition lengths are planned in multiples of
+// 16 bytes; 256 elements for e4m3).  Each lane streams 16-byte vectors
+// (dwordx4), 64 lanes cover 1 KiB per rank per step, and U steps are issued
+// back to back so that U * P loads are in flight per lane before the first
+// add.  Loads and stores carry the nontemporal hint: the data are touched
+// once.  The ragged end (< 16 bytes) of a bucket is done element by element.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "layout.hpp"
+#include "persistent.hpp"
+
+namespace pcoll {
+namespace dev {
+
+// ------------------------------------------------------------ accumulators
+template <bool COMP>
+struct FSum {
+  float s, c;
+  __device__ __forceinline__ void init(float v) { s = v; c = 0.0f; }
+  __device__ __forceinline__ void add(float v) {
+    if (COMP) {  // Sum2 (Ogita, Rump, Oishi 2005): carry the exact errors
+      float e;
+      two_sum(s, v, s, e);
+      c = c + e;
+    } else {
+      s = s + v;
+    }
+  }
+  __device__ __forceinline__ float get() const { return COMP ? s + c : s; }
+};
+
+struct FMax {
+  float m;
+  __device__ __forceinline__ void init(float v) { m = v; }
+  __device__ __forceinline__ void add(float v) { m = v > m ? v : m; }
+  __device__ __forceinline__ float get() const { return m; }
+};
+
+struct ISum {
+  uint32_t s;  // two's-complement wrap
+  __device__ __forceinline__ void init(uint32_t v) { s = v; }
+  __device__ __forceinline__ void add(uint32_t v) { s = s + v; }
+  __device__ __forceinline__ uint32_t get() const { return s; }
+};
+
+struct IMax {
+  int32_t m;
+  __device__ __forceinline__ void init(uint32_t v) { m = (int32_t)v; }
+  __device__ __forceinline__ void add(uint32_t v) {
+    m = (int32_t)v > m ? (int32_t)v : m;
+  }
+  __device__ __forceinline__ uint32_t get() const { return (uint32_t)m; }
+};
+
+// ------------------------------------------------------------------ codecs
+// 32-bit words: the value is the word (float bits or int32).
+struct Word32 {
+  static constexpr int kPerVec = 4;
+  static constexpr int kBytes = 4;
+  using Val = uint32_t;
+  __device__ __forceinline__ static uint32_t get(const uint4& v, int j) {
+    return j == 0 ? v.x : (j == 1 ? v.y : (j == 2 ? v.z : v.w));
+  }
+};
+
+__device__ __forceinline__ float as_f(uint32_t u) { return __uint_as_float(u); }
+
+// bfloat16 -> float is exact (the upper half of a binary32).
+__device__ __forceinline__ float bf16_to_f(uint32_t h) {
+  return __uint_as_float(h << 16);
+}
+// float -> bfloat16, round to nearest even (ties to the even code); NaN
+// stays NaN (quiet bit set); overflow rounds to infinity.
+__device__ __forceinline__ uint32_t f_to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+
+// e4m3 (OCP E4M3FN) encode of a binary32 value, round to nearest even,
+// saturating at +-448.
+__device__ __forceinline__ uint32_t f_to_e4m3(float v) {
+  v = fminf(fmaxf(v, -448.0f), 448.0f);
+  const uint32_t sign = (__float_as_uint(v) >> 24) & 0x80u;
+  const float a = fabsf(v);
+  uint32_t code;
+  if (a < 0x1p-6f) {
+    // subnormal range: multiples of 2^-9 (a * 512 is exact), RNE to integer
+    code = (uint32_t)__builtin_rintf(a * 512.0f);
+  } else {
+    // keep 3 fraction bits, RNE on the binary32 encoding, rebias 127 -> 7
+    const uint32_t ua = __float_as_uint(a);
+    const uint32_t r = ua + 0x7ffffu + ((ua >> 20) & 1u);
+    code = (r >> 20) - (120u << 3);
+  }
+  return code | sign;
+}
+
+// ---------------------------------------------------- 16-byte vector tiles
+// Reduces one 16-byte vector per rank into one 16-byte output vector.
+template <class Acc, int P, int Kind>
+struct VecCombine;
+
+// Kind 0: 32-bit float lanes; Kind 1: 32-bit int lanes; Kind 2: bf16 lanes.
+template <class Acc, int P>
+struct VecCombine<Acc, P, 0> {
+  __device__ __forceinline__ static uint4 run(const uint4 (&x)[P]) {
+    uint32_t o[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      Acc a;
+      a.init(as_f(Word32::get(x[0], j)));
+#pragma unroll
+      for (int r = 1; r < P; ++r) a.add(as_f(Word32::get(x[r], j)));
+      o[j] = __float_as_uint(a.get());
+    }
+    return make_uint4(o[0], o[1], o[2], o[3]);
+  }
+};
+
+template <class Acc, int P>
+struct VecCombine<Acc, P, 1> {
+  __device__ __forceinline__ static uint4 run(const uint4 (&x)[P]) {
+    uint32_t o[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      Acc a;
+      a.init(Word32::get(x[0], j));
+#pragma unroll
+      for (int r = 1; r < P; ++r) a.add(Word32::get(x[r], j));
+      o[j] = a.get();
+    }
+    return make_uint4(o[0], o[1], o[2], o[3]);
+  }
+};
+
+template <class Acc, int P>
+struct VecCombine<Acc, P, 2> {
+  __device__ __forceinline__ static uint4 run(const uint4 (&x)[P]) {
+    uint32_t o[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      Acc lo, hi;
+      uint32_t w = Word32::get(x[0], j);
+      lo.init(bf16_to_f(w & 0xffffu));
+      hi.init(bf16_to_f(w >> 16));
+#pragma unroll
+      for (int r = 1; r < P; ++r) {
+        w = Word32::get(x[r], j);
+        lo.add(bf16_to_f(w & 0xffffu));
+        hi.add(bf16_to_f(w >> 16));
+      }
+      o[j] = f_to_bf16(lo.get()) | (f_to_bf16(hi.get()) << 16);
+    }
+    return make_uint4(o[0], o[1], o[2], o[3]);
+  }
+};
+
+// Scalar path for the last (< 16 bytes) elements of a bucket.
+template <class Acc, int P, int Kind>
+__device__ __forceinline__ void combine_scalar(const char* const (&in)[P],
+                                               char* out, uint32_t i) {
+  if (Kind == 2) {
+    Acc a;
+    a.init(bf16_to_f(reinterpret_cast<const uint16_t*>(in[0])[i]));
+#pragma unroll
+    for (int r = 1; r < P; ++r)
+      a.add(bf16_to_f(reinterpret_cast<const uint16_t*>(in[r])[i]));
+    reinterpret_cast<uint16_t*>(out)[i] = (uint16_t)f_to_bf16(a.get());
+  } else if (Kind == 0) {
+    Acc a;
+    a.init(as_f(reinterpret_cast<const uint32_t*>(in[0])[i]));
+#pragma unroll
+    for (int r = 1; r < P; ++r)
+      a.add(as_f(reinterpret_cast<const uint32_t*>(in[r])[i]));
+    reinterpret_cast<uint32_t*>(out)[i] = __float_as_uint(a.get());
+  } else {
+    Acc a;
+    a.init(reinterpret_cast<const uint32_t*>(in[0])[i]);
+#pragma unroll
+    for (int r = 1; r < P; ++r)
+      a.add(reinterpret_cast<const uint32_t*>(in[r])[i]);
+    reinterpret_cast<uint32_t*>(out)[i] = a.get();
+  }
+}
+
+// Unroll depth: enough loads in flight, bounded register use.
+template <int P>
+struct Unroll {
+  static constexpr int value = P <= 2 ? 4 : (P <= 8 ? 2 : 1);
+};
+
+template <class Acc, int Kind>
+struct VecTile {
+  static constexpr int kElemBytes = Kind == 2 ? 2 : 4;
+  static constexpr int kPerVec = 16 / kElemBytes;
+
+  template <int P>
+  __device__ __forceinline__ static void run(const_ptr<BucketDesc> bd, uint64_t e0,
+                                             uint32_t n) {
+    const uint32_t lane = lane_id();
+    const char* in[P];
+#pragma unroll
+    for (int r = 0; r < P; ++r)
+      in[r] = static_cast<const char*>(bd->in[r]) + e0 * kElemBytes;
+    char* out = static_cast<char*>(bd->out) + e0 * kElemBytes;
+    const uint32_t nv = n / kPerVec;
+    constexpr int U = Unroll<P>::value;
+    uint32_t v = lane;
+    for (; v + 64u * (U - 1) < nv; v += 64u * U) {
+      uint4 x[U][P];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int r = 0; r < P; ++r)
+          x[u][r] = ld_stream(reinterpret_cast<const uint4*>(in[r]) + v +
+                              64u * u);
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        st_stream(reinterpret_cast<uint4*>(out) + v + 64u * u,
+                  VecCombine<Acc, P, Kind>::run(x[u]));
+    }
+    for (; v < nv; v += 64u) {
+      uint4 x[P];
+#pragma unroll
+      for (int r = 0; r < P; ++r)
+        x[r] = ld_stream(reinterpret_cast<const uint4*>(in[r]) + v);
+      st_stream(reinterpret_cast<uint4*>(out) + v,
+                VecCombine<Acc, P, Kind>::run(x));
+    }
+    const uint32_t tail = n - nv * kPerVec;  // < kPerVec <= 8
+    if (lane < tail) combine_scalar<Acc, P, Kind>(in, out, nv * kPerVec + lane);
+  }
+};
+
+// ------------------------------------------------------------- e4m3 tiles
+// Each lane owns 16 consecutive codes; a row of 16 lanes owns one block of
+// 256 elements and its scale.  Inputs: y = sum_r fl(dec(q_r) * s_r) in
+// binary32 (plain or Sum2), then per block amax = max |y|, s = fl(amax/448)
+// (s = 1 if that is not a normal number), codes e4m3(fl(y * fl(1/s))).
+// Tiles start on block boundaries (tile and partition lengths are multiples
+// of 256); only a bucket's last block can be short.
+__device__ __forceinline__ void dec16(const uint4& raw, float scale,
+                                      float (&o)[16]) {
+  const uint32_t w[4] = {raw.x, raw.y, raw.z, raw.w};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[k], false);
+    auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[k], true);
+    o[4 * k + 0] = lo[0] * scale;
+    o[4 * k + 1] = lo[1] * scale;
+    o[4 * k + 2] = hi[0] * scale;
+    o[4 * k + 3] = hi[1] * scale;
+  }
+}
+
+__device__ __forceinline__ uint4 load_codes(const uint8_t* p, uint32_t have) {
+  if (have >= 16u) return ld_stream(reinterpret_cast<const uint4*>(p));
+  uint32_t w[4] = {0u, 0u, 0u, 0u};
+  for (uint32_t j = 0; j < have; ++j) w[j >> 2] |= (uint32_t)p[j] << (8 * (j & 3));
+  return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+template <bool COMP>
+struct E4M3Tile {
+  template <int P>
+  __device__ __forceinline__ static void run(const_ptr<BucketDesc> bd, uint64_t e0,
+                                             uint32_t n) {
+    const uint32_t lane = lane_id();
+    const uint8_t* in[P];
+    const float* sc[P];
+#pragma unroll
+    for (int r = 0; r < P; ++r) {
+      in[r] = static_cast<const uint8_t*>(bd->in[r]) + e0;
+      sc[r] = bd->in_scale[r] + e0 / 256u;
+    }
+    uint8_t* out = static_cast<uint8_t*>(bd->out) + e0;
+    float* osc = bd->out_scale + e0 / 256u;
+    for (uint32_t base = 0; base < n; base += 1024u) {
+      const uint32_t el = base + lane * 16u;
+      const uint32_t blk = el / 256u;
+      const uint32_t have = el < n ? (n - el < 16u ? n - el : 16u) : 0u;
+      uint4 raw[P];
+      float s_in[P];
+#pragma unroll
+      for (int r = 0; r < P; ++r) {
+        raw[r] = have ? load_codes(in[r] + el, have) : make_uint4(0, 0, 0, 0);
+        s_in[r] = have ? sc[r][blk] : 0.0f;
+      }
+      FSum<COMP> acc[16];
+      {
+        float d[16];
+        dec16(raw[0], s_in[0], d);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) acc[j].init(d[j]);
+      }
+#pragma unroll
+      for (int r = 1; r < P; ++r) {
+        float d[16];
+        dec16(raw[r], s_in[r], d);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) acc[j].add(d[j]);
+      }
+      float y[16];
+      float amax = 0.0f;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        y[j] = acc[j].get();
+        if ((uint32_t)j < have) amax = fmaxf(amax, fabsf(y[j]));
+      }
+      // max over the 16 lanes of the block
+      amax = fmaxf(amax, __shfl_xor(amax, 8, 16));
+      amax = fmaxf(amax, __shfl_xor(amax, 4, 16));
+      amax = fmaxf(amax, __shfl_xor(amax, 2, 16));
+      amax = fmaxf(amax, __shfl_xor(amax, 1, 16));
+      float so = amax / 448.0f;
+      if (!(so >= 0x1p-126f)) so = 1.0f;
+      const float inv = 1.0f / so;
+      uint32_t w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+      for (int j = 0; j < 16; ++j) w[j >> 2] |= f_to_e4m3(y[j] * inv) << (8 * (j & 3));
+      if (have == 16u) {
+        st_stream(reinterpret_cast<uint4*>(out + el),
+                  make_uint4(w[0], w[1], w[2], w[3]));
+      } else if (have) {
+        for (uint32_t j = 0; j < have; ++j)
+          out[el + j] = (uint8_t)(w[j >> 2] >> (8 * (j & 3)));
+      }
+      if (have && (lane & 15u) == 0u) osc[blk] = so;
+    }
+  }
+};
+
+}  // namespace dev
+}  // namespace pcoll
