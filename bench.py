@@ -61,6 +61,8 @@ def parse():
     ap.add_argument("--log2n", type=int, default=26)
     ap.add_argument("--nparts", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the other workloads")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--probe-copy", action="store_true",
                     help="only run the streaming-copy probe (counter "
@@ -93,9 +95,9 @@ def probe_copy(pc, torch, steps):
 
 def cpu_baseline(orc, xs_dev, P, seconds):
     """The oracle (FP64 rank-order sum, element-parallel over the host
-    cores) on a bounded sample: the first 2^22 elements of every rank,
-    repeated until about `seconds` of CPU work."""
-    m = 1 << 22
+    cores) on a bounded sample: the first 2^24 elements (64 MiB) of every
+    rank, repeated until about `seconds` of CPU work."""
+    m = 1 << 24
     sample = [x[:m].cpu().numpy() for x in xs_dev]
     reps, t0 = 0, time.perf_counter()
     while True:
@@ -107,9 +109,178 @@ def cpu_baseline(orc, xs_dev, P, seconds):
     algo = (P * m * 4 + m * 4) * reps
     return {"value": round(algo / el / 1e9, 3), "unit": "GB/s",
             "cores": orc.omp_threads(), "kind": "oracle",
-            "sample": f"first 2^22 elements of each of the {P} ranks, FP64 "
+            "sample": f"first 2^24 elements of each of the {P} ranks, FP64 "
                       f"rank-order sum over host cores, {reps} repetitions "
                       f"in {el:.1f} s"}
+
+
+def _events(torch):
+    return (torch.cuda.Event(enable_timing=True),
+            torch.cuda.Event(enable_timing=True))
+
+
+def time_requests(torch, reqs, orders, stream, warmup, reps):
+    """Time-to-reduce of a set of requests sharing one stream: start all,
+    ready every partition (each request's seeded order, one list call per
+    request), wait all.  Returns (host ms per rep, device ms per rep)."""
+    import statistics
+    host, devt = [], []
+    for it in range(warmup + reps):
+        e0, e1 = _events(torch)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record(stream)
+        for r in reqs:
+            r.start()
+        e1.record(stream)
+        for r, o in zip(reqs, orders):
+            r.pready_list(o)
+        for r in reqs:
+            r.wait()
+        t1 = time.perf_counter()
+        e1.synchronize()
+        if it >= warmup:
+            host.append((t1 - t0) * 1e3)
+            devt.append(e0.elapsed_time(e1))
+    return statistics.median(host), statistics.median(devt)
+
+
+def extras(pc, torch, synth, warmup, reps):
+    """The other workloads, timed (correctness and error are the tests'
+    job: the full-size GPU tests check them against the oracle)."""
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(dev)
+    cur = torch.cuda.current_stream(dev)
+    out = {"copy_probe": probe_copy(pc, torch, 10)}
+
+    # workload 1: 4 ranks, FP32, 262144 elements, 8 partitions in order
+    xs = synth.uniform_f32(4, 262144, synth.seed_for(1), device=dev)
+    y = torch.empty(262144, device=dev)
+    req = pc.Request([262144], pc.FLOAT32, pc.SUM, 8, 4)
+    req.bind([xs], [y], stream=stream)
+    h, d = time_requests(torch, [req], [list(range(8))], stream, warmup,
+                         max(reps, 50))
+    out["plain_fp32_p4_1MiB"] = {"host_us": round(h * 1e3, 1),
+                                 "kernel_us": round(d * 1e3, 1),
+                                 "GBps": round(5 * 262144 * 4 / d / 1e6, 1)}
+    req.free()
+    del xs, y
+
+    # workload 3: 64 bf16 gradient buckets, batched graph vs separate fp32
+    counts = synth.batched_bf16_counts()
+    P, nparts = 8, 32
+    f32 = [synth.normal_f32(P, c, synth.seed_for(3) * 1000 + b, std=1e-3,
+                            device=dev) for b, c in enumerate(counts)]
+    bf = []
+    for bucket, c in zip(f32, counts):
+        row = []
+        for t in bucket:
+            o = torch.empty(c, dtype=torch.int16, device=dev)
+            pc.pcoll_pack_bf16(t, o, c, cur)
+            row.append(o)
+        bf.append(row)
+    torch.cuda.synchronize()
+    n_el = sum(counts)
+    res = {"buckets": len(counts), "elements_per_rank": n_el}
+    # (a) batched bf16, one persistent graph-replayed launch
+    yb = [torch.empty(c, dtype=torch.int16, device=dev) for c in counts]
+    rb = pc.Request(counts, pc.BFLOAT16, pc.SUM, nparts, P, batched=True)
+    rb.bind(bf, yb, stream=stream)
+    order = [int(p) for p in synth.permutation(len(counts) * nparts, 3)]
+    h, d = time_requests(torch, [rb], [order], stream, warmup, reps)
+    st = rb.stats()
+    res["batched_bf16_graph"] = {
+        "host_ms": round(h, 4), "kernel_ms": round(d, 4),
+        "GBps": round(n_el * 2 * (P + 1) / d / 1e6, 1),
+        "graph": rb.config().graph, "graph_captures": st.graph_captures,
+        "capture_ms": round(st.last_capture_ms, 3),
+        "instantiate_ms": round(st.last_instantiate_ms, 3)}
+    rb.free()
+    # (b) plain fp32: one request per bucket, no graph
+    yf = [torch.empty(c, device=dev) for c in counts]
+    reqs, orders = [], []
+    for b, c in enumerate(counts):
+        r = pc.Request([c], pc.FLOAT32, pc.SUM, nparts, P, batched=False)
+        r.set_config(graph=0)
+        r.bind([f32[b]], [yf[b]], stream=stream)
+        reqs.append(r)
+        orders.append([int(p) for p in synth.permutation(nparts, b)])
+    h, d = time_requests(torch, reqs, orders, stream, warmup, reps)
+    res["plain_fp32_separate"] = {
+        "host_ms": round(h, 4), "kernel_ms": round(d, 4),
+        "GBps": round(n_el * 4 * (P + 1) / d / 1e6, 1)}
+    # the bf16 result against the fp32 path's result (not the oracle)
+    num = den = 0.0
+    for b in range(len(counts)):
+        v = (yb[b].view(torch.bfloat16).float() - yf[b]).abs()
+        num = max(num, float(v.max()))
+        den = max(den, float(yf[b].abs().max()))
+    res["bf16_vs_fp32_path_max_abs_rel_to_max"] = num / den if den else 0.0
+    for r in reqs:
+        r.free()
+    # (c) batched fp32 (one launch): separates batching from precision
+    rf = pc.Request(counts, pc.FLOAT32, pc.SUM, nparts, P, batched=True)
+    rf.bind(f32, yf, stream=stream)
+    h, d = time_requests(torch, [rf], [order], stream, warmup, reps)
+    res["batched_fp32_graph"] = {"host_ms": round(h, 4),
+                                 "kernel_ms": round(d, 4),
+                                 "GBps": round(n_el * 4 * (P + 1) / d / 1e6,
+                                               1)}
+    rf.free()
+    res["bf16_batched_speedup_vs_plain_fp32"] = round(
+        res["plain_fp32_separate"]["host_ms"] /
+        res["batched_bf16_graph"]["host_ms"], 3)
+    out["batched_bf16_vs_plain_fp32"] = res
+    del f32, bf, yb, yf
+    torch.cuda.empty_cache()
+
+    # workload 4: int32, 16 ranks, 2^24 elements, 256 partitions
+    n4 = 1 << 24
+    xi = synth.uniform_i32(16, n4, synth.seed_for(4), -(1 << 20), 1 << 20,
+                           device=dev)
+    yi = torch.empty(n4, dtype=torch.int32, device=dev)
+    o4 = [int(p) for p in synth.permutation(256, synth.seed_for(4))]
+    for op, name in ((pc.SUM, "int32_sum_p16_64MiB"),
+                     (pc.MAX, "int32_max_p16_64MiB")):
+        r = pc.Request([n4], pc.INT32, op, 256, 16)
+        r.bind([xi], [yi], stream=stream)
+        h, d = time_requests(torch, [r], [o4], stream, warmup, reps)
+        out[name] = {"host_ms": round(h, 4), "kernel_ms": round(d, 4),
+                     "GBps": round(17 * n4 * 4 / d / 1e6, 1)}
+        r.free()
+    del xi, yi
+    torch.cuda.empty_cache()
+
+    # workload 5: e4m3, 8 ranks, 128 buckets totalling 2^30 elements
+    counts5 = synth.fp8_bucket_counts()
+    q5, s5 = [], []
+    for b, c in enumerate(counts5):
+        qrow, srow = [], []
+        for t in synth.normal_with_outliers_f32(
+                8, c, synth.seed_for(5) * 1000 + b, 1e-2, device=dev):
+            q = torch.empty(c, dtype=torch.uint8, device=dev)
+            s = torch.empty((c + 255) // 256, dtype=torch.float32, device=dev)
+            pc.pcoll_pack_fp8(t, q, s, c, cur)
+            qrow.append(q)
+            srow.append(s)
+        q5.append(qrow)
+        s5.append(srow)
+    torch.cuda.synchronize()
+    y5 = [torch.empty(c, dtype=torch.uint8, device=dev) for c in counts5]
+    ys5 = [torch.empty((c + 255) // 256, dtype=torch.float32, device=dev)
+           for c in counts5]
+    r5 = pc.Request(counts5, pc.FP8_E4M3, pc.SUM, 32, 8, batched=True)
+    r5.bind(q5, y5, s5, ys5, stream=stream)
+    o5 = [int(p) for p in synth.permutation(len(counts5) * 32, 5)]
+    h, d = time_requests(torch, [r5], [o5], stream, warmup, reps)
+    n5 = sum(counts5)
+    b5 = 9 * n5 + 9 * 4 * sum((c + 255) // 256 for c in counts5)
+    out["fp8_batched_p8_1GiB"] = {"host_ms": round(h, 4),
+                                  "kernel_ms": round(d, 4),
+                                  "GBps": round(b5 / d / 1e6, 1),
+                                  "comp": r5.config().comp}
+    r5.free()
+    return out
 
 
 def main():
@@ -212,6 +383,10 @@ def main():
         from oracle import get as get_oracle
         line["cpu_baseline"] = cpu_baseline(get_oracle(), xs, P,
                                             args.cpu_seconds)
+    del xs, out
+    torch.cuda.empty_cache()
+    if not args.no_extras:
+        line["extras"] = extras(pc, torch, synth, 2, 5)
     print(json.dumps(line), flush=True)
 
 

@@ -1,0 +1,175 @@
+"""Exhaustive launch-parameter search for libpcoll on the local GPU.
+
+Section 4.4 of the paper tunes scheduling parameters offline by exhaustive
+search and uses the results as defaults (environment variables override
+them), tuning graph and non-graph execution separately.  This tool does the
+same for the persistent reduce kernel: for each tuning key (dtype, op,
+ranks, graph mode, floor(log2(bytes per rank))) it times every
+(tile_elems, groups_per_cu) pair on seeded synthetic inputs and writes the
+fastest into the text table the library reads at request creation
+(tuned_mi355x.txt next to libpcoll.so, or PCOLL_TUNE_FILE).
+
+Timing: median device time of `reps` epochs (HIP events on the bound
+stream around start), every partition readied at once in a seeded random
+order, after `warmup` epochs.  Run on the target GPU:
+
+    python -m paper_2604_22228_amd.autotune --out paper_2604_22228_amd/tuned_mi355x.txt
+"""
+import argparse
+import json
+import math
+import os
+import statistics
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+DTYPE_NAMES = {0: "i32", 1: "f32", 2: "bf16", 3: "e4m3"}
+OP_NAMES = {0: "sum", 1: "max"}
+
+TILES = (1024, 2048, 4096, 8192, 16384, 32768, 65536, 131072)
+GROUPS_PER_CU = (1, 2, 4)
+
+
+def default_keys():
+    """The configurations of the five workloads: (dtype, op, ranks, graph,
+    list of per-bucket element counts, partitions per bucket)."""
+    keys = []
+    for k in range(10, 27, 2):  # the FP32 sweep, 4 KiB .. 256 MiB per rank
+        keys.append((1, 0, 8, 0, [1 << k], 64))
+    keys.append((1, 0, 4, 0, [262144], 8))          # plain workload
+    keys.append((0, 0, 16, 0, [1 << 24], 256))      # int32 sum
+    keys.append((0, 1, 16, 0, [1 << 24], 256))      # int32 max
+    return keys
+
+
+def time_config(pc, torch, synth, dtype, op, ranks, graph, counts, nparts,
+                tile, gpc, warmup, reps, bufs):
+    req = pc.Request(counts, dtype, op, nparts, ranks,
+                     batched=len(counts) > 1)
+    req.set_config(tile_elems=tile, groups_per_cu=gpc, graph=graph,
+                   groups=0)
+    ins, outs, rsc, osc, stream = bufs
+    req.bind(ins, outs, rsc, osc, stream=stream)
+    order = [int(p) for p in synth.permutation(req.nparts_total, 1)]
+    times = []
+    for it in range(warmup + reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        req.start()
+        e1.record(stream)
+        req.pready_list(order)
+        req.wait()
+        if it >= warmup:
+            e1.synchronize()
+            times.append(e0.elapsed_time(e1))
+    req.free()
+    return statistics.median(times)
+
+
+def make_buffers(pc, torch, synth, dtype, ranks, counts):
+    dev = torch.device("cuda:0")
+    tdt = {0: torch.int32, 1: torch.float32, 2: torch.int16,
+           3: torch.uint8}[dtype]
+    ins, outs, rsc, osc = [], [], None, None
+    if dtype == 3:
+        rsc, osc = [], []
+    for b, c in enumerate(counts):
+        m = max(c, 16)
+        if dtype == 0:
+            bucket = synth.uniform_i32(ranks, m, 10 + b, -(1 << 20), 1 << 20,
+                                       device=dev)
+        else:
+            x = synth.normal_f32(ranks, m, 10 + b, device=dev)
+            if dtype == 1:
+                bucket = x
+            elif dtype == 2:
+                bucket = []
+                for t in x:
+                    o = torch.empty(m, dtype=torch.int16, device=dev)
+                    pc.pcoll_pack_bf16(t, o, m, torch.cuda.current_stream())
+                    bucket.append(o)
+            else:
+                bucket, scales = [], []
+                for t in x:
+                    q = torch.empty(m, dtype=torch.uint8, device=dev)
+                    s = torch.empty((m + 255) // 256, dtype=torch.float32,
+                                    device=dev)
+                    pc.pcoll_pack_fp8(t, q, s, m, torch.cuda.current_stream())
+                    bucket.append(q)
+                    scales.append(s)
+                rsc.append(scales)
+                osc.append(torch.empty((m + 255) // 256, dtype=torch.float32,
+                                       device=dev))
+        ins.append(bucket)
+        outs.append(torch.empty(m, dtype=tdt, device=dev))
+    torch.cuda.synchronize()
+    return ins, outs, rsc, osc, torch.cuda.Stream(dev)
+
+
+def tune(keys, tiles, gpcs, warmup, reps, log=print):
+    import torch
+
+    from paper_2604_22228_amd import pcoll as pc
+    from paper_2604_22228_amd import synth
+
+    rows = []
+    for dtype, op, ranks, graph, counts, nparts in keys:
+        bufs = make_buffers(pc, torch, synth, dtype, ranks, counts)
+        nbytes = sum(counts) * pc.ELEM_BYTES[dtype]
+        lg = int(math.floor(math.log2(max(nbytes, 1))))
+        best = None
+        for tile in tiles:
+            for gpc in gpcs:
+                ms = time_config(pc, torch, synth, dtype, op, ranks, graph,
+                                 counts, nparts, tile, gpc, warmup, reps,
+                                 bufs)
+                log(json.dumps({"dtype": DTYPE_NAMES[dtype],
+                                "op": OP_NAMES[op], "ranks": ranks,
+                                "graph": graph, "log2_bytes": lg,
+                                "tile": tile, "gpc": gpc,
+                                "ms": round(ms, 5)}))
+                if best is None or ms < best[0]:
+                    best = (ms, tile, gpc)
+        rows.append((DTYPE_NAMES[dtype], OP_NAMES[op], ranks, graph, lg, lg,
+                     best[1], best[2], best[0]))
+        del bufs
+        torch.cuda.empty_cache()
+    return rows
+
+
+def write_table(rows, path):
+    lines = ["# Tuned launch parameters of libpcoll on MI355X (gfx950), "
+             "written by paper_2604_22228_amd/autotune.py.",
+             "# dtype op ranks graph log2_lo log2_hi tile_elems "
+             "groups_per_cu   # median kernel ms"]
+    for d, o, r, g, lo, hi, t, gpc, ms in rows:
+        lines.append(f"{d} {o} {r} {g} {lo} {hi} {t} {gpc}   # {ms:.4f}")
+    with open(path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=os.path.join(
+        os.path.dirname(os.path.abspath(__file__)), "tuned_mi355x.txt"))
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--quick", action="store_true",
+                    help="a reduced grid (for a smoke run)")
+    args = ap.parse_args()
+    keys = default_keys()
+    tiles, gpcs = TILES, GROUPS_PER_CU
+    if args.quick:
+        keys, tiles, gpcs = keys[:2], (4096, 65536), (1, 2)
+    rows = tune(keys, tiles, gpcs, args.warmup, args.reps,
+                log=lambda s: print(s, flush=True))
+    write_table(rows, args.out)
+    print(f"wrote {args.out} ({len(rows)} rows)", flush=True)
+
+
+if __name__ == "__main__":
+    main()
