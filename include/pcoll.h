@@ -191,13 +191,16 @@ typedef struct {
   int graph;         /* 1 = start replays a cached graph, 0 = direct launch */
   int timeout_ms;    /* device-side deadline of one epoch */
   int debug;         /* 1 = count tiles reduced per partition */
+  int interleave;    /* tile layout: 0 = each tile is a contiguous range of
+                        its partition; 1 = tile j of n takes every n-th row
+                        (64 lanes x 16 bytes) starting at row j */
 } pcoll_config_t;
 
 /* Reads the request's configuration.  The defaults come from the tuned
  * table (env PCOLL_TUNE_FILE, else the table shipped next to the library),
  * then from environment overrides: PCOLL_TILE, PCOLL_GROUPS,
  * PCOLL_GROUPS_PER_CU, PCOLL_COMP, PCOLL_GRAPH, PCOLL_TIMEOUT_MS,
- * PCOLL_DEBUG. */
+ * PCOLL_DEBUG, PCOLL_INTERLEAVE. */
 int pcoll_get_config(pcoll_req_t req, pcoll_config_t *cfg);
 
 /* Replaces the configuration (not while an epoch is active).  Fields out of

@@ -27,26 +27,24 @@ hipError_t launch_reduce(const ReduceArgs& a, int dtype, int op, bool comp,
 }
 
 // ------------------------------------------------------------ ready signal
-// Appends parts[0..n) to the device ready list with the running epoch.  One
-// workgroup reserves its slots with a single atomic; each slot is one
-// 64-bit store, so a reader sees either the old or the new entry.
+// Appends parts[0..n) to the device ready ring.  One workgroup reserves its
+// entries with a single atomic on the ring's 64-bit entry counter; entry c
+// goes to slot c % capacity as one 64-bit store ((uint32)c << 32) | part,
+// so a reader sees either the old or the new entry and can tell them apart.
 __global__ __launch_bounds__(256) void pready_kernel(PreadyArgs a) {
-  __shared__ uint32_t base;
+  __shared__ uint64_t base;
   const uint32_t i = blockIdx.x * 256u + threadIdx.x;
   const uint32_t first = blockIdx.x * 256u;
   const uint32_t cnt = a.n - first < 256u ? a.n - first : 256u;
-  const uint32_t epoch = dev::ld_acq(&a.ctr->epoch);
   if (threadIdx.x == 0)
-    base = __hip_atomic_fetch_add(&a.ctr->dreserve, cnt, __ATOMIC_RELAXED,
-                                  __HIP_MEMORY_SCOPE_AGENT);
+    base = __hip_atomic_fetch_add(&a.ctr->dreserve, (uint64_t)cnt,
+                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
   if (i < a.n) {
-    const uint64_t v = ((uint64_t)epoch << 32) | (uint32_t)a.parts[i];
-    // slots beyond the list (more readies than partitions) are dropped
-    const uint32_t slot = base + threadIdx.x;
-    if (slot < a.capacity)
-      __hip_atomic_store(&a.dlist[slot], v, __ATOMIC_RELEASE,
-                         __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t c = base + threadIdx.x;
+    const uint64_t v = ((uint64_t)(uint32_t)c << 32) | (uint32_t)a.parts[i];
+    __hip_atomic_store(&a.dlist[c % a.capacity], v, __ATOMIC_RELEASE,
+                       __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -54,6 +52,15 @@ hipError_t launch_pready(const PreadyArgs& a, hipStream_t s) {
   if (a.n == 0) return hipSuccess;
   hipLaunchKernelGGL(pready_kernel, dim3((a.n + 255u) / 256u), dim3(256), 0,
                      s, a);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void reset_kernel(ResetArgs a) {
+  dev::reset_epoch(a);
+}
+
+hipError_t launch_reset(const ResetArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -5,8 +5,10 @@
 // contributions each.  Bucket b is split into nparts partitions by the chunk
 // rule of Algorithm 1 (Section 4.3): equal lengths fixed in advance, running
 // offsets, the last one clipped.  Global partition g = b * nparts + k.  A
-// partition is further cut into tiles of `tile_elems` elements; a tile is the
-// unit one wavefront reduces.  Destination regions of partitions and tiles
+// partition is further cut into tiles of about `tile_elems` elements; a tile
+// is the unit one wavefront reduces.  A partition is a sequence of rows (one
+// row = 64 lanes x 16 bytes per rank); a tile is a set of rows, either
+// consecutive or interleaved with the partition's other tiles.  Destination regions of partitions and tiles
 // are disjoint (Section 4.5, Ordering Guarantee), so each is written once.
 #pragma once
 #include <stdint.h>
@@ -45,37 +47,37 @@ struct QEntry {
 // Host-coherent pinned memory shared with the host thread.  Followed in the
 // same allocation by hlist[nparts] and arrived[nparts] (uint32 each).
 struct HostShared {
-  uint32_t epoch;       // host: stamp of the running epoch (informational)
-  uint32_t hcount;      // host: entries in hlist this epoch (store-release)
-  uint32_t abort;       // host: == epoch asks the kernel to give up
-  uint32_t done_epoch;  // device: last epoch whose kernel has drained
-  uint32_t status;      // device: 0, or an error code for done_epoch
-  uint32_t reserved[27];
+  uint32_t epoch;         // host: stamp of the next / running epoch, stored
+                          // before the launch
+  uint32_t hcount;        // host: entries in hlist this epoch (store-release)
+  uint32_t abort;         // host: == epoch asks the kernel to give up
+  uint32_t status;        // device: error code of epoch status_epoch
+  uint32_t status_epoch;  // device: epoch the status belongs to
+  uint32_t reset_done;    // host: 1 = clear every done counter at the next
+                          // start (the last epoch was abandoned midway)
+  uint32_t reserved[26];
 };
 
 // Device-memory counters of one request; each group on its own 128-B line
-// so that polling one does not contend with atomics on another.
+// so that polling one does not contend with atomics on another.  The reset
+// kernel that precedes every reduce launch clears claim, qstate, the ingest
+// group and error; the device ready list counters are never cleared (they
+// index a ring, see ReduceArgs::dlist).
 struct DevCounters {
-  uint32_t claim;                 // next global tile index to hand out
+  uint32_t claim;                 // tiles handed out beyond the first round
   uint32_t pad0[31];
   uint64_t qstate;                // (queue entries << 32) | queued tiles
   uint32_t pad1[30];
   uint32_t ilock;                 // ingest lock (0 free, 1 held)
   uint32_t hconsumed;             // host ready entries already queued
-  uint32_t dconsumed;             // device ready entries already queued
-  uint32_t pad2[29];
-  uint32_t exit_count;            // wavefronts that have left the kernel
+  uint64_t dconsumed;             // device ready entries already queued
+  uint32_t pad2[28];
   uint32_t error;                 // first error seen this epoch
+  uint32_t epoch;                 // epoch of the running launch
   uint32_t pad3[30];
-  uint32_t dreserve;              // slots reserved in the device ready list
-  uint32_t pad4[31];
-  uint32_t epoch;                 // epoch of the next (or running) launch:
-                                  // 1 at creation, +1 by each launch's last
-                                  // wavefront, so it always equals the
-                                  // host's count of starts while one runs
-  uint32_t pad5[31];
+  uint64_t dreserve;              // device ready entries ever reserved
+  uint32_t pad4[30];
 };
-
 // Error codes a kernel can leave in HostShared::status.
 enum KernelStatus : uint32_t {
   kStatusOk = 0,
@@ -91,7 +93,9 @@ struct ReduceArgs {
   uint32_t* done;         // [nparts_total] finished tiles per partition
   uint32_t* queued;       // [nparts_total] epoch stamp once queued
   uint32_t* tile_hits;    // [nparts_total] debug: tiles reduced, or null
-  uint64_t* dlist;        // [nparts_total] device ready list
+  uint64_t* dlist;        // [nparts_total] device ready ring: entry number
+                          // c lives in slot c % nparts_total as
+                          // ((uint32)c << 32) | part
   DevCounters* ctr;
   HostShared* host;       // device-visible address of the host struct
   const uint32_t* hlist;  // device-visible host ready list
@@ -100,6 +104,9 @@ struct ReduceArgs {
   uint32_t total_tiles;
   uint32_t tile_elems;
   uint32_t total_waves;
+  uint32_t interleave;    // 0: tile = contiguous rows; 1: tile j of nt takes
+                          // rows j, j + nt, j + 2 nt, ... of its partition
+  uint32_t reserved;
   uint64_t timeout_ticks; // device wall-clock ticks before giving up
 };
 
@@ -109,6 +116,13 @@ struct PreadyArgs {
   uint32_t capacity;      // slots in dlist (= partitions of the request)
   uint64_t* dlist;
   DevCounters* ctr;
+};
+
+struct ResetArgs {
+  DevCounters* ctr;
+  const HostShared* host;  // device-visible address
+  uint32_t* done;
+  uint32_t nparts_total;
 };
 
 }  // namespace pcoll

@@ -1,33 +1,36 @@
 // Device side of the persistent partitioned reduction (gfx950, wave64).
 //
-// One launch serves one epoch of a request.  Every wavefront is an
-// independent worker; no wavefront ever waits for another one, so the
-// launch needs no co-residency and drains even if it is larger than the
-// machine.  A worker loops:
+// One launch serves one epoch of a request; a one-workgroup reset kernel
+// runs just before it on the same stream (or in the same graph) and clears
+// the epoch's counters, so no wavefront of the reduce kernel ever has to
+// find out that it is the last one.  Every wavefront is an independent
+// worker; none ever waits for another, so the launch needs no co-residency
+// and drains even if it is larger than the machine.  A worker loops:
 //
-//   1. claim the next global tile index t with one atomic add (the claim of
-//      the following tile is issued before the current tile is reduced, so
-//      its latency hides behind the tile);
-//   2. wait until t is covered by the work queue.  While starved, the worker
-//      tries to move newly readied partitions into the queue: it takes a
-//      try-lock, reads the host ready list (host-coherent memory, written by
-//      pready) and the device ready list (written by the pready kernel), and
-//      appends each partition not yet queued this epoch together with the
-//      running total of its tiles.  Partitions are thus reduced in the order
-//      they became ready (the 2-D pipelining of Section 4.3: the message is
-//      cut into chunks that proceed as soon as they can);
+//   1. take a global tile index t: its wavefront number the first time
+//      (no atomic, so the launch does not start with a burst of atomics on
+//      one address), then one atomic add per tile, issued before the
+//      current tile is reduced so that its latency hides behind the tile;
+//   2. wait until t is covered by the work queue.  While starved, the few
+//      workers at the front of the claim order try to move newly readied
+//      partitions into the queue: under a try-lock, read the host ready
+//      list (host-coherent memory, written by pready) and the device ready
+//      ring (written by the ready kernel), and append each partition not yet
+//      queued this epoch together with the running total of its tiles.
+//      Partitions are reduced in the order they became ready (the chunk
+//      pipeline of Section 4.3: chunks proceed as soon as they can);
 //   3. find the queue entry covering t (64 entries per wave-wide probe),
 //      giving the partition and the tile inside it;
 //   4. reduce the tile (rank order 0..P-1 per element), store the result;
-//   5. publish: fence, then one lane adds 1 to the partition's done
-//      counter; the lane that completes the partition stores the epoch into
-//      its arrived flag in host-coherent memory (completion is signalled
-//      only after every chunk of the partition has landed, Section 4.5).
+//   5. publish: one release add on the partition's done counter; the worker
+//      that completes the partition stores the epoch into its arrived flag
+//      in host-coherent memory (completion is signalled only after every
+//      chunk of the partition has landed, Section 4.5).
 //
 // Exit: t >= total tiles.  A worker that starves past the deadline, or sees
-// the host's abort word, records the reason and leaves; the others follow.
-// The last worker out resets the counters for the next epoch and stores the
-// epoch into done_epoch, which the host's wait polls.
+// the host's abort word, records the reason (also in host memory, stamped
+// with the epoch) and leaves; the others follow.  The host's wait returns
+// when every arrived flag carries the epoch, or when an error is recorded.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -143,9 +146,9 @@ __device__ __forceinline__ bool try_ingest(const ReduceArgs& a, uint32_t epoch) 
   if (!uni(got)) return false;
 
   uint32_t hcons = uni(ld_rlx(&c->hconsumed));
-  uint32_t dcons = uni(ld_rlx(&c->dconsumed));
+  uint64_t dcons = uni64(ld_rlx64(&c->dconsumed));
   uint32_t hc = uni(ld_acq_sys(&a.host->hcount));
-  uint32_t dr = uni(ld_acq(&c->dreserve));
+  uint64_t dr = uni64(ld_acq64(&c->dreserve));
   uint64_t qs = uni64(ld_rlx64(&c->qstate));
   uint32_t qcount = (uint32_t)(qs >> 32), qtiles = (uint32_t)qs;
   const uint32_t qtiles0 = qtiles;
@@ -164,35 +167,44 @@ __device__ __forceinline__ bool try_ingest(const ReduceArgs& a, uint32_t epoch) 
   }
   hcons = hc > hcons ? hc : hcons;
 
-  // device ready list: entries are (epoch << 32) | part; stop at the first
-  // reserved slot whose writer has not stored it yet
-  uint32_t dend = dr < a.nparts_total ? dr : a.nparts_total;
-  for (uint32_t base = dcons; base < dend; base += 64) {
-    uint32_t i = base + lane;
-    bool in = i < dend;
-    uint64_t v = in ? ld_rlx64(&a.dlist[i]) : 0ull;
-    bool ok = in && (uint32_t)(v >> 32) == epoch;
-    uint64_t pending = __ballot(in && !ok);
-    uint32_t lim = pending ? (uint32_t)(__ffsll((long long)pending) - 1) : 64u;
+  // device ready ring: entry c sits in slot c % nparts_total, stored as
+  // ((uint32)c << 32) | part; stop at the first reserved entry whose writer
+  // has not stored it yet (its slot still holds another tag)
+  while (dcons < dr) {
+    const uint64_t c = dcons + lane;
+    const bool in = c < dr;
+    uint64_t v = in ? ld_rlx64(&a.dlist[c % a.nparts_total]) : 0ull;
+    const bool ok = in && (uint32_t)(v >> 32) == (uint32_t)c;
+    const uint64_t pending = __ballot(in && !ok);
+    const uint32_t lim =
+        pending ? (uint32_t)(__ffsll((long long)pending) - 1) : 64u;
     queue_append(a, epoch, ok && lane < lim, (uint32_t)v, qcount, qtiles);
-    uint32_t avail = dend - base < 64u ? dend - base : 64u;
-    dcons = base + (lim < avail ? lim : avail);
+    const uint64_t avail = dr - dcons < 64u ? dr - dcons : 64u;
+    dcons += lim < avail ? lim : avail;
     if (pending) break;
   }
 
   st_rlx(&c->hconsumed, hcons);
-  st_rlx(&c->dconsumed, dcons);
+  st_rlx64(&c->dconsumed, dcons);
   st_rel64(&c->qstate, ((uint64_t)qcount << 32) | qtiles);
   if (lane == 0) st_rel(&c->ilock, 0u);
   return qtiles != qtiles0;
 }
 
-__device__ __forceinline__ void set_error(const ReduceArgs& a, uint32_t code) {
+// Records the first error of the epoch; the recording wavefront also
+// publishes it to the host, stamped with the epoch.
+__device__ __forceinline__ void set_error(const ReduceArgs& a, uint32_t code,
+                                          uint32_t epoch) {
   if (lane_id() == 0) {
     uint32_t expect = 0;
-    __hip_atomic_compare_exchange_strong(&a.ctr->error, &expect, code,
-                                         __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                         __HIP_MEMORY_SCOPE_AGENT);
+    if (__hip_atomic_compare_exchange_strong(&a.ctr->error, &expect, code,
+                                             __ATOMIC_RELAXED,
+                                             __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT)) {
+      __hip_atomic_store(&a.host->status, code, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_SYSTEM);
+      st_rel_sys(&a.host->status_epoch, epoch);
+    }
   }
 }
 
@@ -213,11 +225,11 @@ __device__ __forceinline__ uint64_t wait_queued(const ReduceArgs& a,
     if (uni(ld_rlx(&a.ctr->error)) != 0u) return 0;
     if ((spins & 7u) == 7u) {
       if (front && uni(ld_acq_sys(&a.host->abort)) == epoch) {
-        set_error(a, kStatusAborted);
+        set_error(a, kStatusAborted, epoch);
         return 0;
       }
       if (wall_clock64() - t0 > a.timeout_ticks) {
-        set_error(a, kStatusTimeout);
+        set_error(a, kStatusTimeout, epoch);
         return 0;
       }
     }
@@ -277,55 +289,26 @@ __device__ __forceinline__ void finish_tile(const ReduceArgs& a, uint32_t part,
   }
 }
 
-// Leaves the kernel; the last wavefront resets the epoch state.
-__device__ __forceinline__ void leave(const ReduceArgs& a, uint32_t epoch) {
-  const uint32_t lane = lane_id();
-  DevCounters* c = a.ctr;
-  uint32_t last = 0;
-  if (lane == 0)
-    last = __hip_atomic_fetch_add(&c->exit_count, 1u, __ATOMIC_ACQ_REL,
-                                  __HIP_MEMORY_SCOPE_AGENT) +
-               1u ==
-           a.total_waves;
-  if (!uni(last)) return;
-  uint32_t err = uni(ld_acq(&c->error));
-  if (err != 0u) {
-    // an abandoned epoch can leave partial done counts behind
-    for (uint32_t p = lane; p < a.nparts_total; p += 64) st_rlx(&a.done[p], 0u);
-  }
-  if (lane == 0) {
-    st_rlx(&c->claim, 0u);
-    st_rlx64(&c->qstate, 0ull);
-    st_rlx(&c->hconsumed, 0u);
-    st_rlx(&c->dconsumed, 0u);
-    st_rlx(&c->dreserve, 0u);
-    st_rlx(&c->error, 0u);
-    st_rlx(&c->ilock, 0u);
-    st_rlx(&c->exit_count, 0u);
-    st_rlx(&c->epoch, epoch + 1u);
-    __threadfence_system();
-    __hip_atomic_store(&a.host->status, err, __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_SYSTEM);
-    st_rel_sys(&a.host->done_epoch, epoch);
-  }
-}
-
+// The tile index after the first round: one relaxed atomic add by lane 0.
 __device__ __forceinline__ uint32_t claim(const ReduceArgs& a) {
   uint32_t t = 0;
   if (lane_id() == 0)
     t = __hip_atomic_fetch_add(&a.ctr->claim, 1u, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
+                               __HIP_MEMORY_SCOPE_AGENT) +
+        a.total_waves;
   return t;  // valid in lane 0; broadcast by the caller when needed
 }
 
-// The worker loop.  Tile::run<P>(bucket, first element, length) reduces one
+// The worker loop.  Tile::run<P>(bucket, partition offset, partition length,
+// tile index, tiles of the partition, tile_elems, interleave) reduces one
 // tile with the whole wavefront.
 template <class Tile, int P>
 __device__ __forceinline__ void persistent_loop(const ReduceArgs& a) {
   const uint32_t epoch = uni(ld_acq(&a.ctr->epoch));
   const uint64_t t0 = wall_clock64();
   uint32_t cursor = 0, prev_end = 0;
-  uint32_t t = uni(claim(a));
+  // first round: tile = global wavefront number
+  uint32_t t = uni((blockIdx.x * blockDim.x + threadIdx.x) / 64u);
   while (t < a.total_tiles) {
     uint64_t qs = wait_queued(a, t, epoch, t0);
     if (qs == 0) break;
@@ -338,15 +321,30 @@ __device__ __forceinline__ void persistent_loop(const ReduceArgs& a) {
     const const_ptr<BucketDesc> bd =
         (const_ptr<BucketDesc>)(a.buckets) + pd->bucket;
     const uint32_t lt = t - prev_end;
-    const uint64_t skip = (uint64_t)lt * a.tile_elems;
-    const uint64_t rest = plen > skip ? plen - skip : 0;
-    const uint32_t n = (uint32_t)(rest < a.tile_elems ? rest : a.tile_elems);
     uint32_t next = claim(a);  // in flight while the tile is reduced
-    Tile::template run<P>(bd, poff + skip, n);
+    Tile::template run<P>(bd, poff, plen, lt, pnt, a.tile_elems,
+                          a.interleave);
     finish_tile(a, part, pnt, epoch);
     t = uni(next);
   }
-  leave(a, epoch);
+}
+
+// Clears the counters of an epoch before its reduce launch (one workgroup)
+// and copies the epoch stamp from host memory into device memory.
+__device__ __forceinline__ void reset_epoch(const ResetArgs& a) {
+  DevCounters* c = a.ctr;
+  if (threadIdx.x == 0) {
+    st_rlx(&c->claim, 0u);
+    st_rlx64(&c->qstate, 0ull);
+    st_rlx(&c->ilock, 0u);
+    st_rlx(&c->hconsumed, 0u);
+    st_rlx(&c->error, 0u);
+    st_rlx(&c->epoch, ld_acq_sys(&a.host->epoch));
+  }
+  // an abandoned epoch can leave partial done counts behind
+  if (ld_acq_sys(&a.host->reset_done))
+    for (uint32_t p = threadIdx.x; p < a.nparts_total; p += blockDim.x)
+      st_rlx(&a.done[p], 0u);
 }
 
 // ------------------------------------------------------ memory streaming

@@ -6,8 +6,9 @@
 //   * host-coherent pinned memory (HostShared + ready list + arrived flags)
 //     is the channel between the host thread and the running kernel:
 //     pready appends to the ready list and publishes its length with a
-//     store-release; the kernel stores arrived[p] = epoch and, at the end,
-//     done_epoch = epoch;
+//     store-release; the kernel stores arrived[p] = epoch when partition p
+//     is final, and an epoch-stamped status if it gives up; the host's wait
+//     returns once every arrived flag carries the epoch;
 //   * device memory holds the partition table, the work queue and the
 //     counters the kernel's wavefronts share;
 //   * an LRU cache (Section 4.2's graph cache) maps each binding to its
@@ -163,6 +164,8 @@ struct pcoll_req_s {
 
   uint32_t epoch = 0;
   bool active = false;
+  bool reset_pending = false;   // last epoch abandoned: clear done counters
+  uint32_t scan = 0;            // first partition not yet seen arrived
   uint32_t hcount = 0;
   std::vector<uint32_t> stamp;  // epoch in which each partition was readied
   pcoll_stats_t stats{};
@@ -188,7 +191,8 @@ uint64_t launch_signature(const pcoll_req_s* r) {
   uint64_t h = 1469598103934665603ull;
   const uint64_t v[] = {(uint64_t)r->cfg.tile_elems, (uint64_t)r->groups,
                         (uint64_t)r->cfg.comp, (uint64_t)r->cfg.debug,
-                        (uint64_t)r->cfg.timeout_ms, r->total_tiles};
+                        (uint64_t)r->cfg.timeout_ms, r->total_tiles,
+                        (uint64_t)r->cfg.interleave};
   for (uint64_t x : v) {
     h ^= x;
     h *= 1099511628211ull;
@@ -209,6 +213,7 @@ int validate_config(const pcoll_req_s* r, const pcoll_config_t& c) {
   if (c.graph != 0 && c.graph != 1) return PCOLL_ERR_ARG;
   if (c.timeout_ms < 1 || c.timeout_ms > 3600 * 1000) return PCOLL_ERR_ARG;
   if (c.debug != 0 && c.debug != 1) return PCOLL_ERR_ARG;
+  if (c.interleave != 0 && c.interleave != 1) return PCOLL_ERR_ARG;
   return PCOLL_SUCCESS;
 }
 
@@ -252,6 +257,7 @@ pcoll_config_t default_config(const pcoll_req_s* r) {
   TuneChoice t = tune_lookup(tune_rows(), r->dtype, r->op, r->nranks, c.graph,
                              bytes);
   c.tile_elems = env_int("PCOLL_TILE", t.tile_elems);
+  c.interleave = env_int("PCOLL_INTERLEAVE", t.interleave) ? 1 : 0;
   c.groups = env_int("PCOLL_GROUPS", 0);
   c.groups_per_cu = env_int("PCOLL_GROUPS_PER_CU", t.groups_per_cu);
   const bool float_sum = r->op == PCOLL_SUM && r->dtype != PCOLL_INT32;
@@ -304,6 +310,7 @@ int create(const std::vector<uint64_t>& counts, int dtype, int op,
   const uint64_t align = part_align(dtype);
   for (size_t b = 0; b < counts.size(); ++b) {
     const uint64_t ps = plan_psize(counts[b], (uint64_t)nparts, align);
+    if (ps > (1ull << 31)) return PCOLL_ERR_UNSUPPORTED;  // 32-bit row math
     for (int k = 0; k < nparts; ++k) {
       PartDesc p{};
       const uint64_t off = std::min<uint64_t>((uint64_t)k * ps, counts[b]);
@@ -356,10 +363,9 @@ int create(const std::vector<uint64_t>& counts, int dtype, int op,
   if (e != hipSuccess) return e == hipErrorOutOfMemory ? PCOLL_ERR_NOMEM
                                                        : hip_fail(e, "hipMalloc");
   HIP_TRY(hipMemset(r->arena, 0, off));
-  const uint32_t first_epoch = 1;  // the device-side epoch of the first start
-  HIP_TRY(hipMemcpy(&reinterpret_cast<DevCounters*>(
-                         static_cast<char*>(r->arena) + o_ctr)->epoch,
-                    &first_epoch, sizeof(first_epoch), hipMemcpyHostToDevice));
+  // ring slots start with a tag no entry number below 2^32 - 1 carries
+  HIP_TRY(hipMemset(static_cast<char*>(r->arena) + o_dlist, 0xff,
+                    sizeof(uint64_t) * np_total));
   char* base = static_cast<char*>(r->arena);
   r->d_parts = reinterpret_cast<PartDesc*>(base + o_parts);
   r->d_queue = reinterpret_cast<QEntry*>(base + o_queue);
@@ -400,11 +406,19 @@ ReduceArgs make_args(const pcoll_req_s* r) {
   a.total_tiles = r->total_tiles;
   a.tile_elems = (uint32_t)r->cfg.tile_elems;
   a.total_waves = (uint32_t)r->groups * kWavesPerGroup;
+  a.interleave = (uint32_t)r->cfg.interleave;
   a.timeout_ticks = (uint64_t)r->cfg.timeout_ms * (uint64_t)r->clock_khz;
   return a;
 }
 
+// One epoch's launch: the reset kernel, then the persistent reduce kernel.
 int launch_direct(pcoll_req_t r, hipStream_t s) {
+  ResetArgs ra{};
+  ra.ctr = r->d_ctr;
+  ra.host = r->host_dev;
+  ra.done = r->d_done;
+  ra.nparts_total = r->nparts_total;
+  HIP_TRY(launch_reset(ra, s));
   const ReduceArgs a = make_args(r);
   HIP_TRY(launch_reduce(a, r->dtype, r->op, r->cfg.comp != 0, r->nranks,
                         r->groups, s));
@@ -454,32 +468,51 @@ int launch_graph(pcoll_req_t r) {
   return PCOLL_SUCCESS;
 }
 
-// Completes the epoch once done_epoch == epoch.
-int finish_epoch(pcoll_req_t r) {
+// Error recorded by the kernel for the current epoch (0 if none).
+uint32_t epoch_status(const pcoll_req_s* r) {
+  if (__atomic_load_n(&r->host->status_epoch, __ATOMIC_ACQUIRE) != r->epoch)
+    return kStatusOk;
+  return __atomic_load_n(&r->host->status, __ATOMIC_RELAXED);
+}
+
+// Whether every partition has arrived this epoch; `scan` remembers the
+// first one not seen arrived, so a wait reads each flag about once.
+bool all_arrived(pcoll_req_s* r) {
+  while (r->scan < r->nparts_total &&
+         __atomic_load_n(&r->arrived[r->scan], __ATOMIC_ACQUIRE) == r->epoch)
+    ++r->scan;
+  return r->scan == r->nparts_total;
+}
+
+// Completes the epoch: every partition arrived, or the kernel gave up (then
+// wait for it to drain before reporting).
+int finish_epoch(pcoll_req_t r, uint32_t st) {
   r->active = false;
-  const uint32_t st = __atomic_load_n(&r->host->status, __ATOMIC_ACQUIRE);
+  if (st != kStatusOk) {
+    r->reset_pending = true;
+    HIP_TRY(hipEventSynchronize(r->ev_end));
+    return st == kStatusTimeout ? PCOLL_ERR_ABORTED : PCOLL_ERR_TIMEOUT;
+  }
   if (r->cfg.debug && r->ev_start_recorded) {
     float ms = -1.0f;
     if (hipEventSynchronize(r->ev_end) == hipSuccess &&
         hipEventElapsedTime(&ms, r->ev_start, r->ev_end) == hipSuccess)
       r->stats.last_kernel_ms = ms;
   }
-  if (st == kStatusTimeout) return PCOLL_ERR_ABORTED;
-  if (st == kStatusAborted) return PCOLL_ERR_TIMEOUT;
   return PCOLL_SUCCESS;
 }
 
-bool epoch_done(const pcoll_req_s* r) {
-  return __atomic_load_n(&r->host->done_epoch, __ATOMIC_ACQUIRE) == r->epoch;
-}
-
-// Spins until the epoch drains.  With limit_ms >= 0, asks the kernel to
-// stop waiting after that long.  A kernel that never reports (it cannot
-// without a fault: it has its own deadline) is detected through its event.
+// Spins until the epoch completes.  With limit_ms >= 0, asks the kernel to
+// stop waiting for unready partitions after that long.  A kernel that
+// retires without completing the epoch (only a fault could do that: it has
+// its own deadline) is detected through its event.
 int spin_wait(pcoll_req_t r, int limit_ms) {
   auto t0 = std::chrono::steady_clock::now();
   bool aborted = false;
-  for (uint64_t it = 0; !epoch_done(r); ++it) {
+  for (uint64_t it = 0;; ++it) {
+    if (all_arrived(r)) return finish_epoch(r, kStatusOk);
+    const uint32_t st = epoch_status(r);
+    if (st != kStatusOk) return finish_epoch(r, st);
     _mm_pause();
     if ((it & 1023) != 1023) continue;
     const double el = ms_since(t0);
@@ -489,17 +522,20 @@ int spin_wait(pcoll_req_t r, int limit_ms) {
     }
     hipError_t q = hipEventQuery(r->ev_end);
     if (q == hipSuccess) {
-      if (epoch_done(r)) break;
+      if (all_arrived(r)) return finish_epoch(r, kStatusOk);
+      const uint32_t st2 = epoch_status(r);
+      if (st2 != kStatusOk) return finish_epoch(r, st2);
       r->active = false;
-      g_detail = "kernel retired without reporting completion";
+      r->reset_pending = true;
+      g_detail = "kernel retired without completing the epoch";
       return PCOLL_ERR_HIP;
     }
     if (q != hipErrorNotReady) {
       r->active = false;
+      r->reset_pending = true;
       return hip_fail(q, "hipEventQuery");
     }
   }
-  return finish_epoch(r);
 }
 
 int check_req(pcoll_req_t r) { return r ? PCOLL_SUCCESS : PCOLL_ERR_ARG; }
@@ -647,12 +683,14 @@ int pcoll_start(pcoll_req_t r) {
   if (!r->bound || r->active) return PCOLL_ERR_STATE;
   HIP_TRY(hipSetDevice(r->device));
   const uint32_t e = r->epoch + 1;
-  // no kernel of this request runs now: the host owns the shared words
+  // the request's previous kernels are ordered before this launch on the
+  // stream, and a finished epoch no longer reads these words
   r->host->hcount = 0;
   r->host->abort = 0;
-  r->host->status = 0;
+  r->host->reset_done = r->reset_pending ? 1u : 0u;
   __atomic_store_n(&r->host->epoch, e, __ATOMIC_RELEASE);
   r->hcount = 0;
+  r->scan = 0;
   if (r->cfg.debug) {
     HIP_TRY(hipMemsetAsync(r->d_hits, 0, sizeof(uint32_t) * r->nparts_total,
                            r->stream));
@@ -665,6 +703,7 @@ int pcoll_start(pcoll_req_t r) {
   r->ev_end_recorded = true;
   r->epoch = e;
   r->active = true;
+  r->reset_pending = false;
   r->stats.epochs++;
   r->stats.groups = r->groups;
   r->stats.total_tiles = (int)r->total_tiles;
@@ -749,17 +788,23 @@ int pcoll_test(pcoll_req_t r, int* flag) {
     *flag = 1;
     return PCOLL_SUCCESS;
   }
-  if (!epoch_done(r)) {
-    hipError_t q = hipEventQuery(r->ev_end);
-    if (q != hipSuccess && q != hipErrorNotReady) {
-      r->active = false;
-      return hip_fail(q, "hipEventQuery");
-    }
-    *flag = 0;
-    return PCOLL_SUCCESS;
+  if (all_arrived(r)) {
+    *flag = 1;
+    return finish_epoch(r, kStatusOk);
   }
-  *flag = 1;
-  return finish_epoch(r);
+  const uint32_t st = epoch_status(r);
+  if (st != kStatusOk) {
+    *flag = 1;
+    return finish_epoch(r, st);
+  }
+  hipError_t q = hipEventQuery(r->ev_end);
+  if (q != hipSuccess && q != hipErrorNotReady) {
+    r->active = false;
+    r->reset_pending = true;
+    return hip_fail(q, "hipEventQuery");
+  }
+  *flag = 0;
+  return PCOLL_SUCCESS;
 }
 
 int pcoll_wait(pcoll_req_t r) {

@@ -200,46 +200,100 @@ struct Unroll {
   static constexpr int value = P <= 2 ? 4 : (P <= 8 ? 2 : 1);
 };
 
+// Rows of a tile.  A partition is cut into rows of 64 lanes x 16 bytes
+// (kRowElems elements); tile lt of nt takes rows base + k * stride, k =
+// 0, 1, ...: contiguous tiles take rows_per_tile consecutive rows,
+// interleaved tiles take every nt-th row, so that the wavefronts working on
+// one partition stream through it side by side.
+struct RowSet {
+  uint32_t base, stride, limit;  // rows base + k * stride, k < limit
+  __device__ __forceinline__ RowSet(uint32_t lt, uint32_t nt,
+                                    uint32_t rows_per_tile, bool inter,
+                                    uint32_t nrows) {
+    if (inter) {
+      base = lt;
+      stride = nt;
+      limit = lt < nrows ? (nrows - 1 - lt) / nt + 1 : 0;
+    } else {
+      base = lt * rows_per_tile;
+      stride = 1;
+      limit = base < nrows ? min(rows_per_tile, nrows - base) : 0;
+    }
+  }
+  __device__ __forceinline__ uint32_t row(uint32_t k) const {
+    return base + k * stride;
+  }
+};
+
+// Whether tile lt owns row q (used for the ragged end of a partition).
+__device__ __forceinline__ bool owns_row(uint32_t q, uint32_t lt, uint32_t nt,
+                                         uint32_t rows_per_tile, bool inter) {
+  return inter ? q % nt == lt : q / rows_per_tile == lt;
+}
+
 template <class Acc, int Kind>
 struct VecTile {
   static constexpr int kElemBytes = Kind == 2 ? 2 : 4;
   static constexpr int kPerVec = 16 / kElemBytes;
+  static constexpr uint32_t kRowElems = 64 * kPerVec;
 
   template <int P>
-  __device__ __forceinline__ static void run(const_ptr<BucketDesc> bd, uint64_t e0,
-                                             uint32_t n) {
+  __device__ __forceinline__ static void run(const_ptr<BucketDesc> bd,
+                                             uint64_t poff, uint64_t plen,
+                                             uint32_t lt, uint32_t nt,
+                                             uint32_t tile_elems,
+                                             uint32_t inter) {
     const uint32_t lane = lane_id();
-    const char* in[P];
+    const uint4* in[P];
 #pragma unroll
     for (int r = 0; r < P; ++r)
-      in[r] = static_cast<const char*>(bd->in[r]) + e0 * kElemBytes;
-    char* out = static_cast<char*>(bd->out) + e0 * kElemBytes;
-    const uint32_t nv = n / kPerVec;
+      in[r] = reinterpret_cast<const uint4*>(
+          static_cast<const char*>(bd->in[r]) + poff * kElemBytes);
+    uint4* out = reinterpret_cast<uint4*>(static_cast<char*>(bd->out) +
+                                          poff * kElemBytes);
+    const uint32_t nv = (uint32_t)(plen / kPerVec);  // whole vectors
+    const uint32_t full = nv / 64;                    // whole rows
+    const uint32_t rpt = tile_elems / kRowElems;
+    const RowSet rows(lt, nt, rpt, inter != 0, full);
     constexpr int U = Unroll<P>::value;
-    uint32_t v = lane;
-    for (; v + 64u * (U - 1) < nv; v += 64u * U) {
+    uint32_t k = 0;
+    for (; k + U <= rows.limit; k += U) {
       uint4 x[U][P];
 #pragma unroll
       for (int u = 0; u < U; ++u)
 #pragma unroll
         for (int r = 0; r < P; ++r)
-          x[u][r] = ld_stream(reinterpret_cast<const uint4*>(in[r]) + v +
-                              64u * u);
+          x[u][r] = ld_stream(in[r] + rows.row(k + u) * 64u + lane);
 #pragma unroll
       for (int u = 0; u < U; ++u)
-        st_stream(reinterpret_cast<uint4*>(out) + v + 64u * u,
+        st_stream(out + rows.row(k + u) * 64u + lane,
                   VecCombine<Acc, P, Kind>::run(x[u]));
     }
-    for (; v < nv; v += 64u) {
+    for (; k < rows.limit; ++k) {
+      uint4 x[P];
+      const uint32_t v = rows.row(k) * 64u + lane;
+#pragma unroll
+      for (int r = 0; r < P; ++r) x[r] = ld_stream(in[r] + v);
+      st_stream(out + v, VecCombine<Acc, P, Kind>::run(x));
+    }
+    // the partition's ragged end: a partial row and the last < 16 bytes,
+    // done by the tile that owns row `full`
+    if (!owns_row(full, lt, nt, rpt, inter != 0)) return;
+    const uint32_t v = full * 64u + lane;
+    if (v < nv) {
       uint4 x[P];
 #pragma unroll
-      for (int r = 0; r < P; ++r)
-        x[r] = ld_stream(reinterpret_cast<const uint4*>(in[r]) + v);
-      st_stream(reinterpret_cast<uint4*>(out) + v,
-                VecCombine<Acc, P, Kind>::run(x));
+      for (int r = 0; r < P; ++r) x[r] = ld_stream(in[r] + v);
+      st_stream(out + v, VecCombine<Acc, P, Kind>::run(x));
     }
-    const uint32_t tail = n - nv * kPerVec;  // < kPerVec <= 8
-    if (lane < tail) combine_scalar<Acc, P, Kind>(in, out, nv * kPerVec + lane);
+    const uint32_t tail = (uint32_t)(plen - (uint64_t)nv * kPerVec);
+    if (lane < tail) {
+      const char* inb[P];
+#pragma unroll
+      for (int r = 0; r < P; ++r) inb[r] = reinterpret_cast<const char*>(in[r]);
+      combine_scalar<Acc, P, Kind>(inb, reinterpret_cast<char*>(out),
+                                   nv * kPerVec + lane);
+    }
   }
 };
 
@@ -273,21 +327,29 @@ __device__ __forceinline__ uint4 load_codes(const uint8_t* p, uint32_t have) {
 
 template <bool COMP>
 struct E4M3Tile {
+  static constexpr uint32_t kRowElems = 1024;  // 64 lanes x 16 codes
+
   template <int P>
-  __device__ __forceinline__ static void run(const_ptr<BucketDesc> bd, uint64_t e0,
-                                             uint32_t n) {
+  __device__ __forceinline__ static void run(const_ptr<BucketDesc> bd,
+                                             uint64_t poff, uint64_t plen,
+                                             uint32_t lt, uint32_t nt,
+                                             uint32_t tile_elems,
+                                             uint32_t inter) {
     const uint32_t lane = lane_id();
     const uint8_t* in[P];
     const float* sc[P];
 #pragma unroll
     for (int r = 0; r < P; ++r) {
-      in[r] = static_cast<const uint8_t*>(bd->in[r]) + e0;
-      sc[r] = bd->in_scale[r] + e0 / 256u;
+      in[r] = static_cast<const uint8_t*>(bd->in[r]) + poff;
+      sc[r] = bd->in_scale[r] + poff / 256u;
     }
-    uint8_t* out = static_cast<uint8_t*>(bd->out) + e0;
-    float* osc = bd->out_scale + e0 / 256u;
-    for (uint32_t base = 0; base < n; base += 1024u) {
-      const uint32_t el = base + lane * 16u;
+    uint8_t* out = static_cast<uint8_t*>(bd->out) + poff;
+    float* osc = bd->out_scale + poff / 256u;
+    const uint32_t n = (uint32_t)plen;
+    const uint32_t nrows = (n + kRowElems - 1) / kRowElems;
+    const RowSet rows(lt, nt, tile_elems / kRowElems, inter != 0, nrows);
+    for (uint32_t k = 0; k < rows.limit; ++k) {
+      const uint32_t el = rows.row(k) * kRowElems + lane * 16u;
       const uint32_t blk = el / 256u;
       const uint32_t have = el < n ? (n - el < 16u ? n - el : 16u) : 0u;
       uint4 raw[P];

@@ -49,11 +49,11 @@ std::vector<TuneRow> parse_tune_table(const std::string& text) {
     auto hash = line.find('#');
     if (hash != std::string::npos) line.resize(hash);
     std::istringstream ls(line);
-    std::string f[8];
+    std::string f[9];
     int nf = 0;
-    while (nf < 8 && (ls >> f[nf])) ++nf;
+    while (nf < 9 && (ls >> f[nf])) ++nf;
     std::string extra;
-    if (nf != 8 || (ls >> extra)) continue;
+    if ((nf != 8 && nf != 9) || (ls >> extra)) continue;
     TuneRow r;
     r.dtype = parse_dtype(f[0]);
     r.op = parse_op(f[1]);
@@ -65,6 +65,9 @@ std::vector<TuneRow> parse_tune_table(const std::string& text) {
       continue;
     if (!parse_int_or_any(f[6], &r.tile_elems) ||
         !parse_int_or_any(f[7], &r.groups_per_cu))
+      continue;
+    if (nf == 9 && (!parse_int_or_any(f[8], &r.interleave) ||
+                    (r.interleave != 0 && r.interleave != 1)))
       continue;
     if (r.log2_lo < 0) r.log2_lo = 0;
     if (r.log2_hi < 0) r.log2_hi = 63;
@@ -82,11 +85,11 @@ TuneChoice tune_lookup(const std::vector<TuneRow>& rows, int dtype, int op,
   for (const auto& r : rows) {
     if (match(r.dtype, dtype) && match(r.op, op) && match(r.ranks, ranks) &&
         match(r.graph, graph) && lg >= r.log2_lo && lg <= r.log2_hi)
-      return {r.tile_elems, r.groups_per_cu};
+      return {r.tile_elems, r.groups_per_cu, r.interleave};
   }
   // built-in default: 16 KiB of output per tile, two groups per CU
   int elem = dtype == 2 ? 2 : (dtype == 3 ? 1 : 4);
-  return {16384 / elem, 2};
+  return {16384 / elem, 2, 0};
 }
 
 }  // namespace pcoll

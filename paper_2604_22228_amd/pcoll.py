@@ -35,7 +35,7 @@ class Config(C.Structure):
     _fields_ = [("tile_elems", C.c_int), ("groups", C.c_int),
                 ("groups_per_cu", C.c_int), ("comp", C.c_int),
                 ("graph", C.c_int), ("timeout_ms", C.c_int),
-                ("debug", C.c_int)]
+                ("debug", C.c_int), ("interleave", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
