@@ -132,9 +132,9 @@ def time_requests(torch, reqs, orders, stream, warmup, reps):
         e0.record(stream)
         for r in reqs:
             r.start()
-        e1.record(stream)
         for r, o in zip(reqs, orders):
             r.pready_list(o)
+        e1.record(stream)
         for r in reqs:
             r.wait()
         t1 = time.perf_counter()
@@ -329,9 +329,9 @@ def main():
     for e0, e1 in evs:
         e0.record(stream)
         req.start()
-        e1.record(stream)  # enqueued behind the kernel on its stream
         for p in order:
             req.pready(p)
+        e1.record(stream)  # enqueued behind the kernel on its stream
         req.wait()
     torch.cuda.synchronize()
     t1 = time.perf_counter()

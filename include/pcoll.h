@@ -182,8 +182,10 @@ const char *pcoll_last_error_detail(void);
 /* -------------------------------------------------------- configuration */
 
 typedef struct {
-  int tile_elems;    /* elements per tile (one wavefront's unit of work);
-                        a multiple of 1024 */
+  int tile_elems;    /* largest tile (one workgroup's unit of work), in
+                        elements; a multiple of 1024.  Tiles shrink toward
+                        the end of an epoch (guided self-scheduling) */
+  int min_tile_elems; /* smallest tile; a multiple of 1024, <= tile_elems */
   int groups;        /* workgroups of the persistent kernel (4 wavefronts
                         each); 0 = groups_per_cu x compute units */
   int groups_per_cu; /* used when groups = 0 */
@@ -194,13 +196,18 @@ typedef struct {
   int interleave;    /* tile layout: 0 = each tile is a contiguous range of
                         its partition; 1 = tile j of n takes every n-th row
                         (64 lanes x 16 bytes) starting at row j */
+  int guide;         /* guided self-scheduling divisor f (0..64): a
+                        partition queued with R rows of work left in the
+                        epoch gets tiles of about R / (f x workgroups) rows,
+                        clamped to [min_tile_elems, tile_elems]; 0 = every
+                        tile has tile_elems elements */
 } pcoll_config_t;
 
 /* Reads the request's configuration.  The defaults come from the tuned
  * table (env PCOLL_TUNE_FILE, else the table shipped next to the library),
- * then from environment overrides: PCOLL_TILE, PCOLL_GROUPS,
+ * then from environment overrides: PCOLL_TILE, PCOLL_MIN_TILE, PCOLL_GROUPS,
  * PCOLL_GROUPS_PER_CU, PCOLL_COMP, PCOLL_GRAPH, PCOLL_TIMEOUT_MS,
- * PCOLL_DEBUG, PCOLL_INTERLEAVE. */
+ * PCOLL_DEBUG, PCOLL_INTERLEAVE, PCOLL_GUIDE. */
 int pcoll_get_config(pcoll_req_t req, pcoll_config_t *cfg);
 
 /* Replaces the configuration (not while an epoch is active).  Fields out of
@@ -228,14 +235,16 @@ typedef struct {
   float last_kernel_ms;       /* device time of the last epoch's kernel,
                                  if debug timing was on, else -1 */
   int groups;                 /* workgroups of the last launch */
-  int total_tiles;            /* tiles of one epoch */
+  int reserved;
 } pcoll_stats_t;
 
 int pcoll_get_stats(pcoll_req_t req, pcoll_stats_t *st);
 
-/* Debug mode only: tiles reduced per partition in the last epoch (must equal
- * the partition's tile count: every tile exactly once). */
-int pcoll_debug_tile_hits(pcoll_req_t req, uint32_t *hits, int n);
+/* Debug mode only: per partition, the tiles reduced in the last epoch and
+ * the tile count chosen when it was queued (they must be equal: every tile
+ * exactly once). */
+int pcoll_debug_tile_hits(pcoll_req_t req, uint32_t *hits, uint32_t *tiles,
+                          int n);
 
 /* Host-only partition plan (no GPU needed): for a message of `count`
  * elements of `dtype` split into `nparts` partitions, writes the common

@@ -29,8 +29,9 @@ if ROOT not in sys.path:
 DTYPE_NAMES = {0: "i32", 1: "f32", 2: "bf16", 3: "e4m3"}
 OP_NAMES = {0: "sum", 1: "max"}
 
-TILES = (1024, 2048, 4096, 8192, 16384, 32768, 65536, 131072)
-GROUPS_PER_CU = (1, 2, 4)
+TILES = (4096, 16384, 32768, 65536, 131072, 262144)
+GROUPS_PER_CU = (1, 2)
+INTERLEAVE = (1, 0)
 
 
 def default_keys():
@@ -46,11 +47,12 @@ def default_keys():
 
 
 def time_config(pc, torch, synth, dtype, op, ranks, graph, counts, nparts,
-                tile, gpc, warmup, reps, bufs):
+                tile, gpc, inter, warmup, reps, bufs):
     req = pc.Request(counts, dtype, op, nparts, ranks,
                      batched=len(counts) > 1)
-    req.set_config(tile_elems=tile, groups_per_cu=gpc, graph=graph,
-                   groups=0)
+    req.set_config(tile_elems=tile, min_tile_elems=min(tile, 4096),
+                   groups_per_cu=gpc, graph=graph, groups=0,
+                   interleave=inter, guide=0)
     ins, outs, rsc, osc, stream = bufs
     req.bind(ins, outs, rsc, osc, stream=stream)
     order = [int(p) for p in synth.permutation(req.nparts_total, 1)]
@@ -60,8 +62,8 @@ def time_config(pc, torch, synth, dtype, op, ranks, graph, counts, nparts,
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         req.start()
-        e1.record(stream)
         req.pready_list(order)
+        e1.record(stream)
         req.wait()
         if it >= warmup:
             e1.synchronize()
@@ -110,7 +112,7 @@ def make_buffers(pc, torch, synth, dtype, ranks, counts):
     return ins, outs, rsc, osc, torch.cuda.Stream(dev)
 
 
-def tune(keys, tiles, gpcs, warmup, reps, log=print):
+def tune(keys, tiles, gpcs, warmup, reps, log=print, inters=INTERLEAVE):
     import torch
 
     from paper_2604_22228_amd import pcoll as pc
@@ -124,18 +126,20 @@ def tune(keys, tiles, gpcs, warmup, reps, log=print):
         best = None
         for tile in tiles:
             for gpc in gpcs:
-                ms = time_config(pc, torch, synth, dtype, op, ranks, graph,
-                                 counts, nparts, tile, gpc, warmup, reps,
-                                 bufs)
-                log(json.dumps({"dtype": DTYPE_NAMES[dtype],
-                                "op": OP_NAMES[op], "ranks": ranks,
-                                "graph": graph, "log2_bytes": lg,
-                                "tile": tile, "gpc": gpc,
-                                "ms": round(ms, 5)}))
-                if best is None or ms < best[0]:
-                    best = (ms, tile, gpc)
+                for inter in inters:
+                    ms = time_config(pc, torch, synth, dtype, op, ranks,
+                                     graph, counts, nparts, tile, gpc, inter,
+                                     warmup, reps, bufs)
+                    log(json.dumps({"dtype": DTYPE_NAMES[dtype],
+                                    "op": OP_NAMES[op], "ranks": ranks,
+                                    "graph": graph, "log2_bytes": lg,
+                                    "tile": tile, "gpc": gpc,
+                                    "interleave": inter,
+                                    "ms": round(ms, 5)}))
+                    if best is None or ms < best[0]:
+                        best = (ms, tile, gpc, inter)
         rows.append((DTYPE_NAMES[dtype], OP_NAMES[op], ranks, graph, lg, lg,
-                     best[1], best[2], best[0]))
+                     best[1], best[2], best[3], best[0]))
         del bufs
         torch.cuda.empty_cache()
     return rows
@@ -145,9 +149,10 @@ def write_table(rows, path):
     lines = ["# Tuned launch parameters of libpcoll on MI355X (gfx950), "
              "written by paper_2604_22228_amd/autotune.py.",
              "# dtype op ranks graph log2_lo log2_hi tile_elems "
-             "groups_per_cu   # median kernel ms"]
-    for d, o, r, g, lo, hi, t, gpc, ms in rows:
-        lines.append(f"{d} {o} {r} {g} {lo} {hi} {t} {gpc}   # {ms:.4f}")
+             "groups_per_cu interleave   # median kernel ms"]
+    for d, o, r, g, lo, hi, t, gpc, il, ms in rows:
+        lines.append(f"{d} {o} {r} {g} {lo} {hi} {t} {gpc} {il}   # {ms:.4f}")
+    lines.append("* * * * 0 63 131072 1 1   # fallback")
     with open(path, "w") as f:
         f.write("\n".join(lines) + "\n")
 
@@ -164,7 +169,7 @@ def main():
     keys = default_keys()
     tiles, gpcs = TILES, GROUPS_PER_CU
     if args.quick:
-        keys, tiles, gpcs = keys[:2], (4096, 65536), (1, 2)
+        keys, tiles, gpcs = keys[-4:-2], (16384, 131072), (1,)
     rows = tune(keys, tiles, gpcs, args.warmup, args.reps,
                 log=lambda s: print(s, flush=True))
     write_table(rows, args.out)

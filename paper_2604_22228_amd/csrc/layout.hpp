@@ -5,11 +5,12 @@
 // contributions each.  Bucket b is split into nparts partitions by the chunk
 // rule of Algorithm 1 (Section 4.3): equal lengths fixed in advance, running
 // offsets, the last one clipped.  Global partition g = b * nparts + k.  A
-// partition is further cut into tiles of about `tile_elems` elements; a tile
-// is the unit one wavefront reduces.  A partition is a sequence of rows (one
-// row = 64 lanes x 16 bytes per rank); a tile is a set of rows, either
-// consecutive or interleaved with the partition's other tiles.  Destination regions of partitions and tiles
-// are disjoint (Section 4.5, Ordering Guarantee), so each is written once.
+// partition is a sequence of rows (one row = 64 lanes x 16 bytes per rank)
+// and is cut into tiles, the unit one workgroup reduces: a tile is a set of
+// rows, consecutive or interleaved with the partition's other tiles, and
+// the number of tiles is chosen when the partition is queued.  Destination
+// regions of partitions and tiles are disjoint (Section 4.5, Ordering
+// Guarantee), so each is written once.
 #pragma once
 #include <stdint.h>
 
@@ -33,12 +34,14 @@ struct PartDesc {
   uint64_t off;     // first element, relative to the bucket start
   uint64_t len;     // elements (0 for empty partitions)
   uint32_t bucket;  // owning bucket
-  uint32_t ntiles;  // max(1, ceil(len / tile_elems)); empty parts get one
+  uint32_t rows;    // ceil(len / row_elems): rows of 64 lanes x 16 bytes
   uint64_t reserved;
 };
 
 // One entry of the device work queue: partitions in the order they were
-// found ready, with the running total of their tiles.
+// found ready, with the running total of their tiles (a partition's tile
+// count is the difference of consecutive totals; it is chosen when the
+// partition is queued, see persistent.hpp).
 struct QEntry {
   uint32_t part;
   uint32_t cum_end;  // tiles of all entries up to and including this one
@@ -71,7 +74,8 @@ struct DevCounters {
   uint32_t ilock;                 // ingest lock (0 free, 1 held)
   uint32_t hconsumed;             // host ready entries already queued
   uint64_t dconsumed;             // device ready entries already queued
-  uint32_t pad2[28];
+  uint64_t queued_rows;           // rows of the partitions queued so far
+  uint32_t pad2[26];
   uint32_t error;                 // first error seen this epoch
   uint32_t epoch;                 // epoch of the running launch
   uint32_t pad3[30];
@@ -101,12 +105,16 @@ struct ReduceArgs {
   const uint32_t* hlist;  // device-visible host ready list
   uint32_t* arrived;      // device-visible arrived stamps
   uint32_t nparts_total;
-  uint32_t total_tiles;
-  uint32_t tile_elems;
-  uint32_t total_waves;
-  uint32_t interleave;    // 0: tile = contiguous rows; 1: tile j of nt takes
-                          // rows j, j + nt, j + 2 nt, ... of its partition
-  uint32_t reserved;
+  uint32_t total_groups;   // workgroups of the launch
+  uint64_t total_rows;     // rows of all partitions
+  uint32_t row_elems;      // elements per row (1024 bytes per rank)
+  uint32_t min_tile_rows;  // bounds of the rows per tile chosen at queueing
+  uint32_t max_tile_rows;
+  uint32_t interleave;     // 0: tile = consecutive rows; 1: tile j of nt
+                           // takes rows j, j + nt, j + 2 nt, ... of its
+                           // partition
+  uint32_t* tile_counts;   // [nparts_total] debug: tiles chosen, or null
+  uint32_t guide;          // guided-scheduling divisor f (0 = fixed tiles)
   uint64_t timeout_ticks; // device wall-clock ticks before giving up
 };
 

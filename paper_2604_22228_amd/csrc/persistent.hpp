@@ -5,12 +5,17 @@
 // the epoch's counters, so no wavefront of the reduce kernel ever has to
 // find out that it is the last one.  Every wavefront is an independent
 // worker; none ever waits for another, so the launch needs no co-residency
-// and drains even if it is larger than the machine.  A worker loops:
+// and drains even if it is larger than the machine.  The worker is a
+// workgroup of kWavesPerGroup wavefronts that reduce the rows of one tile
+// together (wavefront w takes every kWavesPerGroup-th row), so one claim
+// and one release serve four wavefronts.  Wavefront 0 of the group drives
+// the protocol; the group meets at a barrier before and after each tile.
+// A worker loops:
 //
-//   1. take a global tile index t: its wavefront number the first time
-//      (no atomic, so the launch does not start with a burst of atomics on
-//      one address), then one atomic add per tile, issued before the
-//      current tile is reduced so that its latency hides behind the tile;
+//   1. take a global tile index t: its workgroup number the first time (no
+//      atomic, so the launch does not start with a burst of atomics on one
+//      address), then one atomic add per tile, issued before the current
+//      tile is reduced so that its latency hides behind the tile;
 //   2. wait until t is covered by the work queue.  While starved, the few
 //      workers at the front of the claim order try to move newly readied
 //      partitions into the queue: under a try-lock, read the host ready
@@ -102,12 +107,22 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
 
 // ------------------------------------------------------------- the queue
 
-// Appends the partitions held by the lanes with `valid` set.  Caller holds
-// the ingest lock; qcount / qtiles are wave-uniform and updated in place.
+// Appends the partitions held by the lanes with `valid` set, in lane order.
+// Caller holds the ingest lock; qcount / qtiles / qrows are wave-uniform and
+// updated in place.
+//
+// Tile count (guided self-scheduling, when `guide` f > 0): a partition
+// whose first row has `rem` rows of the request from it to the end (itself
+// included, partitions not yet queued counted too) is cut into tiles of
+// about s = clamp(ceil(rem / (f G)), min_tile_rows, max_tile_rows) rows, G
+// the workgroups of the launch: large tiles while much work remains, small
+// ones near the end, so that workgroups run out of work at about the same
+// time.  With f = 0 every tile has max_tile_rows rows.
 __device__ __forceinline__ void queue_append(const ReduceArgs& a,
                                              uint32_t epoch, bool valid,
                                              uint32_t part, uint32_t& qcount,
-                                             uint32_t& qtiles) {
+                                             uint32_t& qtiles,
+                                             uint64_t& qrows) {
   const uint32_t lane = lane_id();
   valid = valid && part < a.nparts_total;
   if (valid) {
@@ -117,17 +132,31 @@ __device__ __forceinline__ void queue_append(const ReduceArgs& a,
                                          __HIP_MEMORY_SCOPE_AGENT);
     valid = old != epoch;
   }
-  uint32_t nt = valid ? a.parts[part].ntiles : 0u;
-  uint32_t incl = wave_incl_scan(nt);
-  uint64_t vm = __ballot(valid);
-  uint32_t rank = __popcll(vm & ((1ull << lane) - 1ull));
-  uint32_t slot = qcount + rank;
+  const uint32_t rows = valid ? a.parts[part].rows : 0u;
+  const uint32_t rincl = wave_incl_scan(rows);
+  const uint64_t before = qrows + (rincl - rows);
+  const uint64_t rem = a.total_rows > before ? a.total_rows - before : rows;
+  uint64_t s = a.max_tile_rows;
+  if (a.guide) {
+    const uint64_t g = (uint64_t)a.guide * a.total_groups;
+    s = (rem + g - 1) / g;
+    if (s < a.min_tile_rows) s = a.min_tile_rows;
+    if (s > a.max_tile_rows) s = a.max_tile_rows;
+  }
+  const uint32_t nt =
+      valid ? (rows == 0u ? 1u : (uint32_t)((rows + s - 1) / s)) : 0u;
+  const uint32_t incl = wave_incl_scan(nt);
+  const uint64_t vm = __ballot(valid);
+  const uint32_t rank = __popcll(vm & ((1ull << lane) - 1ull));
+  const uint32_t slot = qcount + rank;
   if (valid && slot < a.nparts_total) {
-    uint64_t e = ((uint64_t)(qtiles + incl) << 32) | part;
+    const uint64_t e = ((uint64_t)(qtiles + incl) << 32) | part;
     st_rlx64(reinterpret_cast<uint64_t*>(&a.queue[slot]), e);
+    if (a.tile_counts) a.tile_counts[part] = nt;
   }
   qcount += (uint32_t)__popcll(vm);
   qtiles += uni(__shfl(incl, 63));
+  qrows += uni(__shfl(rincl, 63));
 }
 
 // Moves newly readied partitions into the queue.  Returns true if it queued
@@ -151,6 +180,7 @@ __device__ __forceinline__ bool try_ingest(const ReduceArgs& a, uint32_t epoch) 
   uint64_t dr = uni64(ld_acq64(&c->dreserve));
   uint64_t qs = uni64(ld_rlx64(&c->qstate));
   uint32_t qcount = (uint32_t)(qs >> 32), qtiles = (uint32_t)qs;
+  uint64_t qrows = uni64(ld_rlx64(&c->queued_rows));
   const uint32_t qtiles0 = qtiles;
   if (hc > a.nparts_total) hc = a.nparts_total;
   if (hc <= hcons && dr <= dcons) {
@@ -163,7 +193,7 @@ __device__ __forceinline__ bool try_ingest(const ReduceArgs& a, uint32_t epoch) 
     uint32_t i = base + lane;
     bool in = i < hc;
     uint32_t p = in ? ld_rlx_sys(&a.hlist[i]) : 0u;
-    queue_append(a, epoch, in, p, qcount, qtiles);
+    queue_append(a, epoch, in, p, qcount, qtiles, qrows);
   }
   hcons = hc > hcons ? hc : hcons;
 
@@ -178,7 +208,8 @@ __device__ __forceinline__ bool try_ingest(const ReduceArgs& a, uint32_t epoch) 
     const uint64_t pending = __ballot(in && !ok);
     const uint32_t lim =
         pending ? (uint32_t)(__ffsll((long long)pending) - 1) : 64u;
-    queue_append(a, epoch, ok && lane < lim, (uint32_t)v, qcount, qtiles);
+    queue_append(a, epoch, ok && lane < lim, (uint32_t)v, qcount, qtiles,
+                 qrows);
     const uint64_t avail = dr - dcons < 64u ? dr - dcons : 64u;
     dcons += lim < avail ? lim : avail;
     if (pending) break;
@@ -186,6 +217,7 @@ __device__ __forceinline__ bool try_ingest(const ReduceArgs& a, uint32_t epoch) 
 
   st_rlx(&c->hconsumed, hcons);
   st_rlx64(&c->dconsumed, dcons);
+  st_rlx64(&c->queued_rows, qrows);
   st_rel64(&c->qstate, ((uint64_t)qcount << 32) | qtiles);
   if (lane == 0) st_rel(&c->ilock, 0u);
   return qtiles != qtiles0;
@@ -208,29 +240,40 @@ __device__ __forceinline__ void set_error(const ReduceArgs& a, uint32_t code,
   }
 }
 
-// Waits until tile t is queued.  Returns the queue state, or 0 if the
-// worker must give up (deadline, host abort, or another worker's error).
-// Only the few workers at the front of the claim order (t within 8 tiles of
-// the queued total) poll the ready lists and the host's abort word; the rest
-// re-read the device-side queue state at a slower pace.
-__device__ __forceinline__ uint64_t wait_queued(const ReduceArgs& a,
-                                                uint32_t t, uint32_t epoch,
-                                                uint64_t t0) {
+enum WaitResult { kBail, kStop, kReady };
+
+// Waits until tile t is queued (kReady, with the queue state in qs_out).
+// kStop: every partition is queued and t is beyond the last tile.  kBail:
+// give up (deadline, host abort, or another worker's error).  Only the few
+// workers at the front of the claim order (t within 8 tiles of the queued
+// total) poll the ready lists and the host's abort word; the rest re-read
+// the device-side queue state at a slower pace.
+__device__ __forceinline__ WaitResult wait_queued(const ReduceArgs& a,
+                                                  uint32_t t, uint32_t epoch,
+                                                  uint64_t t0,
+                                                  uint64_t& qs_out) {
+  // the queue state this worker acquired last: entries it covers are
+  // already visible, so a tile inside it needs no new acquire
+  if ((uint32_t)qs_out > t) return kReady;
   for (uint32_t spins = 0;; ++spins) {
-    uint64_t qs = uni64(ld_acq64(&a.ctr->qstate));
+    const uint64_t qs = uni64(ld_acq64(&a.ctr->qstate));
     const uint32_t qt = (uint32_t)qs;
-    if (qt > t) return qs;
+    if (qt > t) {
+      qs_out = qs;
+      return kReady;
+    }
+    if ((uint32_t)(qs >> 32) >= a.nparts_total) return kStop;
     const bool front = t - qt < 8u;
     if (front && try_ingest(a, epoch)) continue;
-    if (uni(ld_rlx(&a.ctr->error)) != 0u) return 0;
+    if (uni(ld_rlx(&a.ctr->error)) != 0u) return kBail;
     if ((spins & 7u) == 7u) {
       if (front && uni(ld_acq_sys(&a.host->abort)) == epoch) {
         set_error(a, kStatusAborted, epoch);
-        return 0;
+        return kBail;
       }
       if (wall_clock64() - t0 > a.timeout_ticks) {
         set_error(a, kStatusTimeout, epoch);
-        return 0;
+        return kBail;
       }
     }
     if (front)
@@ -245,7 +288,8 @@ __device__ __forceinline__ uint64_t wait_queued(const ReduceArgs& a,
 // worker's claims increase.
 __device__ __forceinline__ void locate(const ReduceArgs& a, uint32_t t,
                                        uint32_t qcount, uint32_t& cursor,
-                                       uint32_t& prev_end, uint32_t& part) {
+                                       uint32_t& prev_end, uint32_t& part,
+                                       uint32_t& end) {
   const uint32_t lane = lane_id();
   for (;;) {
     uint32_t i = cursor + lane;
@@ -260,6 +304,7 @@ __device__ __forceinline__ void locate(const ReduceArgs& a, uint32_t t,
       if (k != 0) prev_end = before;
       cursor += k;
       part = uni(__shfl((uint32_t)e, k));
+      end = uni(__shfl(ce, k));
       return;
     }
     prev_end = uni(__shfl(ce, 63));
@@ -267,13 +312,14 @@ __device__ __forceinline__ void locate(const ReduceArgs& a, uint32_t t,
   }
 }
 
-// Publishes one finished tile of `part`: one release add on the
-// partition's done counter (the release covers this wavefront's stores);
-// the wavefront whose add completes the partition acquires the other
-// wavefronts' tiles and stores the epoch into the host-visible arrived flag.
+// Publishes one finished tile of `part` (called by wavefront 0 after the
+// group's barrier): one release add on the partition's done counter (the
+// release covers the group's stores: every wavefront waited for its own
+// stores before the barrier, and the release writes back the L2 they sit
+// in); the worker whose add completes the partition acquires the other
+// workers' tiles and stores the epoch into the host-visible arrived flag.
 __device__ __forceinline__ void finish_tile(const ReduceArgs& a, uint32_t part,
                                             uint32_t ntiles, uint32_t epoch) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   if (lane_id() == 0) {
     if (a.tile_hits)
       __hip_atomic_fetch_add(&a.tile_hits[part], 1u, __ATOMIC_RELAXED,
@@ -295,37 +341,60 @@ __device__ __forceinline__ uint32_t claim(const ReduceArgs& a) {
   if (lane_id() == 0)
     t = __hip_atomic_fetch_add(&a.ctr->claim, 1u, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT) +
-        a.total_waves;
+        a.total_groups;
   return t;  // valid in lane 0; broadcast by the caller when needed
 }
 
-// The worker loop.  Tile::run<P>(bucket, partition offset, partition length,
-// tile index, tiles of the partition, tile_elems, interleave) reduces one
-// tile with the whole wavefront.
+// What wavefront 0 hands the group for one tile.
+struct TileJob {
+  uint32_t part;  // global partition, or ~0u to stop
+  uint32_t lt;    // tile index within the partition
+  uint32_t nt;    // tiles of the partition
+};
+
+// The worker loop of one workgroup.  Tile::run<P>(bucket, partition offset,
+// partition length, tile index, tiles of the partition, interleave,
+// wavefront, wavefronts) reduces this wavefront's rows of a tile.
 template <class Tile, int P>
 __device__ __forceinline__ void persistent_loop(const ReduceArgs& a) {
+  __shared__ TileJob job;
+  const uint32_t wave = threadIdx.x / 64u;
+  const uint32_t nwaves = blockDim.x / 64u;
   const uint32_t epoch = uni(ld_acq(&a.ctr->epoch));
   const uint64_t t0 = wall_clock64();
   uint32_t cursor = 0, prev_end = 0;
-  // first round: tile = global wavefront number
-  uint32_t t = uni((blockIdx.x * blockDim.x + threadIdx.x) / 64u);
-  while (t < a.total_tiles) {
-    uint64_t qs = wait_queued(a, t, epoch, t0);
-    if (qs == 0) break;
-    uint32_t part;
-    locate(a, t, (uint32_t)(qs >> 32), cursor, prev_end, part);
+  uint32_t t = blockIdx.x;  // first round: tile = workgroup number
+  uint32_t next = 0;
+  uint64_t qs = 0;          // queue state last acquired (wavefront 0)
+  for (;;) {
+    if (wave == 0) {
+      TileJob j{~0u, 0u, 0u};
+      if (wait_queued(a, t, epoch, t0, qs) == kReady) {
+        uint32_t end = 0;
+        locate(a, t, (uint32_t)(qs >> 32), cursor, prev_end, j.part, end);
+        j.lt = t - prev_end;
+        j.nt = end - prev_end;
+        next = claim(a);  // in flight while the tile is reduced
+      }
+      if (lane_id() == 0) job = j;
+    }
+    __syncthreads();
+    const TileJob j = job;
+    if (j.part == ~0u) break;
     // descriptor tables are read-only for the whole launch: scalar loads
-    const const_ptr<PartDesc> pd = (const_ptr<PartDesc>)(a.parts) + part;
+    const const_ptr<PartDesc> pd = (const_ptr<PartDesc>)(a.parts) + j.part;
     const uint64_t poff = pd->off, plen = pd->len;
-    const uint32_t pnt = pd->ntiles;
     const const_ptr<BucketDesc> bd =
         (const_ptr<BucketDesc>)(a.buckets) + pd->bucket;
-    const uint32_t lt = t - prev_end;
-    uint32_t next = claim(a);  // in flight while the tile is reduced
-    Tile::template run<P>(bd, poff, plen, lt, pnt, a.tile_elems,
-                          a.interleave);
-    finish_tile(a, part, pnt, epoch);
-    t = uni(next);
+    Tile::template run<P>(bd, poff, plen, j.lt, j.nt, a.interleave, wave,
+                          nwaves);
+    // every wavefront's stores have completed before the group's release
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (wave == 0) {
+      finish_tile(a, j.part, j.nt, epoch);
+      t = uni(next);
+    }
   }
 }
 
@@ -338,6 +407,7 @@ __device__ __forceinline__ void reset_epoch(const ResetArgs& a) {
     st_rlx64(&c->qstate, 0ull);
     st_rlx(&c->ilock, 0u);
     st_rlx(&c->hconsumed, 0u);
+    st_rlx64(&c->queued_rows, 0ull);
     st_rlx(&c->error, 0u);
     st_rlx(&c->epoch, ld_acq_sys(&a.host->epoch));
   }

@@ -134,7 +134,7 @@ struct pcoll_req_s {
   uint32_t nparts_total = 0;
   std::vector<PartDesc> parts;
   pcoll_config_t cfg{};
-  uint32_t total_tiles = 0;
+  uint64_t total_rows = 0;
   int groups = 0;
   int cus = 0;
   int clock_khz = 0;
@@ -150,6 +150,7 @@ struct pcoll_req_s {
   uint32_t* d_done = nullptr;
   uint32_t* d_queued = nullptr;
   uint32_t* d_hits = nullptr;
+  uint32_t* d_tiles = nullptr;
   uint64_t* d_dlist = nullptr;
   DevCounters* d_ctr = nullptr;
 
@@ -189,10 +190,11 @@ void dispose_binding(Binding& b) {
 
 uint64_t launch_signature(const pcoll_req_s* r) {
   uint64_t h = 1469598103934665603ull;
-  const uint64_t v[] = {(uint64_t)r->cfg.tile_elems, (uint64_t)r->groups,
+  const uint64_t v[] = {(uint64_t)r->cfg.tile_elems,
+                        (uint64_t)r->cfg.min_tile_elems, (uint64_t)r->groups,
                         (uint64_t)r->cfg.comp, (uint64_t)r->cfg.debug,
-                        (uint64_t)r->cfg.timeout_ms, r->total_tiles,
-                        (uint64_t)r->cfg.interleave};
+                        (uint64_t)r->cfg.timeout_ms, r->total_rows,
+                        (uint64_t)r->cfg.interleave, (uint64_t)r->cfg.guide};
   for (uint64_t x : v) {
     h ^= x;
     h *= 1099511628211ull;
@@ -204,6 +206,9 @@ int validate_config(const pcoll_req_s* r, const pcoll_config_t& c) {
   if (c.tile_elems < 1024 || c.tile_elems % 1024 != 0 ||
       c.tile_elems > (1 << 26))
     return PCOLL_ERR_ARG;
+  if (c.min_tile_elems < 1024 || c.min_tile_elems % 1024 != 0 ||
+      c.min_tile_elems > c.tile_elems)
+    return PCOLL_ERR_ARG;
   if (c.groups < 0 || c.groups > (1 << 20)) return PCOLL_ERR_ARG;
   if (c.groups == 0 && (c.groups_per_cu < 1 || c.groups_per_cu > 64))
     return PCOLL_ERR_ARG;
@@ -214,31 +219,22 @@ int validate_config(const pcoll_req_s* r, const pcoll_config_t& c) {
   if (c.timeout_ms < 1 || c.timeout_ms > 3600 * 1000) return PCOLL_ERR_ARG;
   if (c.debug != 0 && c.debug != 1) return PCOLL_ERR_ARG;
   if (c.interleave != 0 && c.interleave != 1) return PCOLL_ERR_ARG;
+  if (c.guide < 0 || c.guide > 64) return PCOLL_ERR_ARG;
   return PCOLL_SUCCESS;
 }
 
-// Recomputes tiles for the configuration and uploads the partition table.
+// Elements per row: 64 lanes x 16 bytes per rank.
+uint64_t row_elems(int dtype) { return 1024u / (uint64_t)elem_bytes(dtype); }
+
+// Applies a configuration: workgroups and the signature of the launch.
 int apply_config(pcoll_req_t r, const pcoll_config_t& c) {
   int rc = validate_config(r, c);
   if (rc) return rc;
-  uint64_t total = 0;
-  std::vector<PartDesc> parts = r->parts;
-  for (auto& p : parts) {
-    uint64_t nt = (p.len + (uint64_t)c.tile_elems - 1) / (uint64_t)c.tile_elems;
-    p.ntiles = (uint32_t)(nt ? nt : 1);
-    total += p.ntiles;
-  }
-  if (total >= (1ull << 31)) return PCOLL_ERR_UNSUPPORTED;
   int groups = c.groups ? c.groups : c.groups_per_cu * r->cus;
   if (groups < 1) groups = 1;
   rc = drain(r);
   if (rc) return rc;
-  HIP_TRY(hipSetDevice(r->device));
-  HIP_TRY(hipMemcpy(r->d_parts, parts.data(), parts.size() * sizeof(PartDesc),
-                    hipMemcpyHostToDevice));
-  r->parts = std::move(parts);
   r->cfg = c;
-  r->total_tiles = (uint32_t)total;
   r->groups = groups;
   r->sig = launch_signature(r);
   if (r->cache)  // graphs captured with the old arguments are stale
@@ -257,7 +253,10 @@ pcoll_config_t default_config(const pcoll_req_s* r) {
   TuneChoice t = tune_lookup(tune_rows(), r->dtype, r->op, r->nranks, c.graph,
                              bytes);
   c.tile_elems = env_int("PCOLL_TILE", t.tile_elems);
+  c.min_tile_elems = env_int("PCOLL_MIN_TILE", 4096);
+  if (c.min_tile_elems > c.tile_elems) c.min_tile_elems = c.tile_elems;
   c.interleave = env_int("PCOLL_INTERLEAVE", t.interleave) ? 1 : 0;
+  c.guide = env_int("PCOLL_GUIDE", 0);
   c.groups = env_int("PCOLL_GROUPS", 0);
   c.groups_per_cu = env_int("PCOLL_GROUPS_PER_CU", t.groups_per_cu);
   const bool float_sum = r->op == PCOLL_SUM && r->dtype != PCOLL_INT32;
@@ -317,7 +316,8 @@ int create(const std::vector<uint64_t>& counts, int dtype, int op,
       p.off = off;
       p.len = std::min<uint64_t>(ps, counts[b] - off);
       p.bucket = (uint32_t)b;
-      p.ntiles = 1;
+      p.rows = (uint32_t)((p.len + row_elems(dtype) - 1) / row_elems(dtype));
+      r->total_rows += p.rows;
       r->parts.push_back(p);
     }
   }
@@ -357,6 +357,7 @@ int create(const std::vector<uint64_t>& counts, int dtype, int op,
   const size_t o_done = take(sizeof(uint32_t) * np_total);
   const size_t o_queued = take(sizeof(uint32_t) * np_total);
   const size_t o_hits = take(sizeof(uint32_t) * np_total);
+  const size_t o_tiles = take(sizeof(uint32_t) * np_total);
   const size_t o_dlist = take(sizeof(uint64_t) * np_total);
   const size_t o_ctr = take(sizeof(DevCounters));
   e = hipMalloc(&r->arena, off);
@@ -372,6 +373,10 @@ int create(const std::vector<uint64_t>& counts, int dtype, int op,
   r->d_done = reinterpret_cast<uint32_t*>(base + o_done);
   r->d_queued = reinterpret_cast<uint32_t*>(base + o_queued);
   r->d_hits = reinterpret_cast<uint32_t*>(base + o_hits);
+  r->d_tiles = reinterpret_cast<uint32_t*>(base + o_tiles);
+  HIP_TRY(hipMemcpy(r->d_parts, r->parts.data(),
+                    sizeof(PartDesc) * r->parts.size(),
+                    hipMemcpyHostToDevice));
   r->d_dlist = reinterpret_cast<uint64_t*>(base + o_dlist);
   r->d_ctr = reinterpret_cast<DevCounters*>(base + o_ctr);
 
@@ -403,10 +408,16 @@ ReduceArgs make_args(const pcoll_req_s* r) {
   a.hlist = reinterpret_cast<const uint32_t*>(r->host_dev + 1);
   a.arrived = const_cast<uint32_t*>(a.hlist) + r->nparts_total;
   a.nparts_total = r->nparts_total;
-  a.total_tiles = r->total_tiles;
-  a.tile_elems = (uint32_t)r->cfg.tile_elems;
-  a.total_waves = (uint32_t)r->groups * kWavesPerGroup;
+  a.total_groups = (uint32_t)r->groups;
+  a.total_rows = r->total_rows;
+  a.row_elems = (uint32_t)row_elems(r->dtype);
+  a.min_tile_rows = (uint32_t)std::max<uint64_t>(
+      1, (uint64_t)r->cfg.min_tile_elems / row_elems(r->dtype));
+  a.max_tile_rows = (uint32_t)std::max<uint64_t>(
+      1, (uint64_t)r->cfg.tile_elems / row_elems(r->dtype));
   a.interleave = (uint32_t)r->cfg.interleave;
+  a.tile_counts = r->cfg.debug ? r->d_tiles : nullptr;
+  a.guide = (uint32_t)r->cfg.guide;
   a.timeout_ticks = (uint64_t)r->cfg.timeout_ms * (uint64_t)r->clock_khz;
   return a;
 }
@@ -694,6 +705,8 @@ int pcoll_start(pcoll_req_t r) {
   if (r->cfg.debug) {
     HIP_TRY(hipMemsetAsync(r->d_hits, 0, sizeof(uint32_t) * r->nparts_total,
                            r->stream));
+    HIP_TRY(hipMemsetAsync(r->d_tiles, 0, sizeof(uint32_t) * r->nparts_total,
+                           r->stream));
     HIP_TRY(hipEventRecord(r->ev_start, r->stream));
     r->ev_start_recorded = true;
   }
@@ -706,7 +719,6 @@ int pcoll_start(pcoll_req_t r) {
   r->reset_pending = false;
   r->stats.epochs++;
   r->stats.groups = r->groups;
-  r->stats.total_tiles = (int)r->total_tiles;
   return PCOLL_SUCCESS;
 }
 
@@ -872,13 +884,17 @@ int pcoll_get_stats(pcoll_req_t r, pcoll_stats_t* st) {
   return PCOLL_SUCCESS;
 }
 
-int pcoll_debug_tile_hits(pcoll_req_t r, uint32_t* hits, int n) {
-  if (check_req(r) || !hits || n < (int)r->nparts_total) return PCOLL_ERR_ARG;
+int pcoll_debug_tile_hits(pcoll_req_t r, uint32_t* hits, uint32_t* tiles,
+                          int n) {
+  if (check_req(r) || !hits || !tiles || n < (int)r->nparts_total)
+    return PCOLL_ERR_ARG;
   if (!r->cfg.debug || r->active) return PCOLL_ERR_STATE;
   HIP_TRY(hipSetDevice(r->device));
   int rc = drain(r);
   if (rc) return rc;
   HIP_TRY(hipMemcpy(hits, r->d_hits, sizeof(uint32_t) * r->nparts_total,
+                    hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(tiles, r->d_tiles, sizeof(uint32_t) * r->nparts_total,
                     hipMemcpyDeviceToHost));
   return PCOLL_SUCCESS;
 }

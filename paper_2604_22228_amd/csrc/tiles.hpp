@@ -202,11 +202,13 @@ struct Unroll {
 
 // Rows of a tile.  A partition is cut into rows of 64 lanes x 16 bytes
 // (kRowElems elements); tile lt of nt takes rows base + k * stride, k =
-// 0, 1, ...: contiguous tiles take rows_per_tile consecutive rows,
-// interleaved tiles take every nt-th row, so that the wavefronts working on
+// 0, 1, ...: consecutive tiles take ceil(rows / nt) consecutive rows,
+// interleaved tiles take every nt-th row, so that the workgroups working on
 // one partition stream through it side by side.
 struct RowSet {
   uint32_t base, stride, limit;  // rows base + k * stride, k < limit
+  // nrows: rows this set may use (whole rows); rows_per_tile: ceil(all rows
+  // of the partition / nt) for the consecutive layout
   __device__ __forceinline__ RowSet(uint32_t lt, uint32_t nt,
                                     uint32_t rows_per_tile, bool inter,
                                     uint32_t nrows) {
@@ -237,12 +239,15 @@ struct VecTile {
   static constexpr int kPerVec = 16 / kElemBytes;
   static constexpr uint32_t kRowElems = 64 * kPerVec;
 
+  // Reduces wavefront `wave`'s rows of the tile: rows k = wave, wave +
+  // nwaves, ... of the tile's row set; wavefront 0 also does the
+  // partition's ragged end if this tile owns it.
   template <int P>
   __device__ __forceinline__ static void run(const_ptr<BucketDesc> bd,
                                              uint64_t poff, uint64_t plen,
                                              uint32_t lt, uint32_t nt,
-                                             uint32_t tile_elems,
-                                             uint32_t inter) {
+                                             uint32_t inter, uint32_t wave,
+                                             uint32_t nwaves) {
     const uint32_t lane = lane_id();
     const uint4* in[P];
 #pragma unroll
@@ -253,23 +258,24 @@ struct VecTile {
                                           poff * kElemBytes);
     const uint32_t nv = (uint32_t)(plen / kPerVec);  // whole vectors
     const uint32_t full = nv / 64;                    // whole rows
-    const uint32_t rpt = tile_elems / kRowElems;
+    const uint32_t all = (uint32_t)((plen + kRowElems - 1) / kRowElems);
+    const uint32_t rpt = (all + nt - 1) / nt;
     const RowSet rows(lt, nt, rpt, inter != 0, full);
     constexpr int U = Unroll<P>::value;
-    uint32_t k = 0;
-    for (; k + U <= rows.limit; k += U) {
+    uint32_t k = wave;
+    for (; k + (U - 1) * nwaves < rows.limit; k += U * nwaves) {
       uint4 x[U][P];
 #pragma unroll
       for (int u = 0; u < U; ++u)
 #pragma unroll
         for (int r = 0; r < P; ++r)
-          x[u][r] = ld_stream(in[r] + rows.row(k + u) * 64u + lane);
+          x[u][r] = ld_stream(in[r] + rows.row(k + u * nwaves) * 64u + lane);
 #pragma unroll
       for (int u = 0; u < U; ++u)
-        st_stream(out + rows.row(k + u) * 64u + lane,
+        st_stream(out + rows.row(k + u * nwaves) * 64u + lane,
                   VecCombine<Acc, P, Kind>::run(x[u]));
     }
-    for (; k < rows.limit; ++k) {
+    for (; k < rows.limit; k += nwaves) {
       uint4 x[P];
       const uint32_t v = rows.row(k) * 64u + lane;
 #pragma unroll
@@ -278,7 +284,7 @@ struct VecTile {
     }
     // the partition's ragged end: a partial row and the last < 16 bytes,
     // done by the tile that owns row `full`
-    if (!owns_row(full, lt, nt, rpt, inter != 0)) return;
+    if (wave != 0 || !owns_row(full, lt, nt, rpt, inter != 0)) return;
     const uint32_t v = full * 64u + lane;
     if (v < nv) {
       uint4 x[P];
@@ -333,8 +339,8 @@ struct E4M3Tile {
   __device__ __forceinline__ static void run(const_ptr<BucketDesc> bd,
                                              uint64_t poff, uint64_t plen,
                                              uint32_t lt, uint32_t nt,
-                                             uint32_t tile_elems,
-                                             uint32_t inter) {
+                                             uint32_t inter, uint32_t wave,
+                                             uint32_t nwaves) {
     const uint32_t lane = lane_id();
     const uint8_t* in[P];
     const float* sc[P];
@@ -347,8 +353,8 @@ struct E4M3Tile {
     float* osc = bd->out_scale + poff / 256u;
     const uint32_t n = (uint32_t)plen;
     const uint32_t nrows = (n + kRowElems - 1) / kRowElems;
-    const RowSet rows(lt, nt, tile_elems / kRowElems, inter != 0, nrows);
-    for (uint32_t k = 0; k < rows.limit; ++k) {
+    const RowSet rows(lt, nt, (nrows + nt - 1) / nt, inter != 0, nrows);
+    for (uint32_t k = wave; k < rows.limit; k += nwaves) {
       const uint32_t el = rows.row(k) * kRowElems + lane * 16u;
       const uint32_t blk = el / 256u;
       const uint32_t have = el < n ? (n - el < 16u ? n - el : 16u) : 0u;

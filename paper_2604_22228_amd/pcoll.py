@@ -32,10 +32,12 @@ class PcollError(RuntimeError):
 
 
 class Config(C.Structure):
-    _fields_ = [("tile_elems", C.c_int), ("groups", C.c_int),
+    _fields_ = [("tile_elems", C.c_int), ("min_tile_elems", C.c_int),
+                ("groups", C.c_int),
                 ("groups_per_cu", C.c_int), ("comp", C.c_int),
                 ("graph", C.c_int), ("timeout_ms", C.c_int),
-                ("debug", C.c_int), ("interleave", C.c_int)]
+                ("debug", C.c_int), ("interleave", C.c_int),
+                ("guide", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -49,7 +51,7 @@ class Stats(C.Structure):
                 ("last_capture_ms", C.c_double),
                 ("last_instantiate_ms", C.c_double),
                 ("last_kernel_ms", C.c_float), ("groups", C.c_int),
-                ("total_tiles", C.c_int)]
+                ("reserved", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -80,7 +82,8 @@ _SIGS = {
     "pcoll_part_info": [_p, _i, C.POINTER(_i), C.POINTER(_sz),
                         C.POINTER(_sz)],
     "pcoll_get_stats": [_p, C.POINTER(Stats)],
-    "pcoll_debug_tile_hits": [_p, C.POINTER(C.c_uint32), _i],
+    "pcoll_debug_tile_hits": [_p, C.POINTER(C.c_uint32),
+                              C.POINTER(C.c_uint32), _i],
     "pcoll_plan": [_sz, _i, _i, C.POINTER(_sz), C.POINTER(_sz),
                    C.POINTER(_sz)],
     "pcoll_pack_bf16": [_p, _p, _sz, _p],
@@ -253,9 +256,11 @@ def pcoll_get_stats(h):
 
 
 def pcoll_debug_tile_hits(h, n):
-    arr = (C.c_uint32 * n)()
-    _check(load().pcoll_debug_tile_hits(h, arr, n), "pcoll_debug_tile_hits")
-    return list(arr)
+    hits = (C.c_uint32 * n)()
+    tiles = (C.c_uint32 * n)()
+    _check(load().pcoll_debug_tile_hits(h, hits, tiles, n),
+           "pcoll_debug_tile_hits")
+    return list(hits), list(tiles)
 
 
 def pcoll_plan(count, dtype, nparts):

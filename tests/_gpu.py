@@ -21,6 +21,8 @@ def as_u32(x):
 def new_request(counts, dtype, op, nparts, nranks, **cfg):
     req = pc.Request(counts, dtype, op, nparts, nranks)
     cfg.setdefault("timeout_ms", TEST_TIMEOUT_MS)
+    if "tile_elems" in cfg:
+        cfg.setdefault("min_tile_elems", min(cfg["tile_elems"], 4096))
     req.set_config(**cfg)
     return req
 

@@ -345,14 +345,17 @@ def test_exactly_once_tile_counts(orc, stream):
     xs = synth.normal_f32(P, n, 5)
     out = torch.empty(n, device=DEV)
     req = new_request([n], pc.FLOAT32, pc.SUM, nparts, P, debug=1,
-                      tile_elems=1024)
+                      tile_elems=4096, min_tile_elems=1024)
     req.bind([[x.to(DEV) for x in xs]], [out], stream=stream)
-    run_epoch(req, synth.permutation(nparts, 5), stream)
-    hits = req.tile_hits()
-    for p in range(nparts):
-        _, _, ln = req.part_info(p)
-        assert hits[p] == max(1, -(-ln // 1024)), p
-    assert req.stats().last_kernel_ms > 0
+    for epoch in range(3):
+        run_epoch(req, synth.permutation(nparts, 5 + epoch), stream)
+        hits, tiles = req.tile_hits()
+        for p in range(nparts):
+            _, _, ln = req.part_info(p)
+            rows = -(-ln // 256)  # fp32 rows of 256 elements
+            assert hits[p] == tiles[p], (p, hits[p], tiles[p])
+            assert 1 <= tiles[p] <= max(1, rows), p
+        assert req.stats().last_kernel_ms > 0
     req.free()
 
 
