@@ -186,8 +186,8 @@ typedef struct {
                         elements; a multiple of 1024.  Tiles shrink toward
                         the end of an epoch (guided self-scheduling) */
   int min_tile_elems; /* smallest tile; a multiple of 1024, <= tile_elems */
-  int groups;        /* workgroups of the persistent kernel (4 wavefronts
-                        each); 0 = groups_per_cu x compute units */
+  int groups;        /* workgroups of the persistent kernel; 0 =
+                        groups_per_cu x compute units */
   int groups_per_cu; /* used when groups = 0 */
   int comp;          /* float sums: 1 = Sum2 compensated, 0 = plain */
   int graph;         /* 1 = start replays a cached graph, 0 = direct launch */
@@ -196,6 +196,11 @@ typedef struct {
   int interleave;    /* tile layout: 0 = each tile is a contiguous range of
                         its partition; 1 = tile j of n takes every n-th row
                         (64 lanes x 16 bytes) starting at row j */
+  int group_waves;   /* wavefronts per workgroup (1..8); they share each
+                        tile's rows */
+  int publish_batch; /* finished tiles a workgroup publishes with one
+                        release (1..64): larger amortizes the L2 writeback,
+                        smaller lets partitions arrive sooner */
   int guide;         /* guided self-scheduling divisor f (0..64): a
                         partition queued with R rows of work left in the
                         epoch gets tiles of about R / (f x workgroups) rows,
@@ -207,7 +212,8 @@ typedef struct {
  * table (env PCOLL_TUNE_FILE, else the table shipped next to the library),
  * then from environment overrides: PCOLL_TILE, PCOLL_MIN_TILE, PCOLL_GROUPS,
  * PCOLL_GROUPS_PER_CU, PCOLL_COMP, PCOLL_GRAPH, PCOLL_TIMEOUT_MS,
- * PCOLL_DEBUG, PCOLL_INTERLEAVE, PCOLL_GUIDE. */
+ * PCOLL_DEBUG, PCOLL_INTERLEAVE, PCOLL_GUIDE, PCOLL_GROUP_WAVES,
+ * PCOLL_PUBLISH_BATCH. */
 int pcoll_get_config(pcoll_req_t req, pcoll_config_t *cfg);
 
 /* Replaces the configuration (not while an epoch is active).  Fields out of

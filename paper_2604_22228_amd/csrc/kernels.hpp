@@ -9,8 +9,9 @@
 
 namespace pcoll {
 
-// Wavefronts per workgroup of the persistent reduce kernel (256 threads).
-constexpr int kWavesPerGroup = 4;
+// Largest workgroup of the persistent reduce kernel, in wavefronts (the
+// kernels are compiled for up to 512 threads; the runtime picks 1..8).
+constexpr int kMaxWavesPerGroup = 8;
 
 // Dtype / op codes, equal to the public enums of pcoll.h.
 enum Dtype : int { kI32 = 0, kF32 = 1, kBF16 = 2, kE4M3 = 3 };
@@ -21,11 +22,11 @@ inline int elem_bytes(int dtype) {
   return dtype == kBF16 ? 2 : (dtype == kE4M3 ? 1 : 4);
 }
 
-// The persistent partitioned-reduce kernel: `groups` workgroups of
-// kWavesPerGroup wavefronts.  Returns hipErrorInvalidValue for an
-// unsupported (dtype, op, comp, nranks) combination.
+// The persistent partitioned-reduce kernel: `groups` workgroups of `waves`
+// wavefronts.  Returns hipErrorInvalidValue for an unsupported (dtype, op,
+// comp, nranks) combination.
 hipError_t launch_reduce(const ReduceArgs& a, int dtype, int op, bool comp,
-                         int nranks, int groups, hipStream_t s);
+                         int nranks, int groups, int waves, hipStream_t s);
 // Device-side readiness: appends `a.n` partition ids to the device ready
 // ring.
 hipError_t launch_pready(const PreadyArgs& a, hipStream_t s);

@@ -17,6 +17,7 @@
 namespace pcoll {
 
 constexpr int kMaxRanks = 16;
+constexpr int kMaxPublishBatch = 64;
 
 // Per bucket, in device memory; written once at bind time, read-only to the
 // kernels.
@@ -115,6 +116,8 @@ struct ReduceArgs {
                            // partition
   uint32_t* tile_counts;   // [nparts_total] debug: tiles chosen, or null
   uint32_t guide;          // guided-scheduling divisor f (0 = fixed tiles)
+  uint32_t publish_batch;  // finished tiles a workgroup publishes together
+  uint32_t reserved;
   uint64_t timeout_ticks; // device wall-clock ticks before giving up
 };
 

@@ -6,9 +6,9 @@
 // find out that it is the last one.  Every wavefront is an independent
 // worker; none ever waits for another, so the launch needs no co-residency
 // and drains even if it is larger than the machine.  The worker is a
-// workgroup of kWavesPerGroup wavefronts that reduce the rows of one tile
-// together (wavefront w takes every kWavesPerGroup-th row), so one claim
-// and one release serve four wavefronts.  Wavefront 0 of the group drives
+// workgroup of up to kMaxWavesPerGroup wavefronts that reduce the rows of one
+// tile together (wavefront w of W takes every W-th row), so one claim
+// and one release serve the whole group.  Wavefront 0 of the group drives
 // the protocol; the group meets at a barrier before and after each tile.
 // A worker loops:
 //
@@ -27,10 +27,11 @@
 //   3. find the queue entry covering t (64 entries per wave-wide probe),
 //      giving the partition and the tile inside it;
 //   4. reduce the tile (rank order 0..P-1 per element), store the result;
-//   5. publish: one release add on the partition's done counter; the worker
-//      that completes the partition stores the epoch into its arrived flag
-//      in host-coherent memory (completion is signalled only after every
-//      chunk of the partition has landed, Section 4.5).
+//   5. publish: after a release fence, add the tile to its partition's done
+//      counter (finished tiles are published in batches, see publish()); the
+//      worker that completes the partition stores the epoch into its
+//      arrived flag in host-coherent memory (completion is signalled only
+//      after every chunk of the partition has landed, Section 4.5).
 //
 // Exit: t >= total tiles.  A worker that starves past the deadline, or sees
 // the host's abort word, records the reason (also in host memory, stamped
@@ -312,27 +313,45 @@ __device__ __forceinline__ void locate(const ReduceArgs& a, uint32_t t,
   }
 }
 
-// Publishes one finished tile of `part` (called by wavefront 0 after the
-// group's barrier): one release add on the partition's done counter (the
-// release covers the group's stores: every wavefront waited for its own
-// stores before the barrier, and the release writes back the L2 they sit
-// in); the worker whose add completes the partition acquires the other
-// workers' tiles and stores the epoch into the host-visible arrived flag.
-__device__ __forceinline__ void finish_tile(const ReduceArgs& a, uint32_t part,
-                                            uint32_t ntiles, uint32_t epoch) {
+// Completion of finished tiles.  Publishing a tile means: its stores are
+// visible device-wide, then the partition's done counter counts it; the
+// worker whose count completes the partition acquires the other workers'
+// tiles and stores the epoch into the host-visible arrived flag.  Making
+// stores visible device-wide takes a release fence, which writes back the
+// L2 of this XCD and costs tens of nanoseconds, serialized; so a workgroup
+// keeps up to `batch` finished tiles pending and publishes them together:
+// one release fence (it covers every store the group made before it: each
+// wavefront waited for its own stores before the group's barrier), then one
+// relaxed add per tile (release fence followed by the atomic: the standard
+// fence-to-atomic synchronization).  A group publishes before it waits for
+// work, before it stops, and when `batch` tiles are pending, so a partition
+// arrives at most `batch` tiles of one group late.
+struct Pending {
+  uint32_t part;
+  uint32_t nt;
+};
+
+__device__ __forceinline__ void publish(const ReduceArgs& a, Pending* pend,
+                                        uint32_t& npend, uint32_t epoch) {
+  if (npend == 0) return;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   if (lane_id() == 0) {
-    if (a.tile_hits)
-      __hip_atomic_fetch_add(&a.tile_hits[part], 1u, __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
-    uint32_t old = __hip_atomic_fetch_add(&a.done[part], 1u, __ATOMIC_RELEASE,
-                                          __HIP_MEMORY_SCOPE_AGENT);
-    if (old + 1u == ntiles) {
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      st_rlx(&a.done[part], 0u);
-      __threadfence_system();
-      st_rel_sys(&a.arrived[part], epoch);
+    for (uint32_t i = 0; i < npend; ++i) {
+      const uint32_t part = pend[i].part;
+      if (a.tile_hits)
+        __hip_atomic_fetch_add(&a.tile_hits[part], 1u, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+      const uint32_t old = __hip_atomic_fetch_add(
+          &a.done[part], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (old + 1u == pend[i].nt) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        st_rlx(&a.done[part], 0u);
+        __threadfence_system();
+        st_rel_sys(&a.arrived[part], epoch);
+      }
     }
   }
+  npend = 0;
 }
 
 // The tile index after the first round: one relaxed atomic add by lane 0.
@@ -358,6 +377,7 @@ struct TileJob {
 template <class Tile, int P>
 __device__ __forceinline__ void persistent_loop(const ReduceArgs& a) {
   __shared__ TileJob job;
+  __shared__ Pending pend[kMaxPublishBatch];
   const uint32_t wave = threadIdx.x / 64u;
   const uint32_t nwaves = blockDim.x / 64u;
   const uint32_t epoch = uni(ld_acq(&a.ctr->epoch));
@@ -366,15 +386,20 @@ __device__ __forceinline__ void persistent_loop(const ReduceArgs& a) {
   uint32_t t = blockIdx.x;  // first round: tile = workgroup number
   uint32_t next = 0;
   uint64_t qs = 0;          // queue state last acquired (wavefront 0)
+  uint32_t npend = 0;       // finished tiles not yet published (wavefront 0)
   for (;;) {
     if (wave == 0) {
       TileJob j{~0u, 0u, 0u};
+      // publish before any wait: finished work must not sit behind it
+      if ((uint32_t)qs <= t) publish(a, pend, npend, epoch);
       if (wait_queued(a, t, epoch, t0, qs) == kReady) {
         uint32_t end = 0;
         locate(a, t, (uint32_t)(qs >> 32), cursor, prev_end, j.part, end);
         j.lt = t - prev_end;
         j.nt = end - prev_end;
         next = claim(a);  // in flight while the tile is reduced
+      } else {
+        publish(a, pend, npend, epoch);
       }
       if (lane_id() == 0) job = j;
     }
@@ -392,7 +417,9 @@ __device__ __forceinline__ void persistent_loop(const ReduceArgs& a) {
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (wave == 0) {
-      finish_tile(a, j.part, j.nt, epoch);
+      if (lane_id() == 0) pend[npend] = Pending{j.part, j.nt};
+      ++npend;
+      if (npend >= a.publish_batch) publish(a, pend, npend, epoch);
       t = uni(next);
     }
   }

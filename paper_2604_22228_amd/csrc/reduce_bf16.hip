@@ -3,10 +3,10 @@
 
 namespace pcoll {
 hipError_t launch_reduce_bf16(const ReduceArgs& a, int op, bool comp,
-                              int nranks, int groups, hipStream_t s) {
+                              int nranks, int groups, int waves, hipStream_t s) {
   using namespace dev;
-  if (op == kMax) return launch_ranks<VecTile<FMax, 2>>(a, nranks, groups, s);
-  if (comp) return launch_ranks<VecTile<FSum<true>, 2>>(a, nranks, groups, s);
-  return launch_ranks<VecTile<FSum<false>, 2>>(a, nranks, groups, s);
+  if (op == kMax) return launch_ranks<VecTile<FMax, 2>>(a, nranks, groups, waves, s);
+  if (comp) return launch_ranks<VecTile<FSum<true>, 2>>(a, nranks, groups, waves, s);
+  return launch_ranks<VecTile<FSum<false>, 2>>(a, nranks, groups, waves, s);
 }
 }  // namespace pcoll

@@ -3,9 +3,9 @@
 
 namespace pcoll {
 hipError_t launch_reduce_e4m3(const ReduceArgs& a, bool comp, int nranks,
-                              int groups, hipStream_t s) {
+                              int groups, int waves, hipStream_t s) {
   using namespace dev;
-  if (comp) return launch_ranks<E4M3Tile<true>>(a, nranks, groups, s);
-  return launch_ranks<E4M3Tile<false>>(a, nranks, groups, s);
+  if (comp) return launch_ranks<E4M3Tile<true>>(a, nranks, groups, waves, s);
+  return launch_ranks<E4M3Tile<false>>(a, nranks, groups, waves, s);
 }
 }  // namespace pcoll

@@ -10,15 +10,15 @@
 namespace pcoll {
 
 template <class Tile, int P>
-__global__ __launch_bounds__(64 * kWavesPerGroup) void reduce_persistent(
+__global__ __launch_bounds__(64 * kMaxWavesPerGroup) void reduce_persistent(
     ReduceArgs a) {
   dev::persistent_loop<Tile, P>(a);
 }
 
 template <class Tile>
 hipError_t launch_ranks(const ReduceArgs& a, int nranks, int groups,
-                        hipStream_t s) {
-  const dim3 grid(groups), block(64 * kWavesPerGroup);
+                        int waves, hipStream_t s) {
+  const dim3 grid(groups), block(64 * waves);
   switch (nranks) {
 #define PCOLL_CASE(P)                                                \
   case P:                                                            \
@@ -38,12 +38,12 @@ hipError_t launch_ranks(const ReduceArgs& a, int nranks, int groups,
 
 // Per-family launchers, defined in reduce_<family>.hip.
 hipError_t launch_reduce_f32(const ReduceArgs&, int op, bool comp, int nranks,
-                             int groups, hipStream_t);
+                             int groups, int waves, hipStream_t);
 hipError_t launch_reduce_i32(const ReduceArgs&, int op, int nranks, int groups,
-                             hipStream_t);
+                             int waves, hipStream_t);
 hipError_t launch_reduce_bf16(const ReduceArgs&, int op, bool comp,
-                              int nranks, int groups, hipStream_t);
+                              int nranks, int groups, int waves, hipStream_t);
 hipError_t launch_reduce_e4m3(const ReduceArgs&, bool comp, int nranks,
-                              int groups, hipStream_t);
+                              int groups, int waves, hipStream_t);
 
 }  // namespace pcoll

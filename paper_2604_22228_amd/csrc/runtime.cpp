@@ -194,7 +194,9 @@ uint64_t launch_signature(const pcoll_req_s* r) {
                         (uint64_t)r->cfg.min_tile_elems, (uint64_t)r->groups,
                         (uint64_t)r->cfg.comp, (uint64_t)r->cfg.debug,
                         (uint64_t)r->cfg.timeout_ms, r->total_rows,
-                        (uint64_t)r->cfg.interleave, (uint64_t)r->cfg.guide};
+                        (uint64_t)r->cfg.interleave, (uint64_t)r->cfg.guide,
+                        (uint64_t)r->cfg.group_waves,
+                        (uint64_t)r->cfg.publish_batch};
   for (uint64_t x : v) {
     h ^= x;
     h *= 1099511628211ull;
@@ -220,6 +222,10 @@ int validate_config(const pcoll_req_s* r, const pcoll_config_t& c) {
   if (c.debug != 0 && c.debug != 1) return PCOLL_ERR_ARG;
   if (c.interleave != 0 && c.interleave != 1) return PCOLL_ERR_ARG;
   if (c.guide < 0 || c.guide > 64) return PCOLL_ERR_ARG;
+  if (c.group_waves < 1 || c.group_waves > kMaxWavesPerGroup)
+    return PCOLL_ERR_ARG;
+  if (c.publish_batch < 1 || c.publish_batch > kMaxPublishBatch)
+    return PCOLL_ERR_ARG;
   return PCOLL_SUCCESS;
 }
 
@@ -257,6 +263,8 @@ pcoll_config_t default_config(const pcoll_req_s* r) {
   if (c.min_tile_elems > c.tile_elems) c.min_tile_elems = c.tile_elems;
   c.interleave = env_int("PCOLL_INTERLEAVE", t.interleave) ? 1 : 0;
   c.guide = env_int("PCOLL_GUIDE", 0);
+  c.group_waves = env_int("PCOLL_GROUP_WAVES", t.group_waves);
+  c.publish_batch = env_int("PCOLL_PUBLISH_BATCH", t.publish_batch);
   c.groups = env_int("PCOLL_GROUPS", 0);
   c.groups_per_cu = env_int("PCOLL_GROUPS_PER_CU", t.groups_per_cu);
   const bool float_sum = r->op == PCOLL_SUM && r->dtype != PCOLL_INT32;
@@ -418,6 +426,7 @@ ReduceArgs make_args(const pcoll_req_s* r) {
   a.interleave = (uint32_t)r->cfg.interleave;
   a.tile_counts = r->cfg.debug ? r->d_tiles : nullptr;
   a.guide = (uint32_t)r->cfg.guide;
+  a.publish_batch = (uint32_t)r->cfg.publish_batch;
   a.timeout_ticks = (uint64_t)r->cfg.timeout_ms * (uint64_t)r->clock_khz;
   return a;
 }
@@ -432,7 +441,7 @@ int launch_direct(pcoll_req_t r, hipStream_t s) {
   HIP_TRY(launch_reset(ra, s));
   const ReduceArgs a = make_args(r);
   HIP_TRY(launch_reduce(a, r->dtype, r->op, r->cfg.comp != 0, r->nranks,
-                        r->groups, s));
+                        r->groups, r->cfg.group_waves, s));
   return PCOLL_SUCCESS;
 }
 

@@ -49,11 +49,11 @@ std::vector<TuneRow> parse_tune_table(const std::string& text) {
     auto hash = line.find('#');
     if (hash != std::string::npos) line.resize(hash);
     std::istringstream ls(line);
-    std::string f[9];
+    std::string f[11];
     int nf = 0;
-    while (nf < 9 && (ls >> f[nf])) ++nf;
+    while (nf < 11 && (ls >> f[nf])) ++nf;
     std::string extra;
-    if ((nf != 8 && nf != 9) || (ls >> extra)) continue;
+    if (nf < 8 || (ls >> extra)) continue;
     TuneRow r;
     r.dtype = parse_dtype(f[0]);
     r.op = parse_op(f[1]);
@@ -66,8 +66,14 @@ std::vector<TuneRow> parse_tune_table(const std::string& text) {
     if (!parse_int_or_any(f[6], &r.tile_elems) ||
         !parse_int_or_any(f[7], &r.groups_per_cu))
       continue;
-    if (nf == 9 && (!parse_int_or_any(f[8], &r.interleave) ||
+    if (nf >= 9 && (!parse_int_or_any(f[8], &r.interleave) ||
                     (r.interleave != 0 && r.interleave != 1)))
+      continue;
+    if (nf >= 10 && (!parse_int_or_any(f[9], &r.group_waves) ||
+                     r.group_waves < 1 || r.group_waves > 8))
+      continue;
+    if (nf == 11 && (!parse_int_or_any(f[10], &r.publish_batch) ||
+                     r.publish_batch < 1 || r.publish_batch > 64))
       continue;
     if (r.log2_lo < 0) r.log2_lo = 0;
     if (r.log2_hi < 0) r.log2_hi = 63;
@@ -85,11 +91,12 @@ TuneChoice tune_lookup(const std::vector<TuneRow>& rows, int dtype, int op,
   for (const auto& r : rows) {
     if (match(r.dtype, dtype) && match(r.op, op) && match(r.ranks, ranks) &&
         match(r.graph, graph) && lg >= r.log2_lo && lg <= r.log2_hi)
-      return {r.tile_elems, r.groups_per_cu, r.interleave};
+      return {r.tile_elems, r.groups_per_cu, r.interleave, r.group_waves,
+              r.publish_batch};
   }
   // built-in default: 16 KiB of output per tile, two groups per CU
   int elem = dtype == 2 ? 2 : (dtype == 3 ? 1 : 4);
-  return {16384 / elem, 2, 0};
+  return {16384 / elem, 2, 0, 4, 16};
 }
 
 }  // namespace pcoll

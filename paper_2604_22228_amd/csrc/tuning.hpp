@@ -5,13 +5,15 @@
 // tuned values are defaults that environment variables override.  Here the
 // search is done by the package's autotuner, which writes a text table:
 //
-//   # dtype op ranks graph log2_lo log2_hi tile_elems groups_per_cu interleave
-//   f32     sum 8   0     24      28      8192       2             1
+//   # dtype op ranks graph log2_lo log2_hi tile groups_per_cu interleave waves batch
+//   f32     sum 8   0     24      28      4096   1             1          4     16
 //
 // dtype in {i32, f32, bf16, e4m3, *}, op in {sum, max, *}, ranks a number
 // or *, graph 0 / 1 / *, and [log2_lo, log2_hi] the range of
-// floor(log2(bytes per rank of the whole request)); the interleave column
-// may be omitted (0).  The first matching row wins.  Host-only C++17.
+// floor(log2(bytes per rank of the whole request)); the trailing interleave
+// (default 0), waves-per-workgroup (default 4) and publish-batch (default
+// 16) columns may be omitted, from the right.  The first
+// matching row wins.  Host-only C++17.
 #pragma once
 #include <cstdint>
 #include <string>
@@ -22,13 +24,16 @@ namespace pcoll {
 struct TuneRow {
   int dtype = -1, op = -1, ranks = -1, graph = -1;  // -1 = any
   int log2_lo = 0, log2_hi = 63;
-  int tile_elems = 0, groups_per_cu = 0, interleave = 0;
+  int tile_elems = 0, groups_per_cu = 0, interleave = 0, group_waves = 4;
+  int publish_batch = 16;
 };
 
 struct TuneChoice {
   int tile_elems;
   int groups_per_cu;
   int interleave;
+  int group_waves;
+  int publish_batch;
 };
 
 // Parses a table; malformed lines are skipped.  Returns the rows.

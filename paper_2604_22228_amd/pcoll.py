@@ -37,6 +37,7 @@ class Config(C.Structure):
                 ("groups_per_cu", C.c_int), ("comp", C.c_int),
                 ("graph", C.c_int), ("timeout_ms", C.c_int),
                 ("debug", C.c_int), ("interleave", C.c_int),
+                ("group_waves", C.c_int), ("publish_batch", C.c_int),
                 ("guide", C.c_int)]
 
     def as_dict(self):

@@ -340,15 +340,21 @@ def test_pready_on_stream(orc, stream):
     req.free()
 
 
-def test_exactly_once_tile_counts(orc, stream):
+@pytest.mark.parametrize("batch", [1, 7, 64])
+def test_exactly_once_tile_counts(orc, stream, batch):
+    say(f"case exactly-once publish_batch={batch}")
     P, n, nparts = 2, 100 * 1024 + 3, 7
     xs = synth.normal_f32(P, n, 5)
     out = torch.empty(n, device=DEV)
     req = new_request([n], pc.FLOAT32, pc.SUM, nparts, P, debug=1,
-                      tile_elems=4096, min_tile_elems=1024)
+                      tile_elems=4096, min_tile_elems=1024,
+                      publish_batch=batch)
     req.bind([[x.to(DEV) for x in xs]], [out], stream=stream)
+    want = orc.sum_f32_f32([x.numpy() for x in xs], comp=False)
     for epoch in range(3):
+        out.fill_(float("nan"))
         run_epoch(req, synth.permutation(nparts, 5 + epoch), stream)
+        assert np.array_equal(as_u32(out.cpu().numpy()), as_u32(want))
         hits, tiles = req.tile_hits()
         for p in range(nparts):
             _, _, ln = req.part_info(p)
