@@ -145,14 +145,22 @@ int pcoll_pready_on_stream(pcoll_req_t req, const int *parts_dev, int n,
 
 /* Non-blocking test of one partition: *flag = 1 once its output is final in
  * the current (or last completed) epoch.  PCOLL_ERR_STATE before the first
- * start. */
+ * start.  Arrival (Section 4.5: a partition counts only after all of its
+ * chunks have landed) is signalled either by the partition's own flag,
+ * which the kernel sets as soon as it has published the partition's last
+ * tile, or by the retirement of the epoch's kernel with no error, which
+ * implies every partition: the kernel leaves the tiles that a workgroup
+ * still holds when the work runs out to its own end instead of publishing
+ * them (config field publish_batch).  The second case costs one
+ * hipEventQuery. */
 int pcoll_parrived(pcoll_req_t req, int part, int *flag);
 
 /* Non-blocking test of the whole epoch: *flag = 1 once every partition has
  * arrived; completes the epoch like pcoll_wait when it does. */
 int pcoll_test(pcoll_req_t req, int *flag);
 
-/* Blocks until every partition has arrived and the epoch is complete.
+/* Blocks until every partition has arrived (by its flag, or by the
+ * kernel's clean retirement; see pcoll_parrived) and the epoch is complete.
  * Returns PCOLL_ERR_ABORTED if the kernel gave up on its own deadline
  * (configurable, default 10 s) because some partition was never readied.
  * A request with no active epoch returns at once. */
@@ -199,8 +207,11 @@ typedef struct {
   int group_waves;   /* wavefronts per workgroup (1..8); they share each
                         tile's rows */
   int publish_batch; /* finished tiles a workgroup publishes with one
-                        release (1..64): larger amortizes the L2 writeback,
-                        smaller lets partitions arrive sooner */
+                        release (1..64).  A workgroup also publishes before
+                        it waits for readied work, so the batch only delays
+                        arrival flags while the kernel has a backlog:
+                        larger amortizes the L2 writeback, smaller lets
+                        partitions arrive sooner under backlog */
   int guide;         /* guided self-scheduling divisor f (0..64): a
                         partition queued with R rows of work left in the
                         epoch gets tiles of about R / (f x workgroups) rows,

@@ -57,9 +57,7 @@ struct HostShared {
   uint32_t abort;         // host: == epoch asks the kernel to give up
   uint32_t status;        // device: error code of epoch status_epoch
   uint32_t status_epoch;  // device: epoch the status belongs to
-  uint32_t reset_done;    // host: 1 = clear every done counter at the next
-                          // start (the last epoch was abandoned midway)
-  uint32_t reserved[26];
+  uint32_t reserved[27];
 };
 
 // Device-memory counters of one request; each group on its own 128-B line

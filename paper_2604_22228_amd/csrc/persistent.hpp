@@ -31,12 +31,15 @@
 //      counter (finished tiles are published in batches, see publish()); the
 //      worker that completes the partition stores the epoch into its
 //      arrived flag in host-coherent memory (completion is signalled only
-//      after every chunk of the partition has landed, Section 4.5).
+//      after every chunk of the partition has landed, Section 4.5).  The
+//      tiles a worker still holds when the work runs out complete with the
+//      launch itself.
 //
 // Exit: t >= total tiles.  A worker that starves past the deadline, or sees
 // the host's abort word, records the reason (also in host memory, stamped
 // with the epoch) and leaves; the others follow.  The host's wait returns
-// when every arrived flag carries the epoch, or when an error is recorded.
+// when every arrived flag carries the epoch, or the launch has retired with
+// no error recorded, or an error is recorded.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -244,15 +247,18 @@ __device__ __forceinline__ void set_error(const ReduceArgs& a, uint32_t code,
 enum WaitResult { kBail, kStop, kReady };
 
 // Waits until tile t is queued (kReady, with the queue state in qs_out).
+// Before it first has to wait it calls publish_pending().
 // kStop: every partition is queued and t is beyond the last tile.  kBail:
 // give up (deadline, host abort, or another worker's error).  Only the few
 // workers at the front of the claim order (t within 8 tiles of the queued
 // total) poll the ready lists and the host's abort word; the rest re-read
 // the device-side queue state at a slower pace.
+template <class Publish>
 __device__ __forceinline__ WaitResult wait_queued(const ReduceArgs& a,
                                                   uint32_t t, uint32_t epoch,
                                                   uint64_t t0,
-                                                  uint64_t& qs_out) {
+                                                  uint64_t& qs_out,
+                                                  Publish&& publish_pending) {
   // the queue state this worker acquired last: entries it covers are
   // already visible, so a tile inside it needs no new acquire
   if ((uint32_t)qs_out > t) return kReady;
@@ -264,6 +270,8 @@ __device__ __forceinline__ WaitResult wait_queued(const ReduceArgs& a,
       return kReady;
     }
     if ((uint32_t)(qs >> 32) >= a.nparts_total) return kStop;
+    // about to wait: finished tiles must not sit behind the wait
+    publish_pending();
     const bool front = t - qt < 8u;
     if (front && try_ingest(a, epoch)) continue;
     if (uni(ld_rlx(&a.ctr->error)) != 0u) return kBail;
@@ -317,40 +325,65 @@ __device__ __forceinline__ void locate(const ReduceArgs& a, uint32_t t,
 // visible device-wide, then the partition's done counter counts it; the
 // worker whose count completes the partition acquires the other workers'
 // tiles and stores the epoch into the host-visible arrived flag.  Making
-// stores visible device-wide takes a release fence, which writes back the
-// L2 of this XCD and costs tens of nanoseconds, serialized; so a workgroup
-// keeps up to `batch` finished tiles pending and publishes them together:
-// one release fence (it covers every store the group made before it: each
-// wavefront waited for its own stores before the group's barrier), then one
-// relaxed add per tile (release fence followed by the atomic: the standard
-// fence-to-atomic synchronization).  A group publishes before it waits for
-// work, before it stops, and when `batch` tiles are pending, so a partition
-// arrives at most `batch` tiles of one group late.
+// stores visible device-wide takes an agent-scope release fence, which
+// writes back this XCD's L2 and holds it for a fraction of a microsecond,
+// serialized with every other release on the XCD; so a workgroup keeps up
+// to `publish_batch` finished tiles pending and publishes them together:
+// one release fence (it covers every store of the group: each wavefront
+// waited for its own stores before the group's barrier), then one relaxed
+// add per tile, issued by one lane each (fence followed by the atomic: the
+// standard fence-to-atomic synchronization).  A group publishes when the
+// batch is full and before it waits for work, so a partition is late by at
+// most one batch of one group, and only while the kernel has a backlog of
+// readied work.
+//
+// When a group runs out of tiles for good it publishes nothing: a launch
+// that retires without an error has reduced every tile (a worker leaves
+// without error only once every tile index below the total was claimed, and
+// every claimed tile is reduced), and the kernel's end makes all its stores
+// visible, so the host counts every partition as arrived once the launch
+// has retired cleanly.  That saves the burst of releases at the end, which
+// would serialize on each XCD.  The reset kernel clears the done counters
+// these tiles leave partial.
 struct Pending {
   uint32_t part;
   uint32_t nt;
 };
 
-__device__ __forceinline__ void publish(const ReduceArgs& a, Pending* pend,
-                                        uint32_t& npend, uint32_t epoch) {
+__device__ __forceinline__ void publish(const ReduceArgs& a,
+                                        const Pending* pend, uint32_t& npend,
+                                        uint32_t epoch) {
   if (npend == 0) return;
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  if (lane_id() == 0) {
-    for (uint32_t i = 0; i < npend; ++i) {
-      const uint32_t part = pend[i].part;
-      if (a.tile_hits)
-        __hip_atomic_fetch_add(&a.tile_hits[part], 1u, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-      const uint32_t old = __hip_atomic_fetch_add(
-          &a.done[part], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (old + 1u == pend[i].nt) {
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        st_rlx(&a.done[part], 0u);
-        __threadfence_system();
-        st_rel_sys(&a.arrived[part], epoch);
-      }
-    }
+  // lane i publishes pending tile i: one wave-wide atomic instruction
+  const uint32_t l = lane_id();
+  uint32_t part = 0;
+  bool last = false;
+  if (l < npend) {
+    part = pend[l].part;
+    if (a.tile_hits)
+      __hip_atomic_fetch_add(&a.tile_hits[part], 1u, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t old = __hip_atomic_fetch_add(
+        &a.done[part], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    last = old + 1u == pend[l].nt;  // exactly one add completes a partition
   }
+  if (__builtin_amdgcn_ballot_w64(last) != 0) {
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    __threadfence_system();
+    if (last) st_rel_sys(&a.arrived[part], epoch);
+  }
+  npend = 0;
+}
+
+// The group has no tiles left: its pending tiles complete with the launch.
+// Only the debug tile counts see them.
+__device__ __forceinline__ void retire(const ReduceArgs& a,
+                                       const Pending* pend, uint32_t& npend) {
+  const uint32_t l = lane_id();
+  if (a.tile_hits && l < npend)
+    __hip_atomic_fetch_add(&a.tile_hits[pend[l].part], 1u, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
   npend = 0;
 }
 
@@ -390,16 +423,17 @@ __device__ __forceinline__ void persistent_loop(const ReduceArgs& a) {
   for (;;) {
     if (wave == 0) {
       TileJob j{~0u, 0u, 0u};
-      // publish before any wait: finished work must not sit behind it
-      if ((uint32_t)qs <= t) publish(a, pend, npend, epoch);
-      if (wait_queued(a, t, epoch, t0, qs) == kReady) {
+      const WaitResult w = wait_queued(a, t, epoch, t0, qs, [&] {
+        publish(a, pend, npend, epoch);
+      });
+      if (w == kReady) {
         uint32_t end = 0;
         locate(a, t, (uint32_t)(qs >> 32), cursor, prev_end, j.part, end);
         j.lt = t - prev_end;
         j.nt = end - prev_end;
         next = claim(a);  // in flight while the tile is reduced
-      } else {
-        publish(a, pend, npend, epoch);
+      } else if (w == kStop) {
+        retire(a, pend, npend);
       }
       if (lane_id() == 0) job = j;
     }
@@ -438,10 +472,10 @@ __device__ __forceinline__ void reset_epoch(const ResetArgs& a) {
     st_rlx(&c->error, 0u);
     st_rlx(&c->epoch, ld_acq_sys(&a.host->epoch));
   }
-  // an abandoned epoch can leave partial done counts behind
-  if (ld_acq_sys(&a.host->reset_done))
-    for (uint32_t p = threadIdx.x; p < a.nparts_total; p += blockDim.x)
-      st_rlx(&a.done[p], 0u);
+  // tiles that complete with the launch, and an abandoned epoch, leave
+  // partial done counts behind
+  for (uint32_t p = threadIdx.x; p < a.nparts_total; p += blockDim.x)
+    st_rlx(&a.done[p], 0u);
 }
 
 // ------------------------------------------------------ memory streaming

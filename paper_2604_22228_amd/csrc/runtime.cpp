@@ -165,7 +165,7 @@ struct pcoll_req_s {
 
   uint32_t epoch = 0;
   bool active = false;
-  bool reset_pending = false;   // last epoch abandoned: clear done counters
+  bool epoch_ok = false;        // the last finished epoch completed
   uint32_t scan = 0;            // first partition not yet seen arrived
   uint32_t hcount = 0;
   std::vector<uint32_t> stamp;  // epoch in which each partition was readied
@@ -495,8 +495,9 @@ uint32_t epoch_status(const pcoll_req_s* r) {
   return __atomic_load_n(&r->host->status, __ATOMIC_RELAXED);
 }
 
-// Whether every partition has arrived this epoch; `scan` remembers the
-// first one not seen arrived, so a wait reads each flag about once.
+// Whether every partition has arrived this epoch by its flag; `scan`
+// remembers the first one not seen arrived, so a wait reads each flag
+// about once.
 bool all_arrived(pcoll_req_s* r) {
   while (r->scan < r->nparts_total &&
          __atomic_load_n(&r->arrived[r->scan], __ATOMIC_ACQUIRE) == r->epoch)
@@ -504,12 +505,24 @@ bool all_arrived(pcoll_req_s* r) {
   return r->scan == r->nparts_total;
 }
 
+// Whether the epoch's launch has retired: 1 yes, 0 not yet, or a negative
+// error code (the HIP error is kept for pcoll_last_error_detail).  A launch
+// that retired with no error recorded has reduced every tile, and its end
+// made every store visible: then every partition has arrived, also those
+// whose last tiles the kernel left unpublished.
+int retired(pcoll_req_s* r) {
+  const hipError_t q = hipEventQuery(r->ev_end);
+  if (q == hipSuccess) return 1;
+  if (q == hipErrorNotReady) return 0;
+  return hip_fail(q, "hipEventQuery");
+}
+
 // Completes the epoch: every partition arrived, or the kernel gave up (then
 // wait for it to drain before reporting).
 int finish_epoch(pcoll_req_t r, uint32_t st) {
   r->active = false;
+  r->epoch_ok = st == kStatusOk;
   if (st != kStatusOk) {
-    r->reset_pending = true;
     HIP_TRY(hipEventSynchronize(r->ev_end));
     return st == kStatusTimeout ? PCOLL_ERR_ABORTED : PCOLL_ERR_TIMEOUT;
   }
@@ -522,38 +535,46 @@ int finish_epoch(pcoll_req_t r, uint32_t st) {
   return PCOLL_SUCCESS;
 }
 
+// Finishes an epoch that completed: 1, or a negative error code.
+int complete_ok(pcoll_req_t r) {
+  const int rc = finish_epoch(r, kStatusOk);
+  return rc ? rc : 1;
+}
+
+// One look at the epoch: 1 complete (then finished), 0 not yet, or a
+// negative error code.  The arrived flags are read every time; the launch's
+// retirement, which costs a runtime call, only with query_event.
+int poll_epoch(pcoll_req_t r, bool query_event) {
+  if (all_arrived(r)) return complete_ok(r);
+  uint32_t st = epoch_status(r);
+  if (st != kStatusOk) return finish_epoch(r, st);
+  if (!query_event) return 0;
+  const int rt = retired(r);
+  if (rt == 0) return 0;
+  if (rt < 0) {
+    r->active = false;
+    r->epoch_ok = false;
+    return rt;
+  }
+  // the error word is written before the kernel retires
+  st = epoch_status(r);
+  if (st != kStatusOk) return finish_epoch(r, st);
+  return complete_ok(r);
+}
+
 // Spins until the epoch completes.  With limit_ms >= 0, asks the kernel to
-// stop waiting for unready partitions after that long.  A kernel that
-// retires without completing the epoch (only a fault could do that: it has
-// its own deadline) is detected through its event.
+// stop waiting for unready partitions after that long.
 int spin_wait(pcoll_req_t r, int limit_ms) {
   auto t0 = std::chrono::steady_clock::now();
   bool aborted = false;
   for (uint64_t it = 0;; ++it) {
-    if (all_arrived(r)) return finish_epoch(r, kStatusOk);
-    const uint32_t st = epoch_status(r);
-    if (st != kStatusOk) return finish_epoch(r, st);
+    const int rc = poll_epoch(r, (it & 7) == 7);
+    if (rc != 0) return rc < 0 ? rc : PCOLL_SUCCESS;
     _mm_pause();
-    if ((it & 1023) != 1023) continue;
-    const double el = ms_since(t0);
-    if (!aborted && limit_ms >= 0 && el >= limit_ms) {
+    if (!aborted && limit_ms >= 0 && (it & 1023) == 1023 &&
+        ms_since(t0) >= limit_ms) {
       __atomic_store_n(&r->host->abort, r->epoch, __ATOMIC_RELEASE);
       aborted = true;
-    }
-    hipError_t q = hipEventQuery(r->ev_end);
-    if (q == hipSuccess) {
-      if (all_arrived(r)) return finish_epoch(r, kStatusOk);
-      const uint32_t st2 = epoch_status(r);
-      if (st2 != kStatusOk) return finish_epoch(r, st2);
-      r->active = false;
-      r->reset_pending = true;
-      g_detail = "kernel retired without completing the epoch";
-      return PCOLL_ERR_HIP;
-    }
-    if (q != hipErrorNotReady) {
-      r->active = false;
-      r->reset_pending = true;
-      return hip_fail(q, "hipEventQuery");
     }
   }
 }
@@ -707,7 +728,6 @@ int pcoll_start(pcoll_req_t r) {
   // stream, and a finished epoch no longer reads these words
   r->host->hcount = 0;
   r->host->abort = 0;
-  r->host->reset_done = r->reset_pending ? 1u : 0u;
   __atomic_store_n(&r->host->epoch, e, __ATOMIC_RELEASE);
   r->hcount = 0;
   r->scan = 0;
@@ -725,7 +745,7 @@ int pcoll_start(pcoll_req_t r) {
   r->ev_end_recorded = true;
   r->epoch = e;
   r->active = true;
-  r->reset_pending = false;
+  r->epoch_ok = false;
   r->stats.epochs++;
   r->stats.groups = r->groups;
   return PCOLL_SUCCESS;
@@ -799,7 +819,19 @@ int pcoll_parrived(pcoll_req_t r, int part, int* flag) {
   if (check_req(r) || !flag) return PCOLL_ERR_ARG;
   if (part < 0 || (uint32_t)part >= r->nparts_total) return PCOLL_ERR_ARG;
   if (r->epoch == 0) return PCOLL_ERR_STATE;
-  *flag = __atomic_load_n(&r->arrived[part], __ATOMIC_ACQUIRE) == r->epoch;
+  *flag = 0;
+  if (__atomic_load_n(&r->arrived[part], __ATOMIC_ACQUIRE) == r->epoch) {
+    *flag = 1;
+    return PCOLL_SUCCESS;
+  }
+  if (!r->active) {
+    *flag = r->epoch_ok ? 1 : 0;
+    return PCOLL_SUCCESS;
+  }
+  // a launch that retired cleanly has completed every partition
+  const int rt = retired(r);
+  if (rt < 0) return rt;
+  *flag = rt == 1 && epoch_status(r) == kStatusOk;
   return PCOLL_SUCCESS;
 }
 
@@ -809,23 +841,9 @@ int pcoll_test(pcoll_req_t r, int* flag) {
     *flag = 1;
     return PCOLL_SUCCESS;
   }
-  if (all_arrived(r)) {
-    *flag = 1;
-    return finish_epoch(r, kStatusOk);
-  }
-  const uint32_t st = epoch_status(r);
-  if (st != kStatusOk) {
-    *flag = 1;
-    return finish_epoch(r, st);
-  }
-  hipError_t q = hipEventQuery(r->ev_end);
-  if (q != hipSuccess && q != hipErrorNotReady) {
-    r->active = false;
-    r->reset_pending = true;
-    return hip_fail(q, "hipEventQuery");
-  }
-  *flag = 0;
-  return PCOLL_SUCCESS;
+  const int rc = poll_epoch(r, true);
+  *flag = rc != 0;
+  return rc < 0 ? rc : PCOLL_SUCCESS;
 }
 
 int pcoll_wait(pcoll_req_t r) {

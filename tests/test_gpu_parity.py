@@ -6,6 +6,7 @@ oracle's mirror of the kernel's binary32 arithmetic; floating-point results
 within the Sigma|x|-normalized tolerance against the FP64 reference (1e-6
 fp32, 4e-3 bf16, 6e-2 e4m3).  Inputs come from the seeded generators."""
 import itertools
+import time
 
 import numpy as np
 import pytest
@@ -116,6 +117,50 @@ def test_all_arrival_orders_give_identical_bits(orc, stream):
         assert all(req.parrived(q) for q in range(nparts))
         torch.cuda.synchronize()
         assert np.array_equal(as_u32(out.cpu().numpy()), want), perm
+    req.free()
+
+
+def test_partitions_arrive_before_the_epoch_ends(orc, stream):
+    """Readied partitions arrive by their own flags while later ones are
+    still unready (so the kernel cannot have retired), even with the
+    largest publish batch, and their output is final when the flag is seen:
+    a second stream reads it while the kernel still runs."""
+    P, n, nparts = 4, 256 * 1024 + 40, 8
+    say(f"case early arrival P={P} n={n} nparts={nparts}")
+    xs = synth.normal_f32(P, n, 41)
+    out = torch.full((n,), float("nan"), device=DEV)
+    req = new_request([n], pc.FLOAT32, pc.SUM, nparts, P, tile_elems=4096,
+                      publish_batch=64)
+    req.bind([[x.to(DEV) for x in xs]], [out], stream=stream)
+    want = as_u32(orc.sum_f32_f32([x.numpy() for x in xs]))
+    side = torch.cuda.Stream(DEV)
+    first = [5, 0, 3, 6]
+    req.start()
+    req.pready_list(first)
+    t0 = time.monotonic()
+    while not all(req.parrived(p) for p in first):
+        assert time.monotonic() - t0 < 2.0, "readied partitions never arrived"
+    assert not any(req.parrived(p) for p in range(nparts) if p not in first)
+    snaps = []
+    with torch.cuda.stream(side):
+        for p in first:
+            _, off, ln = req.part_info(p)
+            snaps.append((off, ln, out[off:off + ln].clone()))
+    done = torch.cuda.Event()
+    done.record(side)
+    t0 = time.monotonic()
+    while not done.query() and time.monotonic() - t0 < 2.0:
+        pass
+    concurrent = done.query()
+    req.pready_list([p for p in range(nparts) if p not in first])
+    req.wait()
+    torch.cuda.synchronize()
+    say(f"snapshot taken while the kernel ran: {concurrent}")
+    assert concurrent
+    for off, ln, snap in snaps:
+        assert np.array_equal(as_u32(snap.cpu().numpy()), want[off:off + ln])
+    assert np.array_equal(as_u32(out.cpu().numpy()), want)
+    assert all(req.parrived(p) for p in range(nparts))
     req.free()
 
 
