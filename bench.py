@@ -25,15 +25,17 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, published
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles",
                                "reduce_f32_p8_256MiB_traffic.json")
-KERNEL_SOURCES = ["persistent.hpp", "tiles.hpp", "reduce_impl.hpp",
-                  "reduce_f32.hip", "layout.hpp"]
+# what the counted launch depends on: the kernel's sources and the tuned
+# launch parameters
+KERNEL_SOURCES = ["csrc/persistent.hpp", "csrc/tiles.hpp",
+                  "csrc/reduce_impl.hpp", "csrc/reduce_f32.hip",
+                  "csrc/layout.hpp", "tuned_mi355x.txt"]
 
 
 def kernel_hash():
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2604_22228_amd", "csrc", f),
-                  "rb") as fh:
+        with open(os.path.join(ROOT, "paper_2604_22228_amd", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 

@@ -5,9 +5,12 @@ search and uses the results as defaults (environment variables override
 them), tuning graph and non-graph execution separately.  This tool does the
 same for the persistent reduce kernel: for each tuning key (dtype, op,
 ranks, graph mode, floor(log2(bytes per rank))) it times every
-(tile_elems, groups_per_cu) pair on seeded synthetic inputs and writes the
-fastest into the text table the library reads at request creation
-(tuned_mi355x.txt next to libpcoll.so, or PCOLL_TUNE_FILE).
+(tile_elems, groups_per_cu, interleave, waves per workgroup, publish batch)
+combination of its grid on seeded synthetic inputs and writes the fastest
+into the text table the library reads at request creation (tuned_mi355x.txt
+next to libpcoll.so, or PCOLL_TUNE_FILE).  Rows of one (dtype, op, ranks,
+graph) cover contiguous size ranges: each key's row reaches down to the
+next smaller key's.
 
 Timing: median device time of `reps` epochs (HIP events on the bound
 stream around start), every partition readied at once in a seeded random
@@ -16,6 +19,7 @@ order, after `warmup` epochs.  Run on the target GPU:
     python -m paper_2604_22228_amd.autotune --out paper_2604_22228_amd/tuned_mi355x.txt
 """
 import argparse
+import itertools
 import json
 import math
 import os
@@ -29,30 +33,38 @@ if ROOT not in sys.path:
 DTYPE_NAMES = {0: "i32", 1: "f32", 2: "bf16", 3: "e4m3"}
 OP_NAMES = {0: "sum", 1: "max"}
 
-TILES = (4096, 16384, 32768, 65536, 131072, 262144)
+TILES = (4096, 8192, 16384, 32768, 131072)
 GROUPS_PER_CU = (1, 2)
-INTERLEAVE = (1, 0)
+INTERLEAVE = (1,)
+WAVES = (4, 8)
+BATCH = (64,)
+FALLBACK = "* * * * 0 63 4096 1 1 8 64"
 
 
 def default_keys():
     """The configurations of the five workloads: (dtype, op, ranks, graph,
     list of per-bucket element counts, partitions per bucket)."""
+    from paper_2604_22228_amd import synth
     keys = []
     for k in range(10, 27, 2):  # the FP32 sweep, 4 KiB .. 256 MiB per rank
         keys.append((1, 0, 8, 0, [1 << k], 64))
     keys.append((1, 0, 4, 0, [262144], 8))          # plain workload
     keys.append((0, 0, 16, 0, [1 << 24], 256))      # int32 sum
     keys.append((0, 1, 16, 0, [1 << 24], 256))      # int32 max
+    keys.append((2, 0, 8, 1, list(synth.batched_bf16_counts()), 32))
+    keys.append((3, 0, 8, 1, list(synth.fp8_bucket_counts()), 32))
     return keys
 
 
 def time_config(pc, torch, synth, dtype, op, ranks, graph, counts, nparts,
-                tile, gpc, inter, warmup, reps, bufs):
+                choice, warmup, reps, bufs):
+    tile, gpc, inter, waves, batch = choice
     req = pc.Request(counts, dtype, op, nparts, ranks,
                      batched=len(counts) > 1)
     req.set_config(tile_elems=tile, min_tile_elems=min(tile, 4096),
                    groups_per_cu=gpc, graph=graph, groups=0,
-                   interleave=inter, guide=0)
+                   interleave=inter, guide=0, group_waves=waves,
+                   publish_batch=batch)
     ins, outs, rsc, osc, stream = bufs
     req.bind(ins, outs, rsc, osc, stream=stream)
     order = [int(p) for p in synth.permutation(req.nparts_total, 1)]
@@ -112,7 +124,7 @@ def make_buffers(pc, torch, synth, dtype, ranks, counts):
     return ins, outs, rsc, osc, torch.cuda.Stream(dev)
 
 
-def tune(keys, tiles, gpcs, warmup, reps, log=print, inters=INTERLEAVE):
+def tune(keys, grid, warmup, reps, log=print):
     import torch
 
     from paper_2604_22228_amd import pcoll as pc
@@ -124,35 +136,43 @@ def tune(keys, tiles, gpcs, warmup, reps, log=print, inters=INTERLEAVE):
         nbytes = sum(counts) * pc.ELEM_BYTES[dtype]
         lg = int(math.floor(math.log2(max(nbytes, 1))))
         best = None
-        for tile in tiles:
-            for gpc in gpcs:
-                for inter in inters:
-                    ms = time_config(pc, torch, synth, dtype, op, ranks,
-                                     graph, counts, nparts, tile, gpc, inter,
-                                     warmup, reps, bufs)
-                    log(json.dumps({"dtype": DTYPE_NAMES[dtype],
-                                    "op": OP_NAMES[op], "ranks": ranks,
-                                    "graph": graph, "log2_bytes": lg,
-                                    "tile": tile, "gpc": gpc,
-                                    "interleave": inter,
-                                    "ms": round(ms, 5)}))
-                    if best is None or ms < best[0]:
-                        best = (ms, tile, gpc, inter)
-        rows.append((DTYPE_NAMES[dtype], OP_NAMES[op], ranks, graph, lg, lg,
-                     best[1], best[2], best[3], best[0]))
+        for choice in itertools.product(*grid):
+            ms = time_config(pc, torch, synth, dtype, op, ranks, graph,
+                             counts, nparts, choice, warmup, reps, bufs)
+            log(json.dumps({"dtype": DTYPE_NAMES[dtype],
+                            "op": OP_NAMES[op], "ranks": ranks,
+                            "graph": graph, "log2_bytes": lg,
+                            "tile": choice[0], "gpc": choice[1],
+                            "interleave": choice[2], "waves": choice[3],
+                            "batch": choice[4], "ms": round(ms, 5)}))
+            if best is None or ms < best[0]:
+                best = (ms, choice)
+        rows.append((DTYPE_NAMES[dtype], OP_NAMES[op], ranks, graph, lg,
+                     best[1], best[0]))
         del bufs
         torch.cuda.empty_cache()
     return rows
 
 
 def write_table(rows, path):
+    """One line per key; the keys of one (dtype, op, ranks, graph) cover
+    contiguous ranges of log2(bytes per rank), the largest up to 63."""
+    groups = {}
+    for r in rows:
+        groups.setdefault(r[:4], []).append(r)
     lines = ["# Tuned launch parameters of libpcoll on MI355X (gfx950), "
              "written by paper_2604_22228_amd/autotune.py.",
              "# dtype op ranks graph log2_lo log2_hi tile_elems "
-             "groups_per_cu interleave   # median kernel ms"]
-    for d, o, r, g, lo, hi, t, gpc, il, ms in rows:
-        lines.append(f"{d} {o} {r} {g} {lo} {hi} {t} {gpc} {il}   # {ms:.4f}")
-    lines.append("* * * * 0 63 131072 1 1   # fallback")
+             "groups_per_cu interleave waves batch   # median kernel ms"]
+    for key, rs in groups.items():
+        rs = sorted(rs, key=lambda r: r[4])
+        lo = 0
+        for i, (d, o, rk, g, lg, (t, gpc, il, w, b), ms) in enumerate(rs):
+            hi = 63 if i == len(rs) - 1 else lg
+            lines.append(f"{d} {o} {rk} {g} {lo} {hi} {t} {gpc} {il} {w} {b}"
+                         f"   # {ms:.4f} at 2^{lg} B")
+            lo = hi + 1
+    lines.append(FALLBACK + "   # fallback")
     with open(path, "w") as f:
         f.write("\n".join(lines) + "\n")
 
@@ -167,10 +187,10 @@ def main():
                     help="a reduced grid (for a smoke run)")
     args = ap.parse_args()
     keys = default_keys()
-    tiles, gpcs = TILES, GROUPS_PER_CU
+    grid = [TILES, GROUPS_PER_CU, INTERLEAVE, WAVES, BATCH]
     if args.quick:
-        keys, tiles, gpcs = keys[-4:-2], (16384, 131072), (1,)
-    rows = tune(keys, tiles, gpcs, args.warmup, args.reps,
+        keys, grid = keys[-6:-4], [(16384, 131072), (1,), (1,), (4,), (64,)]
+    rows = tune(keys, grid, args.warmup, args.reps,
                 log=lambda s: print(s, flush=True))
     write_table(rows, args.out)
     print(f"wrote {args.out} ({len(rows)} rows)", flush=True)
