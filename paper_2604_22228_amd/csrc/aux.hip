@@ -38,7 +38,7 @@ __global__ __launch_bounds__(256) void pready_kernel(PreadyArgs a) {
   const uint32_t first = blockIdx.x * 256u;
   const uint32_t cnt = a.n - first < 256u ? a.n - first : 256u;
   if (threadIdx.x == 0)
-    base = __hip_atomic_fetch_add(&a.ctr->dreserve, (uint64_t)cnt,
+    base = __hip_atomic_fetch_add(&a.ring->dreserve, (uint64_t)cnt,
                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
   if (i < a.n) {
@@ -53,15 +53,6 @@ hipError_t launch_pready(const PreadyArgs& a, hipStream_t s) {
   if (a.n == 0) return hipSuccess;
   hipLaunchKernelGGL(pready_kernel, dim3((a.n + 255u) / 256u), dim3(256), 0,
                      s, a);
-  return hipGetLastError();
-}
-
-__global__ __launch_bounds__(256) void reset_kernel(ResetArgs a) {
-  dev::reset_epoch(a);
-}
-
-hipError_t launch_reset(const ResetArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

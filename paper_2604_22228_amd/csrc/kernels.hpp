@@ -30,8 +30,6 @@ hipError_t launch_reduce(const ReduceArgs& a, int dtype, int op, bool comp,
 // Device-side readiness: appends `a.n` partition ids to the device ready
 // ring.
 hipError_t launch_pready(const PreadyArgs& a, hipStream_t s);
-// Clears an epoch's counters before its reduce launch (same stream).
-hipError_t launch_reset(const ResetArgs& a, hipStream_t s);
 // Producer-side packing: FP32 -> bfloat16 (RNE), FP32 -> e4m3 + per-256
 // FP32 scales.
 hipError_t launch_pack_bf16(const float* src, uint16_t* dst, size_t n,

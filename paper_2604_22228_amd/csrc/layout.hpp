@@ -60,27 +60,34 @@ struct HostShared {
   uint32_t reserved[27];
 };
 
-// Device-memory counters of one request; each group on its own 128-B line
-// so that polling one does not contend with atomics on another.  The reset
-// kernel that precedes every reduce launch clears claim, qstate, the ingest
-// group and error; the device ready list counters are never cleared (they
-// index a ring, see ReduceArgs::dlist).
-struct DevCounters {
+// Device-memory counters of one epoch, each group on its own 128-B line so
+// that polling one does not contend with atomics on another.  A request
+// holds two sets: epoch e uses set e & 1, and its launch clears the other
+// set (and the other half of the done counters) for epoch e + 1, which the
+// stream orders after it.  So no separate reset launch precedes the reduce
+// kernel.
+struct EpochCounters {
   uint32_t claim;                 // tiles handed out beyond the first round
   uint32_t pad0[31];
   uint64_t qstate;                // (queue entries << 32) | queued tiles
   uint32_t pad1[30];
   uint32_t ilock;                 // ingest lock (0 free, 1 held)
   uint32_t hconsumed;             // host ready entries already queued
-  uint64_t dconsumed;             // device ready entries already queued
   uint64_t queued_rows;           // rows of the partitions queued so far
-  uint32_t pad2[26];
+  uint32_t pad2[28];
   uint32_t error;                 // first error seen this epoch
-  uint32_t epoch;                 // epoch of the running launch
-  uint32_t pad3[30];
-  uint64_t dreserve;              // device ready entries ever reserved
-  uint32_t pad4[30];
+  uint32_t pad3[31];
 };
+
+// Counters of the device ready ring, never cleared (they number its
+// entries across epochs, see ReduceArgs::dlist).
+struct RingCounters {
+  uint64_t dconsumed;             // device ready entries already queued
+  uint32_t pad0[30];
+  uint64_t dreserve;              // device ready entries ever reserved
+  uint32_t pad1[30];
+};
+
 // Error codes a kernel can leave in HostShared::status.
 enum KernelStatus : uint32_t {
   kStatusOk = 0,
@@ -93,13 +100,15 @@ struct ReduceArgs {
   const BucketDesc* buckets;
   const PartDesc* parts;
   QEntry* queue;          // [nparts_total]
-  uint32_t* done;         // [nparts_total] finished tiles per partition
+  uint32_t* done;         // [2][nparts_total] finished tiles per
+                          // partition, one half per epoch parity
   uint32_t* queued;       // [nparts_total] epoch stamp once queued
   uint32_t* tile_hits;    // [nparts_total] debug: tiles reduced, or null
   uint64_t* dlist;        // [nparts_total] device ready ring: entry number
                           // c lives in slot c % nparts_total as
                           // ((uint32)c << 32) | part
-  DevCounters* ctr;
+  EpochCounters* ctr;     // [2], one set per epoch parity
+  RingCounters* ring;
   HostShared* host;       // device-visible address of the host struct
   const uint32_t* hlist;  // device-visible host ready list
   uint32_t* arrived;      // device-visible arrived stamps
@@ -115,7 +124,8 @@ struct ReduceArgs {
   uint32_t* tile_counts;   // [nparts_total] debug: tiles chosen, or null
   uint32_t guide;          // guided-scheduling divisor f (0 = fixed tiles)
   uint32_t publish_batch;  // finished tiles a workgroup publishes together
-  uint32_t reserved;
+  uint32_t epoch;          // stamp of this launch, or 0: read it from the
+                           // host struct (a graph replays fixed arguments)
   uint64_t timeout_ticks; // device wall-clock ticks before giving up
 };
 
@@ -124,14 +134,8 @@ struct PreadyArgs {
   uint32_t n;
   uint32_t capacity;      // slots in dlist (= partitions of the request)
   uint64_t* dlist;
-  DevCounters* ctr;
+  RingCounters* ring;
 };
 
-struct ResetArgs {
-  DevCounters* ctr;
-  const HostShared* host;  // device-visible address
-  uint32_t* done;
-  uint32_t nparts_total;
-};
 
 }  // namespace pcoll

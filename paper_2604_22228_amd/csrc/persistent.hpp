@@ -1,9 +1,9 @@
 // Device side of the persistent partitioned reduction (gfx950, wave64).
 //
-// One launch serves one epoch of a request; a one-workgroup reset kernel
-// runs just before it on the same stream (or in the same graph) and clears
-// the epoch's counters, so no wavefront of the reduce kernel ever has to
-// find out that it is the last one.  Every wavefront is an independent
+// One launch serves one epoch of a request.  The epoch's counters were
+// cleared by the previous launch (two counter sets alternate by epoch
+// parity), so no wavefront ever has to find out that it is the last one,
+// and no other launch precedes the reduce kernel.  Every wavefront is an independent
 // worker; none ever waits for another, so the launch needs no co-residency
 // and drains even if it is larger than the machine.  The worker is a
 // workgroup of up to kMaxWavesPerGroup wavefronts that reduce the rows of one
@@ -168,7 +168,7 @@ __device__ __forceinline__ void queue_append(const ReduceArgs& a,
 // at most one wavefront at a time reads host memory over the bus.
 __device__ __forceinline__ bool try_ingest(const ReduceArgs& a, uint32_t epoch) {
   const uint32_t lane = lane_id();
-  DevCounters* c = a.ctr;
+  EpochCounters* c = a.ctr;
   uint32_t got = 0;
   if (lane == 0) {
     uint32_t expect = 0;
@@ -178,12 +178,18 @@ __device__ __forceinline__ bool try_ingest(const ReduceArgs& a, uint32_t epoch) 
   }
   if (!uni(got)) return false;
 
-  uint32_t hcons = uni(ld_rlx(&c->hconsumed));
-  uint64_t dcons = uni64(ld_rlx64(&c->dconsumed));
-  uint32_t hc = uni(ld_acq_sys(&a.host->hcount));
-  uint64_t dr = uni64(ld_acq64(&c->dreserve));
   uint64_t qs = uni64(ld_rlx64(&c->qstate));
   uint32_t qcount = (uint32_t)(qs >> 32), qtiles = (uint32_t)qs;
+  // every partition queued: whatever the lists hold now belongs to the next
+  // epoch (its readiness may be signalled while this launch drains)
+  if (qcount >= a.nparts_total) {
+    if (lane == 0) st_rel(&c->ilock, 0u);
+    return false;
+  }
+  uint32_t hcons = uni(ld_rlx(&c->hconsumed));
+  uint64_t dcons = uni64(ld_rlx64(&a.ring->dconsumed));
+  uint32_t hc = uni(ld_acq_sys(&a.host->hcount));
+  uint64_t dr = uni64(ld_acq64(&a.ring->dreserve));
   uint64_t qrows = uni64(ld_rlx64(&c->queued_rows));
   const uint32_t qtiles0 = qtiles;
   if (hc > a.nparts_total) hc = a.nparts_total;
@@ -220,7 +226,7 @@ __device__ __forceinline__ bool try_ingest(const ReduceArgs& a, uint32_t epoch) 
   }
 
   st_rlx(&c->hconsumed, hcons);
-  st_rlx64(&c->dconsumed, dcons);
+  st_rlx64(&a.ring->dconsumed, dcons);
   st_rlx64(&c->queued_rows, qrows);
   st_rel64(&c->qstate, ((uint64_t)qcount << 32) | qtiles);
   if (lane == 0) st_rel(&c->ilock, 0u);
@@ -343,8 +349,8 @@ __device__ __forceinline__ void locate(const ReduceArgs& a, uint32_t t,
 // every claimed tile is reduced), and the kernel's end makes all its stores
 // visible, so the host counts every partition as arrived once the launch
 // has retired cleanly.  That saves the burst of releases at the end, which
-// would serialize on each XCD.  The reset kernel clears the done counters
-// these tiles leave partial.
+// would serialize on each XCD.  The done counters these tiles leave
+// partial are cleared by the next launch, for the one after it.
 struct Pending {
   uint32_t part;
   uint32_t nt;
@@ -404,16 +410,46 @@ struct TileJob {
   uint32_t nt;    // tiles of the partition
 };
 
+// Clears the counter set and done counters of the other epoch parity, for
+// the next launch: the previous launch, which used them, has retired (the
+// stream orders launches), and the next one starts only after this one.
+// Every workgroup clears its share of the done counters; workgroup 0 the
+// counter set.
+__device__ __forceinline__ void clear_next_epoch(const ReduceArgs& args,
+                                                 uint32_t epoch) {
+  const uint32_t other = (epoch & 1u) ^ 1u;
+  uint32_t* done = args.done + (size_t)other * args.nparts_total;
+  for (uint32_t p = blockIdx.x * 64u + lane_id(); p < args.nparts_total;
+       p += args.total_groups * 64u)
+    st_rlx(&done[p], 0u);
+  if (blockIdx.x == 0 && lane_id() == 0) {
+    EpochCounters* c = args.ctr + other;
+    st_rlx(&c->claim, 0u);
+    st_rlx64(&c->qstate, 0ull);
+    st_rlx(&c->ilock, 0u);
+    st_rlx(&c->hconsumed, 0u);
+    st_rlx64(&c->queued_rows, 0ull);
+    st_rlx(&c->error, 0u);
+  }
+}
+
 // The worker loop of one workgroup.  Tile::run<P>(bucket, partition offset,
 // partition length, tile index, tiles of the partition, interleave,
 // wavefront, wavefronts) reduces this wavefront's rows of a tile.
 template <class Tile, int P>
-__device__ __forceinline__ void persistent_loop(const ReduceArgs& a) {
+__device__ __forceinline__ void persistent_loop(const ReduceArgs& args) {
   __shared__ TileJob job;
   __shared__ Pending pend[kMaxPublishBatch];
   const uint32_t wave = threadIdx.x / 64u;
   const uint32_t nwaves = blockDim.x / 64u;
-  const uint32_t epoch = uni(ld_acq(&a.ctr->epoch));
+  // only wavefront 0 runs the protocol and needs the epoch
+  uint32_t epoch = 0;
+  if (wave == 0)
+    epoch = args.epoch ? args.epoch : uni(ld_acq_sys(&args.host->epoch));
+  ReduceArgs a = args;
+  a.ctr = args.ctr + (epoch & 1u);
+  a.done = args.done + (size_t)(epoch & 1u) * args.nparts_total;
+  if (wave == 0) clear_next_epoch(args, epoch);
   const uint64_t t0 = wall_clock64();
   uint32_t cursor = 0, prev_end = 0;
   uint32_t t = blockIdx.x;  // first round: tile = workgroup number
@@ -457,25 +493,6 @@ __device__ __forceinline__ void persistent_loop(const ReduceArgs& a) {
       t = uni(next);
     }
   }
-}
-
-// Clears the counters of an epoch before its reduce launch (one workgroup)
-// and copies the epoch stamp from host memory into device memory.
-__device__ __forceinline__ void reset_epoch(const ResetArgs& a) {
-  DevCounters* c = a.ctr;
-  if (threadIdx.x == 0) {
-    st_rlx(&c->claim, 0u);
-    st_rlx64(&c->qstate, 0ull);
-    st_rlx(&c->ilock, 0u);
-    st_rlx(&c->hconsumed, 0u);
-    st_rlx64(&c->queued_rows, 0ull);
-    st_rlx(&c->error, 0u);
-    st_rlx(&c->epoch, ld_acq_sys(&a.host->epoch));
-  }
-  // tiles that complete with the launch, and an abandoned epoch, leave
-  // partial done counts behind
-  for (uint32_t p = threadIdx.x; p < a.nparts_total; p += blockDim.x)
-    st_rlx(&a.done[p], 0u);
 }
 
 // ------------------------------------------------------ memory streaming

@@ -147,14 +147,16 @@ struct pcoll_req_s {
   void* arena = nullptr;
   PartDesc* d_parts = nullptr;
   QEntry* d_queue = nullptr;
-  uint32_t* d_done = nullptr;
+  uint32_t* d_done = nullptr;     // [2][nparts_total]
   uint32_t* d_queued = nullptr;
   uint32_t* d_hits = nullptr;
   uint32_t* d_tiles = nullptr;
   uint64_t* d_dlist = nullptr;
-  DevCounters* d_ctr = nullptr;
+  EpochCounters* d_ctr = nullptr;  // [2]
+  RingCounters* d_ring = nullptr;
 
   hipStream_t stream = nullptr;
+  hipStream_t launch_stream = nullptr;  // stream of the last launch
   bool bound = false;
   Binding* cur = nullptr;
   std::unique_ptr<LruCache<BindKey, Binding, BindKeyHash>> cache;
@@ -362,12 +364,13 @@ int create(const std::vector<uint64_t>& counts, int dtype, int op,
   };
   const size_t o_parts = take(sizeof(PartDesc) * np_total);
   const size_t o_queue = take(sizeof(QEntry) * np_total);
-  const size_t o_done = take(sizeof(uint32_t) * np_total);
+  const size_t o_done = take(sizeof(uint32_t) * 2 * np_total);
   const size_t o_queued = take(sizeof(uint32_t) * np_total);
   const size_t o_hits = take(sizeof(uint32_t) * np_total);
   const size_t o_tiles = take(sizeof(uint32_t) * np_total);
   const size_t o_dlist = take(sizeof(uint64_t) * np_total);
-  const size_t o_ctr = take(sizeof(DevCounters));
+  const size_t o_ctr = take(2 * sizeof(EpochCounters));
+  const size_t o_ring = take(sizeof(RingCounters));
   e = hipMalloc(&r->arena, off);
   if (e != hipSuccess) return e == hipErrorOutOfMemory ? PCOLL_ERR_NOMEM
                                                        : hip_fail(e, "hipMalloc");
@@ -386,7 +389,8 @@ int create(const std::vector<uint64_t>& counts, int dtype, int op,
                     sizeof(PartDesc) * r->parts.size(),
                     hipMemcpyHostToDevice));
   r->d_dlist = reinterpret_cast<uint64_t*>(base + o_dlist);
-  r->d_ctr = reinterpret_cast<DevCounters*>(base + o_ctr);
+  r->d_ctr = reinterpret_cast<EpochCounters*>(base + o_ctr);
+  r->d_ring = reinterpret_cast<RingCounters*>(base + o_ring);
 
   HIP_TRY(hipStreamCreateWithFlags(&r->capture_stream, hipStreamNonBlocking));
   HIP_TRY(hipEventCreateWithFlags(&r->ev_end, hipEventDefault));
@@ -412,6 +416,7 @@ ReduceArgs make_args(const pcoll_req_s* r) {
   a.tile_hits = r->cfg.debug ? r->d_hits : nullptr;
   a.dlist = r->d_dlist;
   a.ctr = r->d_ctr;
+  a.ring = r->d_ring;
   a.host = r->host_dev;
   a.hlist = reinterpret_cast<const uint32_t*>(r->host_dev + 1);
   a.arrived = const_cast<uint32_t*>(a.hlist) + r->nparts_total;
@@ -431,15 +436,11 @@ ReduceArgs make_args(const pcoll_req_s* r) {
   return a;
 }
 
-// One epoch's launch: the reset kernel, then the persistent reduce kernel.
-int launch_direct(pcoll_req_t r, hipStream_t s) {
-  ResetArgs ra{};
-  ra.ctr = r->d_ctr;
-  ra.host = r->host_dev;
-  ra.done = r->d_done;
-  ra.nparts_total = r->nparts_total;
-  HIP_TRY(launch_reset(ra, s));
-  const ReduceArgs a = make_args(r);
+// One launch per epoch.  epoch == 0 makes the kernel read the stamp from
+// the host struct (for graphs, whose arguments are fixed at capture).
+int launch_direct(pcoll_req_t r, hipStream_t s, uint32_t epoch) {
+  ReduceArgs a = make_args(r);
+  a.epoch = epoch;
   HIP_TRY(launch_reduce(a, r->dtype, r->op, r->cfg.comp != 0, r->nranks,
                         r->groups, r->cfg.group_waves, s));
   return PCOLL_SUCCESS;
@@ -463,7 +464,7 @@ int launch_graph(pcoll_req_t r) {
     auto t0 = std::chrono::steady_clock::now();
     HIP_TRY(hipStreamBeginCapture(r->capture_stream,
                                   hipStreamCaptureModeThreadLocal));
-    int rc = launch_direct(r, r->capture_stream);
+    int rc = launch_direct(r, r->capture_stream, 0);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(r->capture_stream, &g);
     if (rc) {
@@ -723,9 +724,16 @@ int pcoll_start(pcoll_req_t r) {
   if (check_req(r)) return PCOLL_ERR_ARG;
   if (!r->bound || r->active) return PCOLL_ERR_STATE;
   HIP_TRY(hipSetDevice(r->device));
-  const uint32_t e = r->epoch + 1;
-  // the request's previous kernels are ordered before this launch on the
-  // stream, and a finished epoch no longer reads these words
+  // epoch 0 means "read the stamp from host memory" to the kernel, and the
+  // counter sets alternate by parity: after wrapping, continue at 2
+  uint32_t e = r->epoch + 1;
+  if (e == 0) e = 2;
+  // the previous launch may still be draining (its epoch completes when
+  // every partition has arrived): a launch on another stream must follow it
+  if (r->ev_end_recorded && r->launch_stream != r->stream)
+    HIP_TRY(hipStreamWaitEvent(r->stream, r->ev_end, 0));
+  // a draining launch has queued every partition, so it no longer reads
+  // the ready list or the abort word
   r->host->hcount = 0;
   r->host->abort = 0;
   __atomic_store_n(&r->host->epoch, e, __ATOMIC_RELEASE);
@@ -739,10 +747,11 @@ int pcoll_start(pcoll_req_t r) {
     HIP_TRY(hipEventRecord(r->ev_start, r->stream));
     r->ev_start_recorded = true;
   }
-  int rc = r->cfg.graph ? launch_graph(r) : launch_direct(r, r->stream);
+  int rc = r->cfg.graph ? launch_graph(r) : launch_direct(r, r->stream, e);
   if (rc) return rc;
   HIP_TRY(hipEventRecord(r->ev_end, r->stream));
   r->ev_end_recorded = true;
+  r->launch_stream = r->stream;
   r->epoch = e;
   r->active = true;
   r->epoch_ok = false;
@@ -810,7 +819,7 @@ int pcoll_pready_on_stream(pcoll_req_t r, const int* parts_dev, int n,
   a.n = (uint32_t)n;
   a.capacity = r->nparts_total;
   a.dlist = r->d_dlist;
-  a.ctr = r->d_ctr;
+  a.ring = r->d_ring;
   HIP_TRY(launch_pready(a, static_cast<hipStream_t>(stream)));
   return PCOLL_SUCCESS;
 }

@@ -509,6 +509,30 @@ def test_wait_on_stream_orders_consumer(orc, stream):
     req.free()
 
 
+def test_epochs_alternate_streams_and_modes(orc, stream):
+    """Consecutive epochs of one request on two streams, direct and graph
+    launches mixed: each launch follows the previous one even across
+    streams (the counter sets alternate by epoch parity), and every epoch's
+    output is exact."""
+    P, n, nparts = 4, 300 * 1024 + 5, 6
+    say(f"case alternating streams P={P} n={n} nparts={nparts}")
+    xs = synth.normal_f32(P, n, 61)
+    dx = [x.to(DEV) for x in xs]
+    out = torch.empty(n, device=DEV)
+    want = as_u32(orc.sum_f32_f32([x.numpy() for x in xs]))
+    other = torch.cuda.Stream(DEV)
+    req = new_request([n], pc.FLOAT32, pc.SUM, nparts, P, tile_elems=4096)
+    for i in range(8):
+        s = stream if i % 2 == 0 else other
+        req.set_config(graph=(i // 2) % 2)
+        req.bind([dx], [out], stream=s)
+        out.fill_(float("nan"))
+        torch.cuda.synchronize()
+        run_epoch(req, synth.permutation(nparts, 61 + i), s)
+        assert np.array_equal(as_u32(out.cpu().numpy()), want), i
+    req.free()
+
+
 def test_rebind_hits_cache(orc, stream):
     P, n = 2, 4096
     a = [x.to(DEV) for x in synth.normal_f32(P, n, 1)]
