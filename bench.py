@@ -188,7 +188,7 @@ def extras(pc, torch, synth, warmup, reps):
     yb = [torch.empty(c, dtype=torch.int16, device=dev) for c in counts]
     rb = pc.Request(counts, pc.BFLOAT16, pc.SUM, nparts, P, batched=True)
     rb.bind(bf, yb, stream=stream)
-    order = [int(p) for p in synth.permutation(len(counts) * nparts, 3)]
+    order = synth.permutation(len(counts) * nparts, 3).astype("int32")
     h, d = time_requests(torch, [rb], [order], stream, warmup, reps)
     st = rb.stats()
     res["batched_bf16_graph"] = {
@@ -206,7 +206,7 @@ def extras(pc, torch, synth, warmup, reps):
         r.set_config(graph=0)
         r.bind([f32[b]], [yf[b]], stream=stream)
         reqs.append(r)
-        orders.append([int(p) for p in synth.permutation(nparts, b)])
+        orders.append(synth.permutation(nparts, b).astype("int32"))
     h, d = time_requests(torch, reqs, orders, stream, warmup, reps)
     res["plain_fp32_separate"] = {
         "host_ms": round(h, 4), "kernel_ms": round(d, 4),
@@ -241,7 +241,7 @@ def extras(pc, torch, synth, warmup, reps):
     xi = synth.uniform_i32(16, n4, synth.seed_for(4), -(1 << 20), 1 << 20,
                            device=dev)
     yi = torch.empty(n4, dtype=torch.int32, device=dev)
-    o4 = [int(p) for p in synth.permutation(256, synth.seed_for(4))]
+    o4 = synth.permutation(256, synth.seed_for(4)).astype("int32")
     for op, name in ((pc.SUM, "int32_sum_p16_64MiB"),
                      (pc.MAX, "int32_max_p16_64MiB")):
         r = pc.Request([n4], pc.INT32, op, 256, 16)
@@ -273,7 +273,7 @@ def extras(pc, torch, synth, warmup, reps):
            for c in counts5]
     r5 = pc.Request(counts5, pc.FP8_E4M3, pc.SUM, 32, 8, batched=True)
     r5.bind(q5, y5, s5, ys5, stream=stream)
-    o5 = [int(p) for p in synth.permutation(len(counts5) * 32, 5)]
+    o5 = synth.permutation(len(counts5) * 32, 5).astype("int32")
     h, d = time_requests(torch, [r5], [o5], stream, warmup, reps)
     n5 = sum(counts5)
     b5 = 9 * n5 + 9 * 4 * sum((c + 255) // 256 for c in counts5)
@@ -308,7 +308,7 @@ def main():
     P, n, nparts = args.ranks, 1 << args.log2n, args.nparts
     xs = synth.normal_f32(P, n, synth.seed_for(2), device=dev)
     out = torch.empty(n, dtype=torch.float32, device=dev)
-    order = [int(p) for p in synth.permutation(nparts, synth.seed_for(2))]
+    order = synth.permutation(nparts, synth.seed_for(2)).tolist()
     stream = torch.cuda.Stream(dev)
     req = pc.Request([n], pc.FLOAT32, pc.SUM, nparts, P)
     req.bind([xs], [out], stream=stream)

@@ -67,7 +67,7 @@ def time_config(pc, torch, synth, dtype, op, ranks, graph, counts, nparts,
                    publish_batch=batch)
     ins, outs, rsc, osc, stream = bufs
     req.bind(ins, outs, rsc, osc, stream=stream)
-    order = [int(p) for p in synth.permutation(req.nparts_total, 1)]
+    order = synth.permutation(req.nparts_total, 1).astype("int32")
     times = []
     for it in range(warmup + reps):
         e0 = torch.cuda.Event(enable_timing=True)

@@ -129,6 +129,8 @@ __device__ __forceinline__ void queue_append(const ReduceArgs& a,
                                              uint64_t& qrows) {
   const uint32_t lane = lane_id();
   valid = valid && part < a.nparts_total;
+  // the descriptor load does not wait for the stamp exchange
+  const uint32_t prows = valid ? a.parts[part].rows : 0u;
   if (valid) {
     // exactly once per epoch, whatever the number of pready calls
     uint32_t old = __hip_atomic_exchange(&a.queued[part], epoch,
@@ -136,7 +138,7 @@ __device__ __forceinline__ void queue_append(const ReduceArgs& a,
                                          __HIP_MEMORY_SCOPE_AGENT);
     valid = old != epoch;
   }
-  const uint32_t rows = valid ? a.parts[part].rows : 0u;
+  const uint32_t rows = valid ? prows : 0u;
   const uint32_t rincl = wave_incl_scan(rows);
   const uint64_t before = qrows + (rincl - rows);
   const uint64_t rem = a.total_rows > before ? a.total_rows - before : rows;
@@ -198,12 +200,23 @@ __device__ __forceinline__ bool try_ingest(const ReduceArgs& a, uint32_t epoch) 
     return false;
   }
 
-  // host ready list: hlist[hcons .. hc)
-  for (uint32_t base = hcons; base < hc; base += 64) {
-    uint32_t i = base + lane;
-    bool in = i < hc;
-    uint32_t p = in ? ld_rlx_sys(&a.hlist[i]) : 0u;
-    queue_append(a, epoch, in, p, qcount, qtiles, qrows);
+  // host ready list: hlist[hcons .. hc), read 256 entries per round trip
+  // over the bus; the queue state is published after every 64 entries, so
+  // that workers start on them while the rest is read
+  for (uint32_t base = hcons; base < hc; base += 256u) {
+    uint32_t p[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t i = base + 64u * k + lane;
+      p[k] = i < hc ? ld_rlx_sys(&a.hlist[i]) : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t b = base + 64u * k;
+      if (b >= hc) break;
+      queue_append(a, epoch, b + lane < hc, p[k], qcount, qtiles, qrows);
+      st_rel64(&c->qstate, ((uint64_t)qcount << 32) | qtiles);
+    }
   }
   hcons = hc > hcons ? hc : hcons;
 
@@ -300,12 +313,14 @@ __device__ __forceinline__ WaitResult wait_queued(const ReduceArgs& a,
 
 // Finds the queue entry covering tile t among entries [cursor, qcount).
 // cursor / prev_end (cum_end of entry cursor-1) only move forward, since a
-// worker's claims increase.
+// worker's claims increase; part / end hold the entry found last, so a
+// tile in the same partition as the previous one needs no queue read.
 __device__ __forceinline__ void locate(const ReduceArgs& a, uint32_t t,
                                        uint32_t qcount, uint32_t& cursor,
                                        uint32_t& prev_end, uint32_t& part,
                                        uint32_t& end) {
   const uint32_t lane = lane_id();
+  if (t < end) return;  // t >= prev_end: claims increase
   for (;;) {
     uint32_t i = cursor + lane;
     uint64_t e = i < qcount
@@ -452,6 +467,7 @@ __device__ __forceinline__ void persistent_loop(const ReduceArgs& args) {
   if (wave == 0) clear_next_epoch(args, epoch);
   const uint64_t t0 = wall_clock64();
   uint32_t cursor = 0, prev_end = 0;
+  uint32_t cur_part = 0, cur_end = 0;  // queue entry at cursor
   uint32_t t = blockIdx.x;  // first round: tile = workgroup number
   uint32_t next = 0;
   uint64_t qs = 0;          // queue state last acquired (wavefront 0)
@@ -463,10 +479,11 @@ __device__ __forceinline__ void persistent_loop(const ReduceArgs& args) {
         publish(a, pend, npend, epoch);
       });
       if (w == kReady) {
-        uint32_t end = 0;
-        locate(a, t, (uint32_t)(qs >> 32), cursor, prev_end, j.part, end);
+        locate(a, t, (uint32_t)(qs >> 32), cursor, prev_end, cur_part,
+               cur_end);
+        j.part = cur_part;
         j.lt = t - prev_end;
-        j.nt = end - prev_end;
+        j.nt = cur_end - prev_end;
         next = claim(a);  // in flight while the tile is reduced
       } else if (w == kStop) {
         retire(a, pend, npend);

@@ -171,6 +171,8 @@ struct pcoll_req_s {
   uint32_t scan = 0;            // first partition not yet seen arrived
   uint32_t hcount = 0;
   std::vector<uint32_t> stamp;  // epoch in which each partition was readied
+  std::vector<uint64_t> mark;   // call generation that last listed it
+  uint64_t mark_gen = 0;
   pcoll_stats_t stats{};
   uint64_t sig = 0;             // launch signature (config-dependent args)
 };
@@ -332,6 +334,7 @@ int create(const std::vector<uint64_t>& counts, int dtype, int op,
     }
   }
   r->stamp.assign(r->nparts_total, 0u);
+  r->mark.assign(r->nparts_total, 0u);
 
   HIP_TRY(hipGetDevice(&r->device));
   HIP_TRY(hipDeviceGetAttribute(&r->cus, hipDeviceAttributeMultiprocessorCount,
@@ -761,17 +764,15 @@ int pcoll_start(pcoll_req_t r) {
 }
 
 static int publish_ready(pcoll_req_t r, const int* parts, int n, int first) {
-  // validate everything first: all-or-nothing
+  // validate everything first: all-or-nothing, in one pass (a list entry
+  // seen earlier in the same call carries this call's mark)
+  const uint64_t gen = ++r->mark_gen;
   for (int i = 0; i < n; ++i) {
     const int p = parts ? parts[i] : first + i;
     if (p < 0 || (uint32_t)p >= r->nparts_total) return PCOLL_ERR_ARG;
     if (r->stamp[(size_t)p] == r->epoch) return PCOLL_ERR_STATE;
-  }
-  if (parts && n > 1) {  // duplicates within one list
-    std::vector<int> sorted(parts, parts + n);
-    std::sort(sorted.begin(), sorted.end());
-    if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
-      return PCOLL_ERR_ARG;
+    if (r->mark[(size_t)p] == gen) return PCOLL_ERR_ARG;  // duplicate
+    r->mark[(size_t)p] = gen;
   }
   for (int i = 0; i < n; ++i) {
     const int p = parts ? parts[i] : first + i;

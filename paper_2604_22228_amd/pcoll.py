@@ -11,6 +11,8 @@ tensors alive and passes their data pointers and the stream handle.
 import ctypes as C
 import os
 
+import numpy as np
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpcoll.so")
 
@@ -188,8 +190,18 @@ def pcoll_pready_range(h, first, last):
 
 
 def pcoll_pready_list(h, parts):
-    arr = (_i * len(parts))(*[int(p) for p in parts])
-    _check(load().pcoll_pready_list(h, len(parts), arr), "pcoll_pready_list")
+    """parts: a sequence of ints, or (zero-copy) a contiguous int32 numpy
+    array or ctypes int array."""
+    if isinstance(parts, np.ndarray):
+        if parts.dtype != np.int32 or not parts.flags.c_contiguous:
+            parts = np.ascontiguousarray(parts, dtype=np.int32)
+        n, arr = parts.size, parts.ctypes.data_as(C.POINTER(_i))
+    elif isinstance(parts, C.Array):
+        n, arr = len(parts), parts
+    else:
+        n = len(parts)
+        arr = (_i * n)(*[int(p) for p in parts])
+    _check(load().pcoll_pready_list(h, n, arr), "pcoll_pready_list")
 
 
 def pcoll_pready_on_stream(h, parts_dev, n, stream):

@@ -37,7 +37,7 @@ def _gather(ts, idx):
 
 def _run(req, nparts_total, seed, stream):
     req.start()
-    req.pready_list([int(p) for p in synth.permutation(nparts_total, seed)])
+    req.pready_list(synth.permutation(nparts_total, seed).astype("int32"))
     req.wait()
     torch.cuda.synchronize()
 

@@ -440,6 +440,12 @@ def test_state_machine_errors(stream):
         req.pready_list([0, 0])  # duplicate in the list
     assert e.value.code == pc.ERR_ARG
     with pytest.raises(pc.PcollError) as e:
+        req.pready_list(np.array([1, 0, 1], np.int32))  # apart, numpy
+    assert e.value.code == pc.ERR_ARG
+    with pytest.raises(pc.PcollError) as e:
+        req.pready_list(np.array([0, 2]))  # 2 already readied: nothing is
+    assert e.value.code == pc.ERR_STATE     # published, 0 stays unready
+    with pytest.raises(pc.PcollError) as e:
         pc.pcoll_free(req.h)  # active
     assert e.value.code == pc.ERR_STATE
     with pytest.raises(pc.PcollError) as e:
