@@ -147,6 +147,56 @@ def time_requests(torch, reqs, orders, stream, warmup, reps):
     return statistics.median(host), statistics.median(devt)
 
 
+def size_sweep(pc, torch, synth, stream):
+    """The message-size sweep: 8 ranks, FP32 sum, 2^k elements per rank
+    (k = 0..26, 4 B .. 256 MiB), 1 / 4 / 16 / 64 partitions readied in a
+    seeded random order with one list call.  Cold cache: a 1 GiB fill (4x
+    the 256 MB MALL) runs on the stream before every timed epoch, outside
+    the timed events.  Per point: median device us over the epochs (events
+    before start and after the readiness call, on the bound stream) and
+    effective GB/s = 36 * 2^k B / time."""
+    import statistics
+    dev = torch.device("cuda:0")
+    P = 8
+    big = synth.normal_f32(P, 1 << 26, synth.seed_for(2), device=dev)
+    out = torch.empty(1 << 26, device=dev)
+    flush = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    points, gate = [], []
+    for k in range(27):
+        n = 1 << k
+        xs = [b[:n] for b in big]
+        reps = 20 if k <= 22 else 10
+        for nparts in (1, 4, 16, 64):
+            req = pc.Request([n], pc.FLOAT32, pc.SUM, nparts, P)
+            req.bind([xs], [out[:max(n, 4)]], stream=stream)
+            order = synth.permutation(nparts, k * 100 + nparts) \
+                .astype("int32")
+            ts = []
+            for it in range(2 + reps):
+                pc.pcoll_probe_fill(flush, 4 << 28, 0, stream)
+                e0, e1 = _events(torch)
+                e0.record(stream)
+                req.start()
+                req.pready_list(order)
+                e1.record(stream)
+                req.wait()
+                if it >= 2:
+                    e1.synchronize()
+                    ts.append(e0.elapsed_time(e1))
+            req.free()
+            ms = statistics.median(ts)
+            gbps = 36 * n / (ms * 1e-3) / 1e9
+            points.append([k, nparts, round(ms * 1e3, 2), round(gbps, 1)])
+            if k >= 24:
+                gate.append(gbps)
+    del big, out, flush
+    torch.cuda.empty_cache()
+    return {"columns": ["log2_elements", "partitions", "device_us", "GBps"],
+            "points": points, "cold_cache": True,
+            "min_pct_hbm_peak_at_64MiB_and_up": round(
+                100 * min(gate) / HBM_PEAK_GBPS, 2)}
+
+
 def extras(pc, torch, synth, warmup, reps):
     """The other workloads, timed (correctness and error are the tests'
     job: the full-size GPU tests check them against the oracle)."""
@@ -154,6 +204,7 @@ def extras(pc, torch, synth, warmup, reps):
     stream = torch.cuda.Stream(dev)
     cur = torch.cuda.current_stream(dev)
     out = {"copy_probe": probe_copy(pc, torch, 10)}
+    out["size_sweep"] = size_sweep(pc, torch, synth, stream)
 
     # workload 1: 4 ranks, FP32, 262144 elements, 8 partitions in order
     xs = synth.uniform_f32(4, 262144, synth.seed_for(1), device=dev)
@@ -327,6 +378,7 @@ def main():
     evs = [(torch.cuda.Event(enable_timing=True),
             torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     torch.cuda.synchronize()
+    marks = []
     t0 = time.perf_counter()
     for e0, e1 in evs:
         e0.record(stream)
@@ -335,9 +387,15 @@ def main():
             req.pready(p)
         e1.record(stream)  # enqueued behind the kernel on its stream
         req.wait()
+        marks.append(time.perf_counter())
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
+    step_ms = sorted((b - a) * 1e3 for a, b in zip([t0] + marks[:-1], marks))
+    ttr = {"median": round(step_ms[len(step_ms) // 2], 4),
+           "mean": round(sum(step_ms) / len(step_ms), 4),
+           "p10": round(step_ms[len(step_ms) // 10], 4),
+           "p90": round(step_ms[(9 * len(step_ms)) // 10], 4)}
     kernel_ms = sum(a.elapsed_time(b) for a, b in evs) / args.steps
 
     algo = P * n * 4 + n * 4
@@ -368,7 +426,11 @@ def main():
                         f"random order",
             "ranks": P, "elements_per_rank": n, "partitions": nparts,
             "tile_elems": cfg.tile_elems, "groups": st.groups,
+            "group_waves": cfg.group_waves,
             "pct_hbm_peak": round(100 * value / HBM_PEAK_GBPS, 2),
+            "time_to_reduce_ms": ttr,
+            "cache": "cold by construction: 2.4 GB per step, 9x the "
+                     "256 MB MALL",
         },
         "roofline": {
             "bound": "hbm",

@@ -202,8 +202,11 @@ typedef struct {
   int timeout_ms;    /* device-side deadline of one epoch */
   int debug;         /* 1 = count tiles reduced per partition */
   int interleave;    /* tile layout: 0 = each tile is a contiguous range of
-                        its partition; 1 = tile j of n takes every n-th row
-                        (64 lanes x 16 bytes) starting at row j */
+                        its partition; otherwise tiles are interleaved in
+                        bands of B consecutive tiles (1: B = the launch's
+                        workgroups; n >= 2: B = n): tile j of a band of m
+                        tiles takes every m-th row (64 lanes x 16 bytes)
+                        of the band starting at its row j */
   int group_waves;   /* wavefronts per workgroup (1..8); they share each
                         tile's rows */
   int publish_batch; /* finished tiles a workgroup publishes with one

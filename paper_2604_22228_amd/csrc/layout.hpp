@@ -53,11 +53,10 @@ struct QEntry {
 struct HostShared {
   uint32_t epoch;         // host: stamp of the next / running epoch, stored
                           // before the launch
-  uint32_t hcount;        // host: entries in hlist this epoch (store-release)
   uint32_t abort;         // host: == epoch asks the kernel to give up
   uint32_t status;        // device: error code of epoch status_epoch
   uint32_t status_epoch;  // device: epoch the status belongs to
-  uint32_t reserved[27];
+  uint32_t reserved[28];
 };
 
 // Device-memory counters of one epoch, each group on its own 128-B line so
@@ -110,7 +109,10 @@ struct ReduceArgs {
   EpochCounters* ctr;     // [2], one set per epoch parity
   RingCounters* ring;
   HostShared* host;       // device-visible address of the host struct
-  const uint32_t* hlist;  // device-visible host ready list
+  const uint64_t* hlist;  // device-visible host ready list: entry i of an
+                          // epoch is ((uint64)epoch << 32) | part, so a
+                          // reader needs no count (stale entries carry an
+                          // older epoch)
   uint32_t* arrived;      // device-visible arrived stamps
   uint32_t nparts_total;
   uint32_t total_groups;   // workgroups of the launch
@@ -118,9 +120,8 @@ struct ReduceArgs {
   uint32_t row_elems;      // elements per row (1024 bytes per rank)
   uint32_t min_tile_rows;  // bounds of the rows per tile chosen at queueing
   uint32_t max_tile_rows;
-  uint32_t interleave;     // 0: tile = consecutive rows; 1: tile j of nt
-                           // takes rows j, j + nt, j + 2 nt, ... of its
-                           // partition
+  uint32_t interleave;     // tile layout: 0 = consecutive rows, B > 0 =
+                           // interleaved in bands of B tiles (RowSet)
   uint32_t* tile_counts;   // [nparts_total] debug: tiles chosen, or null
   uint32_t guide;          // guided-scheduling divisor f (0 = fixed tiles)
   uint32_t publish_batch;  // finished tiles a workgroup publishes together

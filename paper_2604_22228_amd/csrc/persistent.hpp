@@ -56,6 +56,9 @@ __device__ __forceinline__ uint32_t ld_acq_sys(const uint32_t* p) {
 __device__ __forceinline__ uint32_t ld_rlx_sys(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
+__device__ __forceinline__ uint64_t ld_rlx_sys64(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
 __device__ __forceinline__ uint32_t ld_acq(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -190,35 +193,42 @@ __device__ __forceinline__ bool try_ingest(const ReduceArgs& a, uint32_t epoch) 
   }
   uint32_t hcons = uni(ld_rlx(&c->hconsumed));
   uint64_t dcons = uni64(ld_rlx64(&a.ring->dconsumed));
-  uint32_t hc = uni(ld_acq_sys(&a.host->hcount));
   uint64_t dr = uni64(ld_acq64(&a.ring->dreserve));
   uint64_t qrows = uni64(ld_rlx64(&c->queued_rows));
   const uint32_t qtiles0 = qtiles;
-  if (hc > a.nparts_total) hc = a.nparts_total;
-  if (hc <= hcons && dr <= dcons) {
-    if (lane == 0) st_rel(&c->ilock, 0u);
-    return false;
-  }
 
-  // host ready list: hlist[hcons .. hc), read 256 entries per round trip
-  // over the bus; the queue state is published after every 64 entries, so
-  // that workers start on them while the rest is read
-  for (uint32_t base = hcons; base < hc; base += 256u) {
-    uint32_t p[4];
+  // host ready list: entries hcons.. carrying this epoch's tag, read 256
+  // per round trip over the bus; the queue state is published after every
+  // 64 entries, so that workers start on them while the rest is read
+  for (bool more = hcons < a.nparts_total; more;) {
+    uint64_t v[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const uint32_t i = base + 64u * k + lane;
-      p[k] = i < hc ? ld_rlx_sys(&a.hlist[i]) : 0u;
+      const uint32_t i = hcons + 64u * k + lane;
+      v[k] = i < a.nparts_total ? ld_rlx_sys64(&a.hlist[i]) : 0ull;
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const uint32_t b = base + 64u * k;
-      if (b >= hc) break;
-      queue_append(a, epoch, b + lane < hc, p[k], qcount, qtiles, qrows);
+      // the list ends at the first entry of another epoch (not yet written)
+      const bool ok = hcons + lane < a.nparts_total &&
+                      (uint32_t)(v[k] >> 32) == epoch;
+      const uint64_t bad = __ballot(!ok);
+      const uint32_t lim =
+          bad ? (uint32_t)(__ffsll((long long)bad) - 1) : 64u;
+      if (lim == 0) {
+        more = false;
+        break;
+      }
+      queue_append(a, epoch, lane < lim, (uint32_t)v[k], qcount, qtiles,
+                   qrows);
       st_rel64(&c->qstate, ((uint64_t)qcount << 32) | qtiles);
+      hcons += lim;
+      if (lim < 64u || hcons >= a.nparts_total) {
+        more = false;
+        break;
+      }
     }
   }
-  hcons = hc > hcons ? hc : hcons;
 
   // device ready ring: entry c sits in slot c % nparts_total, stored as
   // ((uint32)c << 32) | part; stop at the first reserved entry whose writer

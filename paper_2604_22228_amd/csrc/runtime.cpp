@@ -141,7 +141,7 @@ struct pcoll_req_s {
 
   HostShared* host = nullptr;      // host address of the pinned block
   HostShared* host_dev = nullptr;  // device address of the same block
-  uint32_t* hlist = nullptr;
+  uint64_t* hlist = nullptr;
   uint32_t* arrived = nullptr;
 
   void* arena = nullptr;
@@ -224,7 +224,7 @@ int validate_config(const pcoll_req_s* r, const pcoll_config_t& c) {
   if (c.graph != 0 && c.graph != 1) return PCOLL_ERR_ARG;
   if (c.timeout_ms < 1 || c.timeout_ms > 3600 * 1000) return PCOLL_ERR_ARG;
   if (c.debug != 0 && c.debug != 1) return PCOLL_ERR_ARG;
-  if (c.interleave != 0 && c.interleave != 1) return PCOLL_ERR_ARG;
+  if (c.interleave < 0 || c.interleave > (1 << 20)) return PCOLL_ERR_ARG;
   if (c.guide < 0 || c.guide > 64) return PCOLL_ERR_ARG;
   if (c.group_waves < 1 || c.group_waves > kMaxWavesPerGroup)
     return PCOLL_ERR_ARG;
@@ -241,6 +241,15 @@ int apply_config(pcoll_req_t r, const pcoll_config_t& c) {
   int rc = validate_config(r, c);
   if (rc) return rc;
   int groups = c.groups ? c.groups : c.groups_per_cu * r->cus;
+  // no more workgroups than the launch can have tiles (a small message
+  // does not dispatch a full grid of workers that would only wait)
+  const uint64_t tile_rows = std::max<uint64_t>(
+      1, (uint64_t)(c.guide ? c.min_tile_elems : c.tile_elems) /
+             row_elems(r->dtype));
+  uint64_t max_tiles = 0;
+  for (const PartDesc& p : r->parts)
+    max_tiles += p.rows ? (p.rows + tile_rows - 1) / tile_rows : 1;
+  if ((uint64_t)groups > max_tiles) groups = (int)max_tiles;
   if (groups < 1) groups = 1;
   rc = drain(r);
   if (rc) return rc;
@@ -265,7 +274,7 @@ pcoll_config_t default_config(const pcoll_req_s* r) {
   c.tile_elems = env_int("PCOLL_TILE", t.tile_elems);
   c.min_tile_elems = env_int("PCOLL_MIN_TILE", 4096);
   if (c.min_tile_elems > c.tile_elems) c.min_tile_elems = c.tile_elems;
-  c.interleave = env_int("PCOLL_INTERLEAVE", t.interleave) ? 1 : 0;
+  c.interleave = env_int("PCOLL_INTERLEAVE", t.interleave);
   c.guide = env_int("PCOLL_GUIDE", 0);
   c.group_waves = env_int("PCOLL_GROUP_WAVES", t.group_waves);
   c.publish_batch = env_int("PCOLL_PUBLISH_BATCH", t.publish_batch);
@@ -344,7 +353,8 @@ int create(const std::vector<uint64_t>& counts, int dtype, int op,
   if (r->clock_khz <= 0) r->clock_khz = 100000;
 
   // host-coherent block: header, ready list, arrived flags
-  const size_t hbytes = sizeof(HostShared) + 2 * sizeof(uint32_t) * np_total;
+  const size_t hbytes =
+      sizeof(HostShared) + (sizeof(uint64_t) + sizeof(uint32_t)) * np_total;
   void* hp = nullptr;
   hipError_t e = hipHostMalloc(&hp, hbytes,
                                hipHostMallocCoherent | hipHostMallocMapped);
@@ -352,8 +362,8 @@ int create(const std::vector<uint64_t>& counts, int dtype, int op,
                                                        : hip_fail(e, "hipHostMalloc");
   std::memset(hp, 0, hbytes);
   r->host = static_cast<HostShared*>(hp);
-  r->hlist = reinterpret_cast<uint32_t*>(r->host + 1);
-  r->arrived = r->hlist + np_total;
+  r->hlist = reinterpret_cast<uint64_t*>(r->host + 1);
+  r->arrived = reinterpret_cast<uint32_t*>(r->hlist + np_total);
   void* dp = nullptr;
   HIP_TRY(hipHostGetDevicePointer(&dp, hp, 0));
   r->host_dev = static_cast<HostShared*>(dp);
@@ -421,8 +431,9 @@ ReduceArgs make_args(const pcoll_req_s* r) {
   a.ctr = r->d_ctr;
   a.ring = r->d_ring;
   a.host = r->host_dev;
-  a.hlist = reinterpret_cast<const uint32_t*>(r->host_dev + 1);
-  a.arrived = const_cast<uint32_t*>(a.hlist) + r->nparts_total;
+  a.hlist = reinterpret_cast<const uint64_t*>(r->host_dev + 1);
+  a.arrived = reinterpret_cast<uint32_t*>(
+      const_cast<uint64_t*>(a.hlist) + r->nparts_total);
   a.nparts_total = r->nparts_total;
   a.total_groups = (uint32_t)r->groups;
   a.total_rows = r->total_rows;
@@ -431,7 +442,9 @@ ReduceArgs make_args(const pcoll_req_s* r) {
       1, (uint64_t)r->cfg.min_tile_elems / row_elems(r->dtype));
   a.max_tile_rows = (uint32_t)std::max<uint64_t>(
       1, (uint64_t)r->cfg.tile_elems / row_elems(r->dtype));
-  a.interleave = (uint32_t)r->cfg.interleave;
+  // 1 = bands as wide as the launch: the tiles of one round of claims
+  a.interleave = r->cfg.interleave == 1 ? (uint32_t)r->groups
+                                         : (uint32_t)r->cfg.interleave;
   a.tile_counts = r->cfg.debug ? r->d_tiles : nullptr;
   a.guide = (uint32_t)r->cfg.guide;
   a.publish_batch = (uint32_t)r->cfg.publish_batch;
@@ -736,8 +749,8 @@ int pcoll_start(pcoll_req_t r) {
   if (r->ev_end_recorded && r->launch_stream != r->stream)
     HIP_TRY(hipStreamWaitEvent(r->stream, r->ev_end, 0));
   // a draining launch has queued every partition, so it no longer reads
-  // the ready list or the abort word
-  r->host->hcount = 0;
+  // the ready list or the abort word; list entries of earlier epochs carry
+  // older tags
   r->host->abort = 0;
   __atomic_store_n(&r->host->epoch, e, __ATOMIC_RELEASE);
   r->hcount = 0;
@@ -774,13 +787,15 @@ static int publish_ready(pcoll_req_t r, const int* parts, int n, int first) {
     if (r->mark[(size_t)p] == gen) return PCOLL_ERR_ARG;  // duplicate
     r->mark[(size_t)p] = gen;
   }
+  // each entry carries the epoch: the kernel takes the prefix of the list
+  // whose entries carry the current one, so no count is published
+  const uint64_t tag = (uint64_t)r->epoch << 32;
   for (int i = 0; i < n; ++i) {
     const int p = parts ? parts[i] : first + i;
     r->stamp[(size_t)p] = r->epoch;
-    r->hlist[r->hcount++] = (uint32_t)p;
+    __atomic_store_n(&r->hlist[r->hcount++], tag | (uint32_t)p,
+                     __ATOMIC_RELEASE);
   }
-  // the kernel reads the list up to the published length
-  __atomic_store_n(&r->host->hcount, r->hcount, __ATOMIC_RELEASE);
   return PCOLL_SUCCESS;
 }
 

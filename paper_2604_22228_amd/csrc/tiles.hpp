@@ -201,22 +201,32 @@ struct Unroll {
 };
 
 // Rows of a tile.  A partition is cut into rows of 64 lanes x 16 bytes
-// (kRowElems elements); tile lt of nt takes rows base + k * stride, k =
-// 0, 1, ...: consecutive tiles take ceil(rows / nt) consecutive rows,
-// interleaved tiles take every nt-th row, so that the workgroups working on
-// one partition stream through it side by side.
+// (kRowElems elements) and into nt tiles of rpt = ceil(rows / nt) rows;
+// tile lt takes rows base + k * stride, k = 0, 1, ...
+//  * consecutive layout (band 0): rows [lt rpt, (lt + 1) rpt);
+//  * banded interleave (band B > 0): tiles are grouped into bands of B
+//    consecutive tiles, band b owning rows [b B rpt, (b B + nb) rpt) (nb =
+//    its tile count, B but the last), and tile j of the band takes every
+//    nb-th row of it starting at row j.  The tiles running at the same time
+//    (consecutive claims) then stream side by side through one band, and
+//    each tile's rows stay within B rpt rows, so a tile touches few pages
+//    whatever the partition's size.
 struct RowSet {
   uint32_t base, stride, limit;  // rows base + k * stride, k < limit
-  // nrows: rows this set may use (whole rows); rows_per_tile: ceil(all rows
-  // of the partition / nt) for the consecutive layout
-  __device__ __forceinline__ RowSet(uint32_t lt, uint32_t nt,
-                                    uint32_t rows_per_tile, bool inter,
-                                    uint32_t nrows) {
-    if (inter) {
-      base = lt;
-      stride = nt;
-      limit = lt < nrows ? (nrows - 1 - lt) / nt + 1 : 0;
+  // nrows: rows this set may use (whole rows); rpt: ceil(all rows of the
+  // partition / nt)
+  __device__ __forceinline__ RowSet(uint32_t lt, uint32_t nt, uint32_t rpt,
+                                    uint32_t band, uint32_t nrows) {
+    if (band) {
+      const uint32_t b = lt / band, j = lt - b * band;
+      const uint32_t nb = min(band, nt - b * band);
+      const uint32_t b0 = b * band * rpt;
+      const uint32_t b1 = min(b0 + nb * rpt, nrows);
+      base = b0 + j;
+      stride = nb;
+      limit = base < b1 ? (b1 - 1 - base) / nb + 1 : 0;
     } else {
+      const uint32_t rows_per_tile = rpt;
       base = lt * rows_per_tile;
       stride = 1;
       limit = base < nrows ? min(rows_per_tile, nrows - base) : 0;
@@ -227,10 +237,15 @@ struct RowSet {
   }
 };
 
-// Whether tile lt owns row q (used for the ragged end of a partition).
+// Whether tile lt owns row q < nt * rpt (used for the ragged end of a
+// partition), in the layout of RowSet.
 __device__ __forceinline__ bool owns_row(uint32_t q, uint32_t lt, uint32_t nt,
-                                         uint32_t rows_per_tile, bool inter) {
-  return inter ? q % nt == lt : q / rows_per_tile == lt;
+                                         uint32_t rpt, uint32_t band) {
+  if (!band) return q / rpt == lt;
+  const uint64_t span = (uint64_t)band * rpt;  // rows of a full band
+  const uint32_t b = (uint32_t)(q / span);
+  const uint32_t nb = min(band, nt - b * band);
+  return b * band + (uint32_t)(q - b * span) % nb == lt;
 }
 
 template <class Acc, int Kind>
@@ -260,7 +275,7 @@ struct VecTile {
     const uint32_t full = nv / 64;                    // whole rows
     const uint32_t all = (uint32_t)((plen + kRowElems - 1) / kRowElems);
     const uint32_t rpt = (all + nt - 1) / nt;
-    const RowSet rows(lt, nt, rpt, inter != 0, full);
+    const RowSet rows(lt, nt, rpt, inter, full);
     constexpr int U = Unroll<P>::value;
     uint32_t k = wave;
     for (; k + (U - 1) * nwaves < rows.limit; k += U * nwaves) {
@@ -284,7 +299,8 @@ struct VecTile {
     }
     // the partition's ragged end: a partial row and the last < 16 bytes,
     // done by the tile that owns row `full`
-    if (wave != 0 || !owns_row(full, lt, nt, rpt, inter != 0)) return;
+    if (wave != 0 || full >= all || !owns_row(full, lt, nt, rpt, inter))
+      return;
     const uint32_t v = full * 64u + lane;
     if (v < nv) {
       uint4 x[P];
@@ -353,7 +369,7 @@ struct E4M3Tile {
     float* osc = bd->out_scale + poff / 256u;
     const uint32_t n = (uint32_t)plen;
     const uint32_t nrows = (n + kRowElems - 1) / kRowElems;
-    const RowSet rows(lt, nt, (nrows + nt - 1) / nt, inter != 0, nrows);
+    const RowSet rows(lt, nt, (nrows + nt - 1) / nt, inter, nrows);
     for (uint32_t k = wave; k < rows.limit; k += nwaves) {
       const uint32_t el = rows.row(k) * kRowElems + lane * 16u;
       const uint32_t blk = el / 256u;

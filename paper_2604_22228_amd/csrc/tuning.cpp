@@ -67,7 +67,7 @@ std::vector<TuneRow> parse_tune_table(const std::string& text) {
         !parse_int_or_any(f[7], &r.groups_per_cu))
       continue;
     if (nf >= 9 && (!parse_int_or_any(f[8], &r.interleave) ||
-                    (r.interleave != 0 && r.interleave != 1)))
+                    r.interleave < 0 || r.interleave > (1 << 20)))
       continue;
     if (nf >= 10 && (!parse_int_or_any(f[9], &r.group_waves) ||
                      r.group_waves < 1 || r.group_waves > 8))

@@ -11,7 +11,8 @@
 // dtype in {i32, f32, bf16, e4m3, *}, op in {sum, max, *}, ranks a number
 // or *, graph 0 / 1 / *, and [log2_lo, log2_hi] the range of
 // floor(log2(bytes per rank of the whole request)); the trailing interleave
-// (default 0), waves-per-workgroup (default 4) and publish-batch (default
+// (tile layout, default 0; 1 = bands of the launch's workgroups, n >= 2 =
+// bands of n tiles), waves-per-workgroup (default 4) and publish-batch (default
 // 16) columns may be omitted, from the right.  The first
 // matching row wins.  Host-only C++17.
 #pragma once

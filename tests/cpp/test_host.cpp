@@ -56,7 +56,7 @@ int main() {
       "i32 max 16 0 0 63 2048 3 1 4 8 extra\n"  // 12 fields: skipped
       "i32 max 16 0 0 63 2048 3 1 4 65\n"    // batch 65: skipped
       "i32 max 16 0 0 63 2048 3 1 9\n"        // 9 waves: skipped
-      "i32 sum 16 0 0 63 2048 3 2\n"        // interleave not 0/1: skipped
+      "i32 sum 16 0 0 63 2048 3 -1\n"       // negative interleave: skipped
       "i32 max 16 0 0 63 2048 3 1\n"
       "bf16 max 4 0 0 63 8192 1 1 2 32\n";
   auto rows = pcoll::parse_tune_table(t);

@@ -74,6 +74,15 @@ def test_fp32_sum2_small_grid(orc, stream, P):
                   tile_elems=2048)
 
 
+@pytest.mark.parametrize("band", [0, 1, 2, 3, 8, 1 << 20])
+def test_tile_layouts(orc, stream, band):
+    """Consecutive tiles (0) and interleaved bands of the launch's width
+    (1) or of 2, 3, 8 and more tiles than exist, with partitions of many
+    tiles and a ragged end: bitwise against the oracle."""
+    _f32_case(orc, stream, 3, 300 * 1024 + 77, 3, 90 + band % 97, False,
+              tile_elems=1024, min_tile_elems=1024, interleave=band)
+
+
 def test_workload1_plain_fp32(orc, stream):
     """4 ranks, FP32 sum, 262144 elements per rank, 8 partitions readied in
     order, uniform [-1, 1) inputs."""
@@ -292,9 +301,9 @@ def test_fp8_identity_covers_every_code(orc, stream, comp):
 
 
 @pytest.mark.parametrize("comp", [True, False])
-def test_fp8_reduce(orc, stream, comp):
+def test_fp8_reduce(orc, stream, comp, layout=None):
     P, n, nparts = 8, 256 * 997 + 131, 32
-    say(f"case fp8 comp={comp} P={P} n={n}")
+    say(f"case fp8 comp={comp} P={P} n={n} layout={layout}")
     xs = synth.normal_with_outliers_f32(P, n, synth.seed_for(5), 1e-2)
     packs = [pack_fp8_gpu(x.to(DEV)) for x in xs]
     opacks = [orc.e4m3_pack(x.numpy()) for x in xs]
@@ -304,7 +313,9 @@ def test_fp8_reduce(orc, stream, comp):
     nb = (n + 255) // 256
     out = torch.full((n,), 0x7F, dtype=torch.uint8, device=DEV)
     osc = torch.full((nb,), float("nan"), device=DEV)
-    req = new_request([n], pc.FP8_E4M3, pc.SUM, nparts, P, comp=int(comp))
+    cfg = {} if layout is None else dict(tile_elems=1024, interleave=layout)
+    req = new_request([n], pc.FP8_E4M3, pc.SUM, nparts, P, comp=int(comp),
+                      **cfg)
     req.bind([[q for q, _ in packs]], [out],
              rank_scales=[[s for _, s in packs]], out_scales=[osc],
              stream=stream)
@@ -324,6 +335,12 @@ def test_fp8_reduce(orc, stream, comp):
     tau = rep(gs) * 2.0 ** -6
     e = np.abs(yv - y64) / np.maximum(np.abs(deq).sum(axis=0), tau)
     assert e.max() <= 6e-2
+
+
+@pytest.mark.parametrize("band", [0, 1, 3])
+def test_fp8_tile_layouts(orc, stream, band):
+    """e4m3 with one-row tiles (8 per partition) in each tile layout."""
+    test_fp8_reduce(orc, stream, True, layout=band)
 
 
 # ------------------------------------------------------- batched and graphs
