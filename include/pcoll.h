@@ -131,7 +131,10 @@ int pcoll_pready(pcoll_req_t req, int part);
 /* Marks partitions first..last (inclusive) ready; all-or-nothing. */
 int pcoll_pready_range(pcoll_req_t req, int first, int last);
 
-/* Marks parts[0..n) ready; all-or-nothing (duplicates are an error). */
+/* Marks parts[0..n) ready; all-or-nothing (duplicates are an error).  The
+ * partitions of one call become ready at the same instant, so the library
+ * queues them in partition order (neighbouring partitions of a bucket are
+ * then reduced together), whatever their order in `parts`. */
 int pcoll_pready_list(pcoll_req_t req, int n, const int *parts);
 
 /* Device-side ready signal: enqueues on `stream` a kernel that marks the

@@ -173,6 +173,7 @@ struct pcoll_req_s {
   std::vector<uint32_t> stamp;  // epoch in which each partition was readied
   std::vector<uint64_t> mark;   // call generation that last listed it
   uint64_t mark_gen = 0;
+  std::vector<int> order;       // scratch: a list in partition order
   pcoll_stats_t stats{};
   uint64_t sig = 0;             // launch signature (config-dependent args)
 };
@@ -344,6 +345,7 @@ int create(const std::vector<uint64_t>& counts, int dtype, int op,
   }
   r->stamp.assign(r->nparts_total, 0u);
   r->mark.assign(r->nparts_total, 0u);
+  r->order.reserve(r->nparts_total);
 
   HIP_TRY(hipGetDevice(&r->device));
   HIP_TRY(hipDeviceGetAttribute(&r->cus, hipDeviceAttributeMultiprocessorCount,
@@ -786,6 +788,22 @@ static int publish_ready(pcoll_req_t r, const int* parts, int n, int first) {
     if (r->stamp[(size_t)p] == r->epoch) return PCOLL_ERR_STATE;
     if (r->mark[(size_t)p] == gen) return PCOLL_ERR_ARG;  // duplicate
     r->mark[(size_t)p] = gen;
+  }
+  // one call readies its partitions at the same instant, so their order in
+  // the call means nothing: queue them in partition order, which keeps the
+  // neighbouring partitions of a bucket together in the kernel's work queue
+  // (tiles claimed together then read neighbouring memory).  A long list is
+  // ordered by a scan of the marks, a short one by sorting a copy.
+  if (parts && n > 1) {
+    r->order.clear();
+    if ((uint64_t)n * 8u >= r->nparts_total) {
+      for (uint32_t p = 0; p < r->nparts_total; ++p)
+        if (r->mark[p] == gen) r->order.push_back((int)p);
+    } else {
+      r->order.assign(parts, parts + n);
+      std::sort(r->order.begin(), r->order.end());
+    }
+    parts = r->order.data();
   }
   // each entry carries the epoch: the kernel takes the prefix of the list
   // whose entries carry the current one, so no count is published
