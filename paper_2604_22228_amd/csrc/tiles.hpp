@@ -89,21 +89,21 @@ __device__ __forceinline__ uint32_t f_to_bf16(float f) {
 
 // e4m3 (OCP E4M3FN) encode of a binary32 value, round to nearest even,
 // saturating at +-448.
+// Both ranges are computed and one is selected, so that the encode has no
+// branch (a wavefront's lanes mix both ranges).
 __device__ __forceinline__ uint32_t f_to_e4m3(float v) {
   v = fminf(fmaxf(v, -448.0f), 448.0f);
-  const uint32_t sign = (__float_as_uint(v) >> 24) & 0x80u;
-  const float a = fabsf(v);
-  uint32_t code;
-  if (a < 0x1p-6f) {
-    // subnormal range: multiples of 2^-9 (a * 512 is exact), RNE to integer
-    code = (uint32_t)__builtin_rintf(a * 512.0f);
-  } else {
-    // keep 3 fraction bits, RNE on the binary32 encoding, rebias 127 -> 7
-    const uint32_t ua = __float_as_uint(a);
-    const uint32_t r = ua + 0x7ffffu + ((ua >> 20) & 1u);
-    code = (r >> 20) - (120u << 3);
-  }
-  return code | sign;
+  const uint32_t u = __float_as_uint(v);
+  const uint32_t sign = (u >> 24) & 0x80u;
+  const uint32_t ua = u & 0x7fffffffu;
+  const float a = __uint_as_float(ua);
+  // normal range: keep 3 fraction bits, RNE on the binary32 encoding,
+  // rebias 127 -> 7
+  const uint32_t rn = ua + 0x7ffffu + ((ua >> 20) & 1u);
+  const uint32_t cn = (rn >> 20) - (120u << 3);
+  // subnormal range: multiples of 2^-9 (a * 512 is exact), RNE to integer
+  const uint32_t cs = (uint32_t)__builtin_rintf(a * 512.0f);
+  return (a < 0x1p-6f ? cs : cn) | sign;
 }
 
 // ---------------------------------------------------- 16-byte vector tiles
@@ -351,6 +351,70 @@ template <bool COMP>
 struct E4M3Tile {
   static constexpr uint32_t kRowElems = 1024;  // 64 lanes x 16 codes
 
+  // One row: lane `lane` owns codes el .. el + 16 of block blk.  FULL: the
+  // whole row is inside the bucket (every lane has 16 codes), which spares
+  // the per-lane length checks; otherwise `have` codes (0..16).
+  template <int P, bool FULL>
+  __device__ __forceinline__ static void row(const uint8_t* const (&in)[P],
+                                             const float* const (&sc)[P],
+                                             uint8_t* out, float* osc,
+                                             uint32_t el, uint32_t have) {
+    const uint32_t blk = el / 256u;
+    uint4 raw[P];
+    float s_in[P];
+#pragma unroll
+    for (int r = 0; r < P; ++r) {
+      if (FULL) {
+        raw[r] = ld_stream(reinterpret_cast<const uint4*>(in[r] + el));
+        s_in[r] = sc[r][blk];
+      } else {
+        raw[r] = have ? load_codes(in[r] + el, have) : make_uint4(0, 0, 0, 0);
+        s_in[r] = have ? sc[r][blk] : 0.0f;
+      }
+    }
+    FSum<COMP> acc[16];
+    {
+      float d[16];
+      dec16(raw[0], s_in[0], d);
+#pragma unroll
+      for (int j = 0; j < 16; ++j) acc[j].init(d[j]);
+    }
+#pragma unroll
+    for (int r = 1; r < P; ++r) {
+      float d[16];
+      dec16(raw[r], s_in[r], d);
+#pragma unroll
+      for (int j = 0; j < 16; ++j) acc[j].add(d[j]);
+    }
+    float y[16];
+    float amax = 0.0f;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      y[j] = acc[j].get();
+      if (FULL || (uint32_t)j < have) amax = fmaxf(amax, fabsf(y[j]));
+    }
+    // max over the 16 lanes of the block
+    amax = fmaxf(amax, __shfl_xor(amax, 8, 16));
+    amax = fmaxf(amax, __shfl_xor(amax, 4, 16));
+    amax = fmaxf(amax, __shfl_xor(amax, 2, 16));
+    amax = fmaxf(amax, __shfl_xor(amax, 1, 16));
+    float so = amax / 448.0f;
+    if (!(so >= 0x1p-126f)) so = 1.0f;
+    const float inv = 1.0f / so;
+    uint32_t w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+      w[j >> 2] |= f_to_e4m3(y[j] * inv) << (8 * (j & 3));
+    if (FULL || have == 16u) {
+      st_stream(reinterpret_cast<uint4*>(out + el),
+                make_uint4(w[0], w[1], w[2], w[3]));
+    } else if (have) {
+      for (uint32_t j = 0; j < have; ++j)
+        out[el + j] = (uint8_t)(w[j >> 2] >> (8 * (j & 3)));
+    }
+    if ((FULL || have) && (lane_id() & 15u) == 0u) osc[blk] = so;
+  }
+
   template <int P>
   __device__ __forceinline__ static void run(const_ptr<BucketDesc> bd,
                                              uint64_t poff, uint64_t plen,
@@ -371,56 +435,14 @@ struct E4M3Tile {
     const uint32_t nrows = (n + kRowElems - 1) / kRowElems;
     const RowSet rows(lt, nt, (nrows + nt - 1) / nt, inter, nrows);
     for (uint32_t k = wave; k < rows.limit; k += nwaves) {
-      const uint32_t el = rows.row(k) * kRowElems + lane * 16u;
-      const uint32_t blk = el / 256u;
-      const uint32_t have = el < n ? (n - el < 16u ? n - el : 16u) : 0u;
-      uint4 raw[P];
-      float s_in[P];
-#pragma unroll
-      for (int r = 0; r < P; ++r) {
-        raw[r] = have ? load_codes(in[r] + el, have) : make_uint4(0, 0, 0, 0);
-        s_in[r] = have ? sc[r][blk] : 0.0f;
+      const uint32_t q = rows.row(k);
+      const uint32_t el = q * kRowElems + lane * 16u;
+      if ((q + 1u) * kRowElems <= n) {  // uniform: the row is whole
+        row<P, true>(in, sc, out, osc, el, 16u);
+      } else {
+        const uint32_t have = el < n ? (n - el < 16u ? n - el : 16u) : 0u;
+        row<P, false>(in, sc, out, osc, el, have);
       }
-      FSum<COMP> acc[16];
-      {
-        float d[16];
-        dec16(raw[0], s_in[0], d);
-#pragma unroll
-        for (int j = 0; j < 16; ++j) acc[j].init(d[j]);
-      }
-#pragma unroll
-      for (int r = 1; r < P; ++r) {
-        float d[16];
-        dec16(raw[r], s_in[r], d);
-#pragma unroll
-        for (int j = 0; j < 16; ++j) acc[j].add(d[j]);
-      }
-      float y[16];
-      float amax = 0.0f;
-#pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        y[j] = acc[j].get();
-        if ((uint32_t)j < have) amax = fmaxf(amax, fabsf(y[j]));
-      }
-      // max over the 16 lanes of the block
-      amax = fmaxf(amax, __shfl_xor(amax, 8, 16));
-      amax = fmaxf(amax, __shfl_xor(amax, 4, 16));
-      amax = fmaxf(amax, __shfl_xor(amax, 2, 16));
-      amax = fmaxf(amax, __shfl_xor(amax, 1, 16));
-      float so = amax / 448.0f;
-      if (!(so >= 0x1p-126f)) so = 1.0f;
-      const float inv = 1.0f / so;
-      uint32_t w[4] = {0u, 0u, 0u, 0u};
-#pragma unroll
-      for (int j = 0; j < 16; ++j) w[j >> 2] |= f_to_e4m3(y[j] * inv) << (8 * (j & 3));
-      if (have == 16u) {
-        st_stream(reinterpret_cast<uint4*>(out + el),
-                  make_uint4(w[0], w[1], w[2], w[3]));
-      } else if (have) {
-        for (uint32_t j = 0; j < have; ++j)
-          out[el + j] = (uint8_t)(w[j >> 2] >> (8 * (j & 3)));
-      }
-      if (have && (lane & 15u) == 0u) osc[blk] = so;
     }
   }
 };
