@@ -125,23 +125,42 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
 // the workgroups of the launch: large tiles while much work remains, small
 // ones near the end, so that workgroups run out of work at about the same
 // time.  With f = 0 every tile has max_tile_rows rows.
+//
+// A partition is appended once per epoch, whatever the number of ready
+// signals: queue_stamp() exchanges its queued stamp first and the append
+// keeps it only if the stamp was not this epoch's already.  queue_stamp()
+// issues nothing that waits, so the stamps of several chunks can be in
+// flight together before their appends.
+struct Stamped {
+  uint32_t part;
+  uint32_t rows;   // rows of the partition (when valid)
+  bool valid;
+};
+
+__device__ __forceinline__ Stamped queue_stamp(const ReduceArgs& a,
+                                               uint32_t epoch, bool valid,
+                                               uint32_t part) {
+  Stamped c{part, 0u, valid && part < a.nparts_total};
+  uint32_t old = epoch;
+  if (c.valid) {
+    // the descriptor load does not wait for the stamp exchange
+    c.rows = a.parts[part].rows;
+    old = __hip_atomic_exchange(&a.queued[part], epoch, __ATOMIC_RELAXED,
+                                __HIP_MEMORY_SCOPE_AGENT);
+  }
+  c.valid = c.valid && old != epoch;
+  return c;
+}
+
 __device__ __forceinline__ void queue_append(const ReduceArgs& a,
-                                             uint32_t epoch, bool valid,
-                                             uint32_t part, uint32_t& qcount,
+                                             const Stamped& c,
+                                             uint32_t& qcount,
                                              uint32_t& qtiles,
                                              uint64_t& qrows) {
   const uint32_t lane = lane_id();
-  valid = valid && part < a.nparts_total;
-  // the descriptor load does not wait for the stamp exchange
-  const uint32_t prows = valid ? a.parts[part].rows : 0u;
-  if (valid) {
-    // exactly once per epoch, whatever the number of pready calls
-    uint32_t old = __hip_atomic_exchange(&a.queued[part], epoch,
-                                         __ATOMIC_RELAXED,
-                                         __HIP_MEMORY_SCOPE_AGENT);
-    valid = old != epoch;
-  }
-  const uint32_t rows = valid ? prows : 0u;
+  const bool valid = c.valid;
+  const uint32_t part = c.part;
+  const uint32_t rows = valid ? c.rows : 0u;
   const uint32_t rincl = wave_incl_scan(rows);
   const uint64_t before = qrows + (rincl - rows);
   const uint64_t rem = a.total_rows > before ? a.total_rows - before : rows;
@@ -207,27 +226,32 @@ __device__ __forceinline__ bool try_ingest(const ReduceArgs& a, uint32_t epoch) 
       const uint32_t i = hcons + 64u * k + lane;
       v[k] = i < a.nparts_total ? ld_rlx_sys64(&a.hlist[i]) : 0ull;
     }
+    // the list ends at the first entry of another epoch (not yet written):
+    // lim[k] entries of chunk k, counted while the chunks before are whole
+    uint32_t lim[4];
+    uint32_t prefix = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      // the list ends at the first entry of another epoch (not yet written)
-      const bool ok = hcons + lane < a.nparts_total &&
+      const bool ok = hcons + 64u * k + lane < a.nparts_total &&
                       (uint32_t)(v[k] >> 32) == epoch;
       const uint64_t bad = __ballot(!ok);
-      const uint32_t lim =
-          bad ? (uint32_t)(__ffsll((long long)bad) - 1) : 64u;
-      if (lim == 0) {
-        more = false;
-        break;
-      }
-      queue_append(a, epoch, lane < lim, (uint32_t)v[k], qcount, qtiles,
-                   qrows);
-      st_rel64(&c->qstate, ((uint64_t)qcount << 32) | qtiles);
-      hcons += lim;
-      if (lim < 64u || hcons >= a.nparts_total) {
-        more = false;
-        break;
-      }
+      lim[k] = bad ? (uint32_t)(__ffsll((long long)bad) - 1) : 64u;
+      if (prefix != 64u * k) lim[k] = 0u;
+      prefix += lim[k];
     }
+    // stamps and descriptors of every chunk in flight together
+    Stamped st[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      st[k] = queue_stamp(a, epoch, lane < lim[k], (uint32_t)v[k]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (lim[k] == 0u) break;
+      queue_append(a, st[k], qcount, qtiles, qrows);
+      st_rel64(&c->qstate, ((uint64_t)qcount << 32) | qtiles);
+    }
+    hcons += prefix;
+    more = prefix == 256u && hcons < a.nparts_total;
   }
 
   // device ready ring: entry c sits in slot c % nparts_total, stored as
@@ -241,8 +265,8 @@ __device__ __forceinline__ bool try_ingest(const ReduceArgs& a, uint32_t epoch) 
     const uint64_t pending = __ballot(in && !ok);
     const uint32_t lim =
         pending ? (uint32_t)(__ffsll((long long)pending) - 1) : 64u;
-    queue_append(a, epoch, ok && lane < lim, (uint32_t)v, qcount, qtiles,
-                 qrows);
+    queue_append(a, queue_stamp(a, epoch, ok && lane < lim, (uint32_t)v),
+                 qcount, qtiles, qrows);
     const uint64_t avail = dr - dcons < 64u ? dr - dcons : 64u;
     dcons += lim < avail ? lim : avail;
     if (pending) break;
