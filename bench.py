@@ -19,6 +19,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -197,6 +199,151 @@ def size_sweep(pc, torch, synth, stream):
                 100 * min(gate) / HBM_PEAK_GBPS, 2)}
 
 
+def rank_readiness(pc, torch, synth, reps=5):
+    """Per-rank readiness against bulk readiness, with compute-bound
+    producers (the gradient-producing backward pass that per-rank readiness
+    is for): 8 ranks, FP32, 2^26 elements per rank, 8 partitions; the
+    producer of (rank, partition) is a 4096 x 512 by 512 x 2048 FP32 matrix
+    product written into that rank's partition (a synthetic workload,
+    outside the library), ranks spread over two streams.  overlapped: the
+    reduction starts first and each (rank, partition) is marked on the
+    device right after its product, so the kernel reduces each partition
+    while later ones are produced; run with the default grid and with 64
+    workgroups (a persistent kernel that waits holds registers the
+    producers could use).  bulk: every product first, then start, ready
+    everything, wait.  Host ms from the first product to the return of wait
+    (median); `identical`: every run gives the same output bits."""
+    import statistics
+    dev = torch.device("cuda:0")
+    P, n, nparts = 8, 1 << 26, 8
+    m, k, q = 4096, 512, 2048
+    gen = torch.Generator(device=dev).manual_seed(synth.seed_for(2) + 7)
+    a_ = [torch.randn(m, k, device=dev, generator=gen) for _ in range(P)]
+    b_ = torch.randn(k, q, device=dev, generator=gen)
+    xs = [torch.empty(n, device=dev) for _ in range(P)]
+    out = torch.empty(n, device=dev)
+    sig = [torch.cuda.Stream(dev) for _ in range(2)]
+    stream = torch.cuda.Stream(dev)
+    req = pc.Request([n], pc.FLOAT32, pc.SUM, nparts, P)
+    req.bind([xs], [out], stream=stream)
+    parts_dev = torch.arange(nparts, dtype=torch.int32, device=dev)
+    spans = [pc.pcoll_part_info(req.h, j)[1:] for j in range(nparts)]
+    assert all(ln == m * q for _, ln in spans)
+    allp = np.arange(nparts, dtype=np.int32)
+    torch.cuda.synchronize()
+
+    def produce(r, j):
+        off, ln = spans[j]
+        with torch.cuda.stream(sig[r % 2]):
+            torch.mm(a_[r], b_, out=xs[r][off:off + ln].view(m, q))
+
+    def overlapped():
+        req.start()
+        for j in range(nparts):
+            for r in range(P):
+                produce(r, j)
+                req.pready_rank_on_stream(r, parts_dev[j:j + 1], 1,
+                                          sig[r % 2])
+        req.wait()
+
+    def bulk():
+        for j in range(nparts):
+            for r in range(P):
+                produce(r, j)
+        for s_ in sig:
+            s_.synchronize()
+        req.start()
+        req.pready_list(allp)
+        req.wait()
+
+    res = {}
+    outs = []
+    for name, fn, groups in (("overlapped_ms", overlapped, 0),
+                             ("overlapped_64_groups_ms", overlapped, 64),
+                             ("bulk_ms", bulk, 0)):
+        req.set_config(groups=groups)
+        ts = []
+        for it in range(2 + reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            ts.append((time.perf_counter() - t0) * 1e3)
+        torch.cuda.synchronize()
+        outs.append(out.clone())
+        res[name] = round(statistics.median(ts[2:]), 4)
+    res["identical"] = all(bool(torch.equal(o, outs[0])) for o in outs)
+    req.free()
+    del a_, b_, xs, out, outs
+    torch.cuda.empty_cache()
+    res["speedup"] = round(res["bulk_ms"] / min(
+        res["overlapped_ms"], res["overlapped_64_groups_ms"]), 3)
+    res["workload"] = ("8 ranks, FP32, 2^26 elements per rank, 8 partitions, "
+                       "an 8.6 GFLOP FP32 product per rank and partition")
+    return res
+
+
+def graph_lifecycle(pc, torch, reps=20):
+    """Graph against direct launch over bucket counts (equal buckets, FP32,
+    8 ranks) at 2 MiB and 512 MiB per rank: bind (descriptor table upload),
+    first start (graph: capture + instantiate + launch), then per epoch the
+    host time of start and the device time of the epoch (medians)."""
+    import statistics
+    dev = torch.device("cuda:0")
+    P = 8
+    big = [torch.ones(1 << 27, device=dev) for _ in range(P)]
+    obig = torch.empty(1 << 27, device=dev)
+    stream = torch.cuda.Stream(dev)
+    rows = []
+    for total in (1 << 19, 1 << 27):  # elements per rank: 2 MiB, 512 MiB
+        for nb in (1, 8, 32, 128):
+            c = total // nb
+            counts = [c] * nb
+            ins = [[b[i * c:(i + 1) * c] for b in big] for i in range(nb)]
+            outs = [obig[i * c:(i + 1) * c] for i in range(nb)]
+            rec = {"bytes_per_rank": total * 4, "buckets": nb}
+            for graph in (1, 0):
+                req = pc.Request(counts, pc.FLOAT32, pc.SUM, 8, P,
+                                 batched=True)
+                req.set_config(graph=graph)
+                t0 = time.perf_counter()
+                req.bind(ins, outs, stream=stream)
+                t1 = time.perf_counter()
+                order = np.arange(req.nparts_total, dtype=np.int32)
+                req.start()
+                t2 = time.perf_counter()
+                req.pready_list(order)
+                req.wait()
+                hs, ds = [], []
+                for it in range(reps):
+                    e0, e1 = _events(torch)
+                    torch.cuda.synchronize()
+                    e0.record(stream)
+                    h0 = time.perf_counter()
+                    req.start()
+                    h1 = time.perf_counter()
+                    req.pready_list(order)
+                    e1.record(stream)
+                    req.wait()
+                    e1.synchronize()
+                    hs.append((h1 - h0) * 1e6)
+                    ds.append(e0.elapsed_time(e1))
+                st = req.stats()
+                key = "graph" if graph else "direct"
+                rec[key] = {"bind_ms": round((t1 - t0) * 1e3, 3),
+                            "first_start_ms": round((t2 - t1) * 1e3, 3),
+                            "start_us": round(statistics.median(hs), 1),
+                            "epoch_ms": round(statistics.median(ds), 4)}
+                if graph:
+                    rec[key]["capture_ms"] = round(st.last_capture_ms, 3)
+                    rec[key]["instantiate_ms"] = round(
+                        st.last_instantiate_ms, 3)
+                req.free()
+            rows.append(rec)
+    del big, obig
+    torch.cuda.empty_cache()
+    return rows
+
+
 def extras(pc, torch, synth, warmup, reps):
     """The other workloads, timed (correctness and error are the tests'
     job: the full-size GPU tests check them against the oracle)."""
@@ -205,6 +352,8 @@ def extras(pc, torch, synth, warmup, reps):
     cur = torch.cuda.current_stream(dev)
     out = {"copy_probe": probe_copy(pc, torch, 10)}
     out["size_sweep"] = size_sweep(pc, torch, synth, stream)
+    out["rank_readiness"] = rank_readiness(pc, torch, synth)
+    out["graph_lifecycle"] = graph_lifecycle(pc, torch)
 
     # workload 1: 4 ranks, FP32, 262144 elements, 8 partitions in order
     xs = synth.uniform_f32(4, 262144, synth.seed_for(1), device=dev)
@@ -235,20 +384,26 @@ def extras(pc, torch, synth, warmup, reps):
     torch.cuda.synchronize()
     n_el = sum(counts)
     res = {"buckets": len(counts), "elements_per_rank": n_el}
-    # (a) batched bf16, one persistent graph-replayed launch
+    # (a) batched bf16, one persistent launch per epoch: direct (the
+    # default) and replayed from a captured graph
     yb = [torch.empty(c, dtype=torch.int16, device=dev) for c in counts]
-    rb = pc.Request(counts, pc.BFLOAT16, pc.SUM, nparts, P, batched=True)
-    rb.bind(bf, yb, stream=stream)
     order = synth.permutation(len(counts) * nparts, 3).astype("int32")
-    h, d = time_requests(torch, [rb], [order], stream, warmup, reps)
-    st = rb.stats()
-    res["batched_bf16_graph"] = {
-        "host_ms": round(h, 4), "kernel_ms": round(d, 4),
-        "GBps": round(n_el * 2 * (P + 1) / d / 1e6, 1),
-        "graph": rb.config().graph, "graph_captures": st.graph_captures,
-        "capture_ms": round(st.last_capture_ms, 3),
-        "instantiate_ms": round(st.last_instantiate_ms, 3)}
-    rb.free()
+    for graph, key in ((0, "batched_bf16"), (1, "batched_bf16_graph")):
+        rb = pc.Request(counts, pc.BFLOAT16, pc.SUM, nparts, P,
+                        batched=True)
+        rb.set_config(graph=graph)
+        rb.bind(bf, yb, stream=stream)
+        h, d = time_requests(torch, [rb], [order], stream, warmup, reps)
+        st = rb.stats()
+        res[key] = {"host_ms": round(h, 4), "kernel_ms": round(d, 4),
+                    "GBps": round(n_el * 2 * (P + 1) / d / 1e6, 1),
+                    "graph": rb.config().graph}
+        if graph:
+            res[key].update({"graph_captures": st.graph_captures,
+                             "capture_ms": round(st.last_capture_ms, 3),
+                             "instantiate_ms": round(st.last_instantiate_ms,
+                                                     3)})
+        rb.free()
     # (b) plain fp32: one request per bucket, no graph
     yf = [torch.empty(c, device=dev) for c in counts]
     reqs, orders = [], []
@@ -275,14 +430,12 @@ def extras(pc, torch, synth, warmup, reps):
     rf = pc.Request(counts, pc.FLOAT32, pc.SUM, nparts, P, batched=True)
     rf.bind(f32, yf, stream=stream)
     h, d = time_requests(torch, [rf], [order], stream, warmup, reps)
-    res["batched_fp32_graph"] = {"host_ms": round(h, 4),
-                                 "kernel_ms": round(d, 4),
-                                 "GBps": round(n_el * 4 * (P + 1) / d / 1e6,
-                                               1)}
+    res["batched_fp32"] = {"host_ms": round(h, 4), "kernel_ms": round(d, 4),
+                           "GBps": round(n_el * 4 * (P + 1) / d / 1e6, 1)}
     rf.free()
     res["bf16_batched_speedup_vs_plain_fp32"] = round(
         res["plain_fp32_separate"]["host_ms"] /
-        res["batched_bf16_graph"]["host_ms"], 3)
+        res["batched_bf16"]["host_ms"], 3)
     out["batched_bf16_vs_plain_fp32"] = res
     del f32, bf, yb, yf
     torch.cuda.empty_cache()

@@ -142,9 +142,40 @@ int pcoll_pready_list(pcoll_req_t req, int n, const int *parts);
  * readiness can follow producer kernels in stream order (or be captured in
  * a graph).  `stream` must not be the bound stream (the reduce kernel
  * occupies it until every partition is ready).  Each partition must be
- * readied once per epoch; ids out of range are ignored. */
+ * readied once per epoch; ids out of range are ignored.
+ *
+ * The signal must be able to run while the reduce kernel runs, so its
+ * stream must not share the bound stream's hardware queue: HIP spreads a
+ * process's streams over GPU_MAX_HW_QUEUES hardware queues per device (4
+ * by default), and work queued behind the reduce kernel in its hardware
+ * queue waits for it.  Keep the streams that signal during an epoch fewer
+ * than that limit.  A signal that cannot run leaves its partitions
+ * unready: the kernel reaches its deadline and the epoch fails with
+ * PCOLL_ERR_ABORTED; it does not hang. */
 int pcoll_pready_on_stream(pcoll_req_t req, const int *parts_dev, int n,
                            void *stream);
+
+/* Per-rank readiness (the receive side of a partitioned allreduce): rank
+ * `rank` (0..nranks-1) has placed its contribution to partition `part`.
+ * The partition becomes ready, exactly as by pcoll_pready, once every rank
+ * has readied it this epoch; until then the kernel does not touch it.
+ * Host-side bookkeeping only (no GPU call unless this completes the
+ * partition).  PCOLL_ERR_STATE if no epoch is active, if this rank already
+ * readied the partition this epoch, or if the partition is already ready;
+ * PCOLL_ERR_ARG if rank or part is out of range. */
+int pcoll_pready_rank(pcoll_req_t req, int rank, int part);
+
+/* Device-side per-rank readiness: enqueues on `stream` a kernel that marks
+ * rank `rank`'s contributions to the partitions parts_dev[0..n) (device
+ * array) in place when it runs, so each rank's marks can follow its
+ * producer kernels in that rank's stream order.  A partition is queued
+ * when the marks of all ranks for the current epoch are in; repeated marks
+ * of one rank are idempotent and ids out of range are ignored.  All ranks
+ * of one partition must mark it on the device (pcoll_pready_rank counts on
+ * the host, apart).  `stream` must not be the bound stream, nor share its
+ * hardware queue (see pcoll_pready_on_stream). */
+int pcoll_pready_rank_on_stream(pcoll_req_t req, int rank,
+                                const int *parts_dev, int n, void *stream);
 
 /* Non-blocking test of one partition: *flag = 1 once its output is final in
  * the current (or last completed) epoch.  PCOLL_ERR_STATE before the first
@@ -201,7 +232,10 @@ typedef struct {
                         groups_per_cu x compute units */
   int groups_per_cu; /* used when groups = 0 */
   int comp;          /* float sums: 1 = Sum2 compensated, 0 = plain */
-  int graph;         /* 1 = start replays a cached graph, 0 = direct launch */
+  int graph;         /* 1 = start replays a cached graph (captured once per
+                        binding and configuration), 0 = direct launch (the
+                        default: an epoch is one kernel, so a graph has no
+                        launches to save and its launch costs more) */
   int timeout_ms;    /* device-side deadline of one epoch */
   int debug;         /* 1 = count tiles reduced per partition */
   int interleave;    /* tile layout: 0 = each tile is a contiguous range of

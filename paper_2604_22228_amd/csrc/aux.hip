@@ -56,6 +56,63 @@ hipError_t launch_pready(const PreadyArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Per-rank marks.  Each lane sets its rank's bit in the partition's
+// epoch-tagged mask with a compare-and-swap (acquire-release: the ranks'
+// producers, ordered before their marks by their streams, are visible to
+// the lane whose mark completes the mask, which then publishes with a
+// release store).  Marks already set are idempotent, so a partition is
+// appended exactly once; the completing lanes of a wavefront reserve their
+// ring entries with one atomic.
+__global__ __launch_bounds__(256) void pready_rank_kernel(PreadyRankArgs a) {
+  const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+  const uint32_t lane = threadIdx.x & 63u;
+  bool done = false;
+  uint32_t part = 0;
+  if (i < a.n) {
+    part = (uint32_t)a.parts[i];
+    if (part < a.capacity) {
+      uint64_t* w = &a.rank_marks[part];
+      const uint64_t tag = (uint64_t)a.epoch << 32;
+      const uint64_t bit = 1ull << a.rank;
+      uint64_t old = __hip_atomic_load(w, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+      for (;;) {
+        const uint64_t cur = (old & ~0xffffffffull) == tag ? old : tag;
+        const uint64_t nw = cur | bit;
+        if (nw == old) break;  // this rank's mark is already in
+        if (__hip_atomic_compare_exchange_strong(
+                w, &old, nw, __ATOMIC_ACQ_REL, __ATOMIC_RELAXED,
+                __HIP_MEMORY_SCOPE_AGENT)) {
+          done = (uint32_t)nw == a.full && (uint32_t)cur != a.full;
+          break;
+        }
+      }
+    }
+  }
+  const uint64_t m = __ballot(done);
+  if (m == 0) return;
+  const uint32_t leader = (uint32_t)(__ffsll((long long)m) - 1);
+  uint64_t base = 0;
+  if (lane == leader)
+    base = __hip_atomic_fetch_add(&a.ring->dreserve,
+                                  (uint64_t)__popcll(m), __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
+  base = __shfl(base, (int)leader);
+  if (done) {
+    const uint64_t c = base + __popcll(m & ((1ull << lane) - 1ull));
+    const uint64_t v = ((uint64_t)(uint32_t)c << 32) | part;
+    __hip_atomic_store(&a.dlist[c % a.capacity], v, __ATOMIC_RELEASE,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+hipError_t launch_pready_rank(const PreadyRankArgs& a, hipStream_t s) {
+  if (a.n == 0) return hipSuccess;
+  hipLaunchKernelGGL(pready_rank_kernel, dim3((a.n + 255u) / 256u),
+                     dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ packers
 __global__ __launch_bounds__(256) void pack_bf16_kernel(const float* src,
                                                         uint16_t* dst,

@@ -30,6 +30,10 @@ hipError_t launch_reduce(const ReduceArgs& a, int dtype, int op, bool comp,
 // Device-side readiness: appends `a.n` partition ids to the device ready
 // ring.
 hipError_t launch_pready(const PreadyArgs& a, hipStream_t s);
+// Device-side per-rank readiness: marks one rank's contribution to a.n
+// partitions; each partition whose last rank this completes is appended to
+// the ring.
+hipError_t launch_pready_rank(const PreadyRankArgs& a, hipStream_t s);
 // Producer-side packing: FP32 -> bfloat16 (RNE), FP32 -> e4m3 + per-256
 // FP32 scales.
 hipError_t launch_pack_bf16(const float* src, uint16_t* dst, size_t n,

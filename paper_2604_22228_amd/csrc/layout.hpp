@@ -138,5 +138,22 @@ struct PreadyArgs {
   RingCounters* ring;
 };
 
+// Per-rank readiness on the device: rank `rank` marks its contribution to
+// parts[0..n) in place.  rank_marks[p] = (epoch << 32) | mask of the ranks
+// that marked p in that epoch (a word of another epoch counts as empty);
+// the mark that completes the mask appends p to the ready ring.
+struct PreadyRankArgs {
+  const int32_t* parts;
+  uint32_t n;
+  uint32_t capacity;      // partitions of the request
+  uint32_t rank;
+  uint32_t epoch;
+  uint32_t full;          // mask of all ranks: (1 << nranks) - 1
+  uint32_t reserved;
+  uint64_t* rank_marks;   // [capacity]
+  uint64_t* dlist;
+  RingCounters* ring;
+};
+
 
 }  // namespace pcoll

@@ -187,12 +187,36 @@ __device__ __forceinline__ void queue_append(const ReduceArgs& a,
   qrows += uni(__shfl(rincl, 63));
 }
 
+// Whether the ready lists may hold entries not yet queued: the host list's
+// next entry carries this epoch, or the device ring has reserved entries
+// beyond the consumed ones.  Relaxed reads, no lock: a stale answer only
+// costs one lock attempt or one more probe.  A worker that has waited a
+// while probes before it takes the lock, so an epoch that waits for its
+// producers does not keep an atomic and a 2 KiB bus read in flight per
+// probe; a short wait (the host's readiness calls right after the launch)
+// goes straight to the lock and saves the probe's bus round trip.
+__device__ __forceinline__ bool ready_lists_moved(const ReduceArgs& a,
+                                                  uint32_t epoch) {
+  EpochCounters* c = a.ctr;
+  if (uni(ld_rlx(&c->ilock)) != 0u) return false;  // being ingested
+  const uint32_t hcons = uni(ld_rlx(&c->hconsumed));
+  uint64_t head = 0;
+  if (hcons < a.nparts_total && lane_id() == 0)
+    head = ld_rlx_sys64(&a.hlist[hcons]);
+  if ((uint32_t)(uni64(head) >> 32) == epoch && hcons < a.nparts_total)
+    return true;
+  return uni64(ld_rlx64(&a.ring->dreserve)) >
+         uni64(ld_rlx64(&a.ring->dconsumed));
+}
+
 // Moves newly readied partitions into the queue.  Returns true if it queued
 // any tile.  Wave-wide.  The lock is taken before the host list is read, so
 // at most one wavefront at a time reads host memory over the bus.
-__device__ __forceinline__ bool try_ingest(const ReduceArgs& a, uint32_t epoch) {
+__device__ __forceinline__ bool try_ingest(const ReduceArgs& a, uint32_t epoch,
+                                           bool probe) {
   const uint32_t lane = lane_id();
   EpochCounters* c = a.ctr;
+  if (probe && !ready_lists_moved(a, epoch)) return false;
   uint32_t got = 0;
   if (lane == 0) {
     uint32_t expect = 0;
@@ -212,7 +236,7 @@ __device__ __forceinline__ bool try_ingest(const ReduceArgs& a, uint32_t epoch) 
   }
   uint32_t hcons = uni(ld_rlx(&c->hconsumed));
   uint64_t dcons = uni64(ld_rlx64(&a.ring->dconsumed));
-  uint64_t dr = uni64(ld_acq64(&a.ring->dreserve));
+  uint64_t dr = uni64(ld_rlx64(&a.ring->dreserve));
   uint64_t qrows = uni64(ld_rlx64(&c->queued_rows));
   const uint32_t qtiles0 = qtiles;
 
@@ -239,6 +263,9 @@ __device__ __forceinline__ bool try_ingest(const ReduceArgs& a, uint32_t epoch) 
       if (prefix != 64u * k) lim[k] = 0u;
       prefix += lim[k];
     }
+    // the entries were written with release stores after the host saw
+    // their partitions' data in place: acquire before queueing them
+    if (prefix) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
     // stamps and descriptors of every chunk in flight together
     Stamped st[4];
 #pragma unroll
@@ -265,6 +292,9 @@ __device__ __forceinline__ bool try_ingest(const ReduceArgs& a, uint32_t epoch) 
     const uint64_t pending = __ballot(in && !ok);
     const uint32_t lim =
         pending ? (uint32_t)(__ffsll((long long)pending) - 1) : 64u;
+    // entries were stored with release after their producers: acquire
+    if (__ballot(ok && lane < lim)) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE,
+                                                            "agent");
     queue_append(a, queue_stamp(a, epoch, ok && lane < lim, (uint32_t)v),
                  qcount, qtiles, qrows);
     const uint64_t avail = dr - dcons < 64u ? dr - dcons : 64u;
@@ -316,9 +346,13 @@ __device__ __forceinline__ WaitResult wait_queued(const ReduceArgs& a,
   // already visible, so a tile inside it needs no new acquire
   if ((uint32_t)qs_out > t) return kReady;
   for (uint32_t spins = 0;; ++spins) {
-    const uint64_t qs = uni64(ld_acq64(&a.ctr->qstate));
+    // polled relaxed; acquired (one fence) only once it covers t: an
+    // acquire invalidates caches, which a waiting kernel should not keep
+    // doing to the kernels that run beside it
+    const uint64_t qs = uni64(ld_rlx64(&a.ctr->qstate));
     const uint32_t qt = (uint32_t)qs;
     if (qt > t) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       qs_out = qs;
       return kReady;
     }
@@ -326,10 +360,10 @@ __device__ __forceinline__ WaitResult wait_queued(const ReduceArgs& a,
     // about to wait: finished tiles must not sit behind the wait
     publish_pending();
     const bool front = t - qt < 8u;
-    if (front && try_ingest(a, epoch)) continue;
+    if (front && try_ingest(a, epoch, spins >= 16u)) continue;
     if (uni(ld_rlx(&a.ctr->error)) != 0u) return kBail;
     if ((spins & 7u) == 7u) {
-      if (front && uni(ld_acq_sys(&a.host->abort)) == epoch) {
+      if (front && uni(ld_rlx_sys(&a.host->abort)) == epoch) {
         set_error(a, kStatusAborted, epoch);
         return kBail;
       }

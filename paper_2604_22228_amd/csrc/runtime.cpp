@@ -152,6 +152,7 @@ struct pcoll_req_s {
   uint32_t* d_hits = nullptr;
   uint32_t* d_tiles = nullptr;
   uint64_t* d_dlist = nullptr;
+  uint64_t* d_rank_marks = nullptr;  // [partitions] device per-rank marks
   EpochCounters* d_ctr = nullptr;  // [2]
   RingCounters* d_ring = nullptr;
 
@@ -174,6 +175,8 @@ struct pcoll_req_s {
   std::vector<uint64_t> mark;   // call generation that last listed it
   uint64_t mark_gen = 0;
   std::vector<int> order;       // scratch: a list in partition order
+  std::vector<uint32_t> rank_mask;   // host per-rank readiness: ranks that
+  std::vector<uint32_t> rank_epoch;  // readied each partition, and when
   pcoll_stats_t stats{};
   uint64_t sig = 0;             // launch signature (config-dependent args)
 };
@@ -269,7 +272,9 @@ pcoll_config_t default_config(const pcoll_req_s* r) {
   uint64_t bytes = 0;
   for (uint64_t c : r->counts) bytes += c * (uint64_t)elem_bytes(r->dtype);
   pcoll_config_t c{};
-  c.graph = env_int("PCOLL_GRAPH", r->nbuckets > 1 ? 1 : 0) ? 1 : 0;
+  // direct launch by default: the request's work is one kernel, and a
+  // graph launch of one node costs more host time than a kernel launch
+  c.graph = env_int("PCOLL_GRAPH", 0) ? 1 : 0;
   TuneChoice t = tune_lookup(tune_rows(), r->dtype, r->op, r->nranks, c.graph,
                              bytes);
   c.tile_elems = env_int("PCOLL_TILE", t.tile_elems);
@@ -346,6 +351,8 @@ int create(const std::vector<uint64_t>& counts, int dtype, int op,
   r->stamp.assign(r->nparts_total, 0u);
   r->mark.assign(r->nparts_total, 0u);
   r->order.reserve(r->nparts_total);
+  r->rank_mask.assign(r->nparts_total, 0u);
+  r->rank_epoch.assign(r->nparts_total, 0u);
 
   HIP_TRY(hipGetDevice(&r->device));
   HIP_TRY(hipDeviceGetAttribute(&r->cus, hipDeviceAttributeMultiprocessorCount,
@@ -384,6 +391,7 @@ int create(const std::vector<uint64_t>& counts, int dtype, int op,
   const size_t o_hits = take(sizeof(uint32_t) * np_total);
   const size_t o_tiles = take(sizeof(uint32_t) * np_total);
   const size_t o_dlist = take(sizeof(uint64_t) * np_total);
+  const size_t o_marks = take(sizeof(uint64_t) * np_total);
   const size_t o_ctr = take(2 * sizeof(EpochCounters));
   const size_t o_ring = take(sizeof(RingCounters));
   e = hipMalloc(&r->arena, off);
@@ -404,6 +412,7 @@ int create(const std::vector<uint64_t>& counts, int dtype, int op,
                     sizeof(PartDesc) * r->parts.size(),
                     hipMemcpyHostToDevice));
   r->d_dlist = reinterpret_cast<uint64_t*>(base + o_dlist);
+  r->d_rank_marks = reinterpret_cast<uint64_t*>(base + o_marks);
   r->d_ctr = reinterpret_cast<EpochCounters*>(base + o_ctr);
   r->d_ring = reinterpret_cast<RingCounters*>(base + o_ring);
 
@@ -828,6 +837,46 @@ int pcoll_pready_range(pcoll_req_t r, int first, int last) {
   if (!r->active) return PCOLL_ERR_STATE;
   if (last < first) return PCOLL_ERR_ARG;
   return publish_ready(r, nullptr, last - first + 1, first);
+}
+
+int pcoll_pready_rank(pcoll_req_t r, int rank, int part) {
+  if (check_req(r)) return PCOLL_ERR_ARG;
+  if (rank < 0 || rank >= r->nranks) return PCOLL_ERR_ARG;
+  if (part < 0 || (uint32_t)part >= r->nparts_total) return PCOLL_ERR_ARG;
+  if (!r->active) return PCOLL_ERR_STATE;
+  const size_t p = (size_t)part;
+  if (r->stamp[p] == r->epoch) return PCOLL_ERR_STATE;  // already ready
+  if (r->rank_epoch[p] != r->epoch) {
+    r->rank_epoch[p] = r->epoch;
+    r->rank_mask[p] = 0u;
+  }
+  const uint32_t bit = 1u << rank;
+  if (r->rank_mask[p] & bit) return PCOLL_ERR_STATE;  // this rank, twice
+  r->rank_mask[p] |= bit;
+  if (r->rank_mask[p] != (1u << r->nranks) - 1u) return PCOLL_SUCCESS;
+  return publish_ready(r, &part, 1, 0);  // the last rank: queue it
+}
+
+int pcoll_pready_rank_on_stream(pcoll_req_t r, int rank, const int* parts_dev,
+                                int n, void* stream) {
+  if (check_req(r)) return PCOLL_ERR_ARG;
+  if (rank < 0 || rank >= r->nranks) return PCOLL_ERR_ARG;
+  if (n < 0 || (n > 0 && !parts_dev)) return PCOLL_ERR_ARG;
+  if (!r->active) return PCOLL_ERR_STATE;
+  if (static_cast<hipStream_t>(stream) == r->stream) return PCOLL_ERR_ARG;
+  HIP_TRY(hipSetDevice(r->device));
+  PreadyRankArgs a{};
+  a.parts = parts_dev;
+  a.n = (uint32_t)n;
+  a.capacity = r->nparts_total;
+  a.rank = (uint32_t)rank;
+  a.epoch = r->epoch;
+  a.full = (1u << r->nranks) - 1u;
+  a.rank_marks = r->d_rank_marks;
+  a.dlist = r->d_dlist;
+  a.ring = r->d_ring;
+  HIP_TRY(launch_pready_rank(a, static_cast<hipStream_t>(stream)));
+  return PCOLL_SUCCESS;
 }
 
 int pcoll_pready_list(pcoll_req_t r, int n, const int* parts) {

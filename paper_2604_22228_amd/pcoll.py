@@ -71,6 +71,8 @@ _SIGS = {
     "pcoll_pready_range": [_p, _i, _i],
     "pcoll_pready_list": [_p, _i, C.POINTER(_i)],
     "pcoll_pready_on_stream": [_p, _p, _i, _p],
+    "pcoll_pready_rank": [_p, _i, _i],
+    "pcoll_pready_rank_on_stream": [_p, _i, _p, _i, _p],
     "pcoll_parrived": [_p, _i, C.POINTER(_i)],
     "pcoll_test": [_p, C.POINTER(_i)],
     "pcoll_wait": [_p],
@@ -208,6 +210,16 @@ def pcoll_pready_on_stream(h, parts_dev, n, stream):
     _check(load().pcoll_pready_on_stream(h, _ptr(parts_dev), n,
                                          _stream(stream)),
            "pcoll_pready_on_stream")
+
+
+def pcoll_pready_rank(h, rank, part):
+    _check(load().pcoll_pready_rank(h, rank, part), "pcoll_pready_rank")
+
+
+def pcoll_pready_rank_on_stream(h, rank, parts_dev, n, stream):
+    _check(load().pcoll_pready_rank_on_stream(h, rank, _ptr(parts_dev), n,
+                                              _stream(stream)),
+           "pcoll_pready_rank_on_stream")
 
 
 def pcoll_parrived(h, part):
@@ -378,6 +390,12 @@ class Request:
 
     def pready_on_stream(self, parts_dev, n, stream):
         pcoll_pready_on_stream(self.h, parts_dev, n, stream)
+
+    def pready_rank(self, rank, part):
+        pcoll_pready_rank(self.h, rank, part)
+
+    def pready_rank_on_stream(self, rank, parts_dev, n, stream):
+        pcoll_pready_rank_on_stream(self.h, rank, parts_dev, n, stream)
 
     def parrived(self, part):
         return pcoll_parrived(self.h, part)

@@ -117,11 +117,12 @@ def test_workload4_int32_full(orc):
         req.free()
 
 
-def test_workload3_batched_bf16_full(orc):
+@pytest.mark.parametrize("graph", [0, 1])
+def test_workload3_batched_bf16_full(orc, graph):
     counts = synth.batched_bf16_counts()
     P, nparts = 8, 32
     say(f"case batched bf16 full buckets={len(counts)} "
-        f"elements/rank={sum(counts)}")
+        f"elements/rank={sum(counts)} graph={graph}")
     stream = torch.cuda.Stream(DEV)
     cur = torch.cuda.current_stream(DEV)
     pays, outs = [], []
@@ -136,8 +137,10 @@ def test_workload3_batched_bf16_full(orc):
         outs.append(torch.full((c,), 0x7FC0, dtype=torch.int16, device=DEV))
     torch.cuda.synchronize()
     req = pc.Request(counts, pc.BFLOAT16, pc.SUM, nparts, P, batched=True)
+    if graph:
+        req.set_config(graph=1)
+    assert req.config().graph == graph
     req.bind(pays, outs, stream=stream)
-    assert req.config().graph == 1
     _run(req, len(counts) * nparts, 3, stream)
     errs = []
     for b, c in enumerate(counts):
@@ -156,7 +159,7 @@ def test_workload3_batched_bf16_full(orc):
     say("errors " + json.dumps({"workload": "batched bf16",
                                 "max_norm_err": float(max(errs))}))
     assert max(errs) <= 4e-3
-    assert req.stats().graph_launches == 1
+    assert req.stats().graph_launches == graph
     req.free()
 
 
