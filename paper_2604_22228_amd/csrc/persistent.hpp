@@ -525,7 +525,11 @@ __device__ __forceinline__ void persistent_loop(const ReduceArgs& args) {
   __shared__ Pending pend[kMaxPublishBatch];
   const uint32_t wave = threadIdx.x / 64u;
   const uint32_t nwaves = blockDim.x / 64u;
-  // only wavefront 0 runs the protocol and needs the epoch
+  // only wavefront 0 runs the protocol and needs the epoch.  A graph
+  // replay reads it from host memory: the launch has no more workgroups
+  // than tiles, every workgroup's first tile is its own number, so the
+  // epoch cannot complete (and the host cannot store the next stamp)
+  // before every workgroup has read this one
   uint32_t epoch = 0;
   if (wave == 0)
     epoch = args.epoch ? args.epoch : uni(ld_acq_sys(&args.host->epoch));

@@ -245,11 +245,16 @@ int apply_config(pcoll_req_t r, const pcoll_config_t& c) {
   int rc = validate_config(r, c);
   if (rc) return rc;
   int groups = c.groups ? c.groups : c.groups_per_cu * r->cus;
-  // no more workgroups than the launch can have tiles (a small message
-  // does not dispatch a full grid of workers that would only wait)
-  const uint64_t tile_rows = std::max<uint64_t>(
-      1, (uint64_t)(c.guide ? c.min_tile_elems : c.tile_elems) /
-             row_elems(r->dtype));
+  // No more workgroups than the launch has tiles for sure: every partition
+  // has at least max(1, ceil(rows / largest tile)) tiles in any mode.  So
+  // every workgroup owns a first tile (its own number), a small message
+  // does not dispatch workers that would only wait, and an epoch cannot
+  // complete before every workgroup of its launch has started; a graph
+  // replay, whose workgroups read the epoch stamp from host memory when
+  // they start, depends on that (the host writes the next stamp only
+  // after the epoch completed).
+  const uint64_t tile_rows =
+      std::max<uint64_t>(1, (uint64_t)c.tile_elems / row_elems(r->dtype));
   uint64_t max_tiles = 0;
   for (const PartDesc& p : r->parts)
     max_tiles += p.rows ? (p.rows + tile_rows - 1) / tile_rows : 1;

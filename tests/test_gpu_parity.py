@@ -427,6 +427,29 @@ def test_exactly_once_tile_counts(orc, stream, batch):
     req.free()
 
 
+@pytest.mark.parametrize("guide,graph", [(1, 0), (4, 0), (2, 1)])
+def test_guided_tiles(orc, stream, guide, graph):
+    """Guided self-scheduling (tiles shrink as the remaining work does):
+    bitwise against the oracle, every tile reduced once, over epochs in
+    both launch modes."""
+    say(f"case guided guide={guide} graph={graph}")
+    P, n, nparts = 4, 700 * 1024 + 11, 9
+    xs = synth.normal_f32(P, n, 81)
+    out = torch.empty(n, device=DEV)
+    req = new_request([n], pc.FLOAT32, pc.SUM, nparts, P, debug=1,
+                      tile_elems=32768, min_tile_elems=1024, guide=guide,
+                      graph=graph)
+    req.bind([[x.to(DEV) for x in xs]], [out], stream=stream)
+    want = as_u32(orc.sum_f32_f32([x.numpy() for x in xs]))
+    for epoch in range(3):
+        out.fill_(float("nan"))
+        run_epoch(req, synth.permutation(nparts, 81 + epoch), stream)
+        assert np.array_equal(as_u32(out.cpu().numpy()), want), epoch
+        hits, tiles = req.tile_hits()
+        assert all(h == t for h, t in zip(hits, tiles)), (hits, tiles)
+    req.free()
+
+
 def test_state_machine_errors(stream):
     n = 4096
     x = torch.zeros(n, device=DEV)
