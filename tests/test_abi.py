@@ -88,6 +88,10 @@ def test_plan_rejects_bad_arguments():
     ((100, pc.FLOAT32, pc.SUM, 4, 0), pc.ERR_ARG),  # nranks
     ((100, pc.FLOAT32, pc.SUM, 4, 17), pc.ERR_UNSUPPORTED),
     ((100, pc.FP8_E4M3, pc.MAX, 4, 4), pc.ERR_UNSUPPORTED),
+    # a partition beyond 2^31 elements (the kernels' 32-bit row indices)
+    ((1 << 33, pc.FLOAT32, pc.SUM, 1, 4), pc.ERR_UNSUPPORTED),
+    ((1 << 41, pc.INT32, pc.SUM, 4096, 4), pc.ERR_UNSUPPORTED),
+    ((100, pc.FLOAT32, pc.SUM, (1 << 24) + 1, 4), pc.ERR_UNSUPPORTED),
 ])
 def test_init_argument_errors_need_no_gpu(args, code):
     with pytest.raises(pc.PcollError) as e:
@@ -111,6 +115,9 @@ def test_null_request_is_an_argument_error():
     for name in ("pcoll_start", "pcoll_wait", "pcoll_free"):
         assert getattr(lib, name)(None) == pc.ERR_ARG
     assert lib.pcoll_pready(None, 0) == pc.ERR_ARG
+    assert lib.pcoll_pready_rank(None, 0, 0) == pc.ERR_ARG
+    assert lib.pcoll_pready_rank_on_stream(None, 0, None, 0, None) == \
+        pc.ERR_ARG
 
 
 def test_probe_and_pack_reject_unaligned_sizes():
