@@ -242,8 +242,11 @@ __device__ __forceinline__ bool try_ingest(const ReduceArgs& a, uint32_t epoch,
 
   // host ready list: entries hcons.. carrying this epoch's tag, read 256
   // per round trip over the bus; the queue state is published after every
-  // 64 entries, so that workers start on them while the rest is read
-  for (bool more = hcons < a.nparts_total; more;) {
+  // 64 entries, so that workers start on them while the rest is read.  An
+  // empty first read is repeated a few times while the lock is held (one
+  // bus round trip per poll, instead of a lock, the counters and a read),
+  // unless the device ring has entries
+  for (uint32_t polls = 0; hcons < a.nparts_total; ++polls) {
     uint64_t v[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -263,6 +266,13 @@ __device__ __forceinline__ bool try_ingest(const ReduceArgs& a, uint32_t epoch,
       if (prefix != 64u * k) lim[k] = 0u;
       prefix += lim[k];
     }
+    if (prefix == 0u) {
+      if (qtiles != qtiles0 || polls >= 7u) break;
+      dr = uni64(ld_rlx64(&a.ring->dreserve));
+      if (dr > dcons) break;
+      __builtin_amdgcn_s_sleep(1);
+      continue;
+    }
     // the entries were written with release stores after the host saw
     // their partitions' data in place: acquire before queueing them
     if (prefix) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
@@ -278,7 +288,8 @@ __device__ __forceinline__ bool try_ingest(const ReduceArgs& a, uint32_t epoch,
       st_rel64(&c->qstate, ((uint64_t)qcount << 32) | qtiles);
     }
     hcons += prefix;
-    more = prefix == 256u && hcons < a.nparts_total;
+    if (prefix != 256u) break;
+    polls = 8u;  // found entries: no more empty polls
   }
 
   // device ready ring: entry c sits in slot c % nparts_total, stored as
@@ -375,7 +386,7 @@ __device__ __forceinline__ WaitResult wait_queued(const ReduceArgs& a,
     if (front)
       __builtin_amdgcn_s_sleep(2);
     else
-      __builtin_amdgcn_s_sleep(32);
+      __builtin_amdgcn_s_sleep(8);
   }
 }
 
