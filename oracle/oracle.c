@@ -31,6 +31,10 @@
  *   - e4m3 (OCP 8-bit floating point, "E4M3FN"): 1 sign, 4 exponent (bias 7),
  *     3 fraction bits; no infinities; S.1111.111 is NaN; max 448; subnormal
  *     quantum 2^-9.  Encoding rounds to nearest, ties to even, and saturates.
+ *   - e5m2 (OCP 8-bit floating point, "E5M2"): 1 sign, 5 exponent (bias 15),
+ *     2 fraction bits; S.11111.00 is infinity, S.11111.xx (xx != 0) NaN; max
+ *     57344; subnormal quantum 2^-16.  Encoding rounds to nearest, ties to
+ *     even, and saturates at +-57344.
  *
  * Build with -O2 -ffp-contract=off and SSE2 arithmetic (no x87, no fast-math)
  * so that every float / double operation is one IEEE-754 RNE operation.
@@ -355,5 +359,113 @@ void orc_sum_e4m3_f32(int P, int64_t n, const uint8_t *const *q,
       if (y32) y32[i] = blk[i - lo];
     }
     orc_e4m3_pack(hi - lo, blk, yq + lo, ys + b);
+  }
+}
+
+/* ------------------------------------------------------------------ */
+/* e5m2 (OCP E5M2) with one FP32 scale per block of 256 elements        */
+/* ------------------------------------------------------------------ */
+
+double orc_e5m2_decode(uint8_t q) {
+  int s = (q >> 7) & 1;
+  int e = (q >> 2) & 0x1f;
+  int f = q & 0x3;
+  double v;
+  if (e == 0x1f) {
+    if (f != 0) return NAN;
+    v = INFINITY;
+  } else if (e == 0) {
+    v = ldexp((double)f, -14 - 2); /* 0.f x 2^-14 */
+  } else {
+    v = ldexp((double)(4 + f), e - 15 - 2); /* 1.f x 2^(e-15) */
+  }
+  return s ? -v : v;
+}
+
+uint8_t orc_e5m2_encode(double v) {
+  if (isnan(v)) return 0x7f;
+  int s = signbit(v) ? 1 : 0;
+  double a = fabs(v);
+  const double max_e5m2 = 57344.0; /* 1.11b x 2^15 */
+  double r;
+  if (a >= max_e5m2) {
+    r = max_e5m2; /* saturate (infinities included) */
+  } else if (a == 0.0) {
+    return (uint8_t)(s << 7);
+  } else {
+    int e;
+    frexp(a, &e);
+    int ufp = e - 1;
+    if (ufp < -14) ufp = -14; /* subnormals: quantum 2^-16 */
+    r = round_to_quantum_rne(a, ldexp(1.0, ufp - 2));
+    if (r > max_e5m2) r = max_e5m2;
+  }
+  uint8_t bits;
+  if (r < ldexp(1.0, -14)) {
+    bits = (uint8_t)(r / ldexp(1.0, -16));
+  } else {
+    int ee;
+    double m = frexp(r, &ee);
+    int E = ee - 1 + 15;
+    int F = (int)((m * 2.0 - 1.0) * 4.0);
+    bits = (uint8_t)((E << 2) | F);
+  }
+  return (uint8_t)((s << 7) | bits);
+}
+
+/* Scale of one e5m2 block: s = fl32(amax / 57344); s = 1 when amax is 0 or
+ * s would not be a normal binary32 number. */
+static float block_scale_e5m2(float amax) {
+  float s = amax / 57344.0f;
+  if (!(s >= 0x1p-126f)) s = 1.0f;
+  return s;
+}
+
+/* As orc_e4m3_pack, for e5m2: q = e5m2(fl32(x * fl32(1 / s))). */
+void orc_e5m2_pack(int64_t n, const float *x, uint8_t *q, float *s) {
+  for (int64_t b = 0; b * 256 < n; ++b) {
+    int64_t lo = b * 256, hi = lo + 256 < n ? lo + 256 : n;
+    float amax = 0.0f;
+    for (int64_t i = lo; i < hi; ++i) {
+      float a = fabsf(x[i]);
+      if (a > amax) amax = a;
+    }
+    float sc = block_scale_e5m2(amax);
+    float inv = 1.0f / sc;
+    s[b] = sc;
+    for (int64_t i = lo; i < hi; ++i) {
+      float t = x[i] * inv;
+      q[i] = orc_e5m2_encode((double)t);
+    }
+  }
+}
+
+/* FP64 reference: sum of the exactly dequantized payloads
+ * dec(q_r[i]) * s_r[i / 256] (3 x 24 significant bits: exact in double). */
+void orc_sum_e5m2_f64(int P, int64_t n, const uint8_t *const *q,
+                      const float *const *s, double *y) {
+  for (int64_t i = 0; i < n; ++i) {
+    double acc = 0.0;
+    for (int r = 0; r < P; ++r)
+      acc += orc_e5m2_decode(q[r][i]) * (double)s[r][i / 256];
+    y[i] = acc;
+  }
+}
+
+/* FP32 mirror, as orc_sum_e4m3_f32 with the e5m2 codec and scale. */
+void orc_sum_e5m2_f32(int P, int64_t n, const uint8_t *const *q,
+                      const float *const *s, int comp, uint8_t *yq,
+                      float *ys, float *y32) {
+  float v[64];
+  float blk[256];
+  for (int64_t b = 0; b * 256 < n; ++b) {
+    int64_t lo = b * 256, hi = lo + 256 < n ? lo + 256 : n;
+    for (int64_t i = lo; i < hi; ++i) {
+      for (int r = 0; r < P; ++r)
+        v[r] = (float)orc_e5m2_decode(q[r][i]) * s[r][b];
+      blk[i - lo] = acc_f32(P, v, comp);
+      if (y32) y32[i] = blk[i - lo];
+    }
+    orc_e5m2_pack(hi - lo, blk, yq + lo, ys + b);
   }
 }

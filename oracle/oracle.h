@@ -42,6 +42,14 @@ void orc_sum_e4m3_f64(int P, int64_t n, const uint8_t *const *q,
 void orc_sum_e4m3_f32(int P, int64_t n, const uint8_t *const *q,
                       const float *const *s, int comp, uint8_t *yq,
                       float *ys, float *y32);
+double orc_e5m2_decode(uint8_t q);
+uint8_t orc_e5m2_encode(double v);
+void orc_e5m2_pack(int64_t n, const float *x, uint8_t *q, float *s);
+void orc_sum_e5m2_f64(int P, int64_t n, const uint8_t *const *q,
+                      const float *const *s, double *y);
+void orc_sum_e5m2_f32(int P, int64_t n, const uint8_t *const *q,
+                      const float *const *s, int comp, uint8_t *yq,
+                      float *ys, float *y32);
 
 #ifdef __cplusplus
 }

@@ -42,6 +42,11 @@ def _load(path=None):
         "orc_e4m3_pack": (None, [i64, p, p, p]),
         "orc_sum_e4m3_f64": (None, [i32, i64, p, p, p]),
         "orc_sum_e4m3_f32": (None, [i32, i64, p, p, i32, p, p, p]),
+        "orc_e5m2_decode": (C.c_double, [C.c_uint8]),
+        "orc_e5m2_encode": (C.c_uint8, [C.c_double]),
+        "orc_e5m2_pack": (None, [i64, p, p, p]),
+        "orc_sum_e5m2_f64": (None, [i32, i64, p, p, p]),
+        "orc_sum_e5m2_f32": (None, [i32, i64, p, p, i32, p, p, p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -188,6 +193,45 @@ class Oracle:
         ys = np.empty((n + 255) // 256, np.float32)
         y32 = np.empty(n, np.float32)
         self.lib.orc_sum_e4m3_f32(len(arrs), n, tab, stab, int(comp),
+                                  self._ptr(yq), self._ptr(ys),
+                                  self._ptr(y32))
+        return yq, ys, y32
+
+
+    # ---- e5m2 with per-256 FP32 scales ----------------------------------
+    def e5m2_decode(self, q):
+        return float(self.lib.orc_e5m2_decode(int(q)))
+
+    def e5m2_encode(self, v):
+        return int(self.lib.orc_e5m2_encode(float(v)))
+
+    def e5m2_decode_table(self):
+        return np.array([self.lib.orc_e5m2_decode(q) for q in range(256)],
+                        dtype=np.float64)
+
+    def e5m2_pack(self, x):
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        n = len(x)
+        q = np.empty(n, np.uint8)
+        s = np.empty((n + 255) // 256, np.float32)
+        self.lib.orc_e5m2_pack(n, self._ptr(x), self._ptr(q), self._ptr(s))
+        return q, s
+
+    def sum_e5m2_f64(self, qs, ss):
+        arrs, tab, n = self._ptrs(qs, np.uint8)
+        sarr, stab, _ = self._ptrs(ss, np.float32)
+        y = np.empty(n, np.float64)
+        self.lib.orc_sum_e5m2_f64(len(arrs), n, tab, stab, self._ptr(y))
+        return y
+
+    def sum_e5m2_f32(self, qs, ss, comp=True):
+        """Returns (e5m2 codes, per-256 scales, binary32 sums)."""
+        arrs, tab, n = self._ptrs(qs, np.uint8)
+        sarr, stab, _ = self._ptrs(ss, np.float32)
+        yq = np.empty(n, np.uint8)
+        ys = np.empty((n + 255) // 256, np.float32)
+        y32 = np.empty(n, np.float32)
+        self.lib.orc_sum_e5m2_f32(len(arrs), n, tab, stab, int(comp),
                                   self._ptr(yq), self._ptr(ys),
                                   self._ptr(y32))
         return yq, ys, y32

@@ -60,6 +60,14 @@ MUTANTS = {
     "e4m3_mirror_transposed_scale": (
         "v[r] = (float)orc_e4m3_decode(q[r][i]) * s[r][b];",
         "v[r] = (float)orc_e4m3_decode(q[r][i]) * s[0][b];"),
+    "e5m2_decode_bias": (
+        "v = ldexp((double)(4 + f), e - 15 - 2);",
+        "v = ldexp((double)(4 + f), e - 16 - 2);"),
+    "e5m2_no_subnormals": (
+        "if (ufp < -14) ufp = -14; /* subnormals: quantum 2^-16 */",
+        "if (ufp < -15) ufp = -15;"),
+    "e5m2_scale_uses_448": (
+        "float s = amax / 57344.0f;", "float s = amax / 448.0f;"),
     "plan_floor_instead_of_ceil": (
         "int64_t psize = (count + nparts - 1) / nparts;",
         "int64_t psize = count / nparts + (count > 0);"),

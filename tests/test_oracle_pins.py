@@ -518,3 +518,158 @@ def test_e4m3_sum_error_within_tolerance(orc):
         assert e.max() <= 6e-2
         e32 = np.abs(y32 - y64) / np.maximum(absum, 1e-38)
         assert e32.max() <= (_gamma(P - 1) + U32 if not comp else 3 * U32)
+
+
+# --------------------------------------------------------------------------
+# e5m2 codec, block scaling and sums
+# --------------------------------------------------------------------------
+def test_e5m2_golden_values(orc):
+    for line in _rows("e5m2_ocp_values.txt"):
+        code, val = line.split()
+        v = orc.e5m2_decode(int(code, 16))
+        if val == "nan":
+            assert math.isnan(v)
+            continue
+        assert v == float(val) and math.copysign(1, v) == math.copysign(
+            1, float(val)), line
+        if not math.isinf(v):
+            assert orc.e5m2_encode(float(val)) == int(code, 16), line
+
+
+def test_e5m2_rounding_fixtures(orc):
+    for line in _rows("e5m2_rounding.txt"):
+        val, code = line.split()
+        assert orc.e5m2_encode(_num(val)) == int(code, 16), line
+
+
+def test_e5m2_decode_table_vs_torch(orc):
+    table = orc.e5m2_decode_table()
+    ref = torch.arange(256, dtype=torch.int32).to(torch.uint8) \
+        .view(torch.float8_e5m2).to(torch.float64).numpy()
+    nan = np.isnan(ref)
+    assert nan.sum() == 6 and np.isinf(ref).sum() == 2
+    assert np.array_equal(np.isnan(table), nan)
+    assert np.array_equal(table[~nan], ref[~nan])
+
+
+def test_e5m2_encode_vs_torch_cast(orc):
+    g = torch.Generator().manual_seed(25)
+    x = torch.randn(20000, generator=g) * torch.exp(
+        torch.empty(20000).uniform_(-18, 12, generator=g))
+    x = torch.cat([x, torch.tensor([0.0, -0.0, 57344.0, -57344.0,
+                                    2.0 ** -16, 2.0 ** -17, 3 * 2.0 ** -17])])
+    clamped = x.clamp(-57344, 57344)
+    ref = clamped.to(torch.float8_e5m2).view(torch.uint8).numpy()
+    got = np.array([orc.e5m2_encode(float(v)) for v in x], np.uint8)
+    assert np.array_equal(got, ref)
+
+
+def test_e5m2_encode_is_nearest_even_brute_force(orc):
+    table = orc.e5m2_decode_table()
+    pos = np.arange(0, 0x7c)  # +0 .. 57344
+    vals = table[pos]
+    rng = np.random.default_rng(26)
+    for v in np.concatenate([rng.uniform(0, 57344, 500),
+                             np.exp(rng.uniform(-11, 10, 500)),
+                             vals[:-1] + np.diff(vals) / 2]):
+        k = np.searchsorted(vals, v)
+        cands = [c for c in (k - 1, k) if 0 <= c < len(vals)]
+        best = min(cands, key=lambda c: (abs(vals[c] - v), pos[c] & 1))
+        assert orc.e5m2_encode(v) == pos[best], v
+
+
+def test_e5m2_pack_properties(orc):
+    rng = np.random.default_rng(27)
+    n = 256 * 40 + 77  # ragged last block
+    x = (rng.standard_normal(n) * np.exp(rng.uniform(-6, 6, n))) \
+        .astype(np.float32)
+    x[256:512] = 0.0  # an all-zero block
+    q, s = orc.e5m2_pack(x)
+    table = orc.e5m2_decode_table()
+    assert len(s) == (n + 255) // 256
+    for b in range(len(s)):
+        blk = x[b * 256:(b + 1) * 256]
+        qb = q[b * 256:(b + 1) * 256]
+        amax = float(np.abs(blk).max())
+        if amax == 0.0:
+            assert s[b] == 1.0 and (qb & 0x7f == 0).all()
+            continue
+        assert s[b] == np.float32(np.float32(amax) / np.float32(57344.0))
+        mags = np.abs(table[qb])
+        assert mags.max() == 57344.0  # the largest element maps to +-57344
+        # half a quantum of the e5m2 grid relative to the element (2^-3),
+        # the subnormal floor s * 2^-17, the binary32 rounding of x / s
+        deq = table[qb] * float(s[b])
+        err = np.abs(deq - blk.astype(np.float64))
+        lim = np.abs(blk) * (2.0 ** -3 + 4 * U32) + float(s[b]) * 2.0 ** -17
+        assert (err <= lim).all()
+        assert (np.sign(table[qb]) * np.sign(blk) >= 0).all()
+
+
+def _pack_ranks_e5m2(orc, xs32):
+    qs, ss = [], []
+    for x in xs32:
+        q, s = orc.e5m2_pack(x)
+        qs.append(q)
+        ss.append(s)
+    return qs, ss
+
+
+def test_e5m2_sum_reference_exact(orc):
+    rng = np.random.default_rng(28)
+    P, n = 8, 256 * 6 + 31
+    xs32 = [(rng.standard_normal(n) * 1e-2).astype(np.float32)
+            for _ in range(P)]
+    qs, ss = _pack_ranks_e5m2(orc, xs32)
+    y64 = orc.sum_e5m2_f64(qs, ss)
+    table = orc.e5m2_decode_table()
+    for i in range(0, n, 5):
+        exact = sum(Fraction(float(table[qs[r][i]])) *
+                    Fraction(float(ss[r][i // 256])) for r in range(P))
+        assert Fraction(float(y64[i])) == exact
+
+
+def test_e5m2_sum_identity_and_powers_of_two(orc):
+    rng = np.random.default_rng(29)
+    n = 256 * 9 + 100
+    x = (rng.standard_normal(n) * 1e-2).astype(np.float32)
+    q, s = orc.e5m2_pack(x)
+    for comp in (False, True):
+        yq, ys, _ = orc.sum_e5m2_f32([q], [s], comp=comp)
+        assert np.array_equal(yq, q)
+        assert np.allclose(ys, s, rtol=2 * U32, atol=0)
+        for P in (2, 4, 8, 16):
+            zq, zs, _ = orc.sum_e5m2_f32([q] * P, [s] * P, comp=comp)
+            assert np.array_equal(zq, yq)
+            if comp:
+                assert np.array_equal(zs, ys * np.float32(P))
+            else:
+                assert np.allclose(zs, ys * np.float32(P), rtol=4 * U32,
+                                   atol=0)
+
+
+def test_e5m2_sum_error_within_bound(orc):
+    """The fp8 workload's shape (N(0, 1e-2), 1% outliers at 50x): the
+    output rounding bounds the error, u / (1 + u) = 1/9 for e5m2's 3
+    significant bits, plus the binary32 accumulation."""
+    rng = np.random.default_rng(30)
+    P, n = 8, 256 * 64
+    xs32 = []
+    for _ in range(P):
+        x = rng.standard_normal(n) * 1e-2
+        m = rng.uniform(size=n) < 0.01
+        x[m] *= 50
+        xs32.append(x.astype(np.float32))
+    qs, ss = _pack_ranks_e5m2(orc, xs32)
+    y64 = orc.sum_e5m2_f64(qs, ss)
+    table = orc.e5m2_decode_table()
+    deq = np.stack([table[qs[r]] * np.repeat(ss[r].astype(np.float64),
+                                            256)[:n] for r in range(P)])
+    absum = np.abs(deq).sum(axis=0)
+    for comp in (False, True):
+        yq, ys, y32 = orc.sum_e5m2_f32(qs, ss, comp=comp)
+        yv = table[yq] * np.repeat(ys.astype(np.float64), 256)[:n]
+        tau = np.repeat(ys.astype(np.float64), 256)[:n] * 2.0 ** -14
+        e = np.abs(yv - y64) / np.maximum(absum, tau)
+        assert e.max() <= 1 / 9 + 16 * U32
+        assert e.max() > 0.05  # the bound is approached, not vacuous
