@@ -16,7 +16,7 @@
  * Partitions.  Each message is cut into `nparts` partitions by the chunk
  * rule of Algorithm 1 (Section 4.3): every partition has the same length
  * psize = ceil(count / nparts) rounded up to whole 16-byte vectors (to 256
- * elements for PCOLL_FP8_E4M3, the scale block), offsets are fixed in
+ * elements for the 8-bit dtypes, the scale block), offsets are fixed in
  * advance as running sums, and the last partitions are clipped (possibly to
  * zero length).  Destination regions are disjoint (Section 4.5, Ordering
  * Guarantee): each partition of the output is written exactly once per
@@ -62,9 +62,11 @@ typedef enum {
   PCOLL_INT32 = 0,     /* two's-complement wrap sum, max: bit-exact */
   PCOLL_FLOAT32 = 1,   /* binary32 in and out, binary32 accumulation */
   PCOLL_BFLOAT16 = 2,  /* bf16 in and out, binary32 accumulation, RNE out */
-  PCOLL_FP8_E4M3 = 3   /* OCP e4m3 codes + one binary32 scale per 256
+  PCOLL_FP8_E4M3 = 3,  /* OCP e4m3 codes + one binary32 scale per 256
                           elements (value = code * scale), binary32
                           accumulation, output re-quantized per 256 */
+  PCOLL_FP8_E5M2 = 4   /* OCP e5m2 codes (2 fraction bits, range 57344),
+                          otherwise as PCOLL_FP8_E4M3 */
 } pcoll_dtype_t;
 
 typedef enum { PCOLL_SUM = 0, PCOLL_MAX = 1 } pcoll_op_t;
@@ -89,7 +91,7 @@ enum {
  * `dtype`, reduced with `op` over `nranks` ranks (1..PCOLL_MAX_RANKS), split
  * into `nparts` >= 1 partitions.  Allocates the request's flags (host-
  * coherent pinned memory) and counters (device memory) on the current HIP
- * device.  PCOLL_ERR_UNSUPPORTED for max on PCOLL_FP8_E4M3. */
+ * device.  PCOLL_ERR_UNSUPPORTED for max on the 8-bit dtypes. */
 int pcoll_init(size_t count, int dtype, int op, int nparts, int nranks,
                pcoll_req_t *out);
 
@@ -106,7 +108,7 @@ int pcoll_init_batch(int nbuckets, const size_t *counts, int dtype, int op,
  *   outs       nbuckets device pointers (may equal a rank buffer only if
  *              the caller accepts that rank's input being overwritten
  *              partition by partition).
- *   rank_scales / out_scales: PCOLL_FP8_E4M3 only (else NULL): per-256
+ *   rank_scales / out_scales: 8-bit dtypes only (else NULL): per-256
  *              binary32 scales, laid out like rank_bufs / outs, with
  *              ceil(count / 256) entries per bucket.
  * Not allowed while an epoch is active.  A binding seen before (same
@@ -320,6 +322,12 @@ int pcoll_pack_bf16(const float *src, uint16_t *dst, size_t n, void *stream);
  * dst[i] = e4m3(src[i] * (1 / s)), saturating, round to nearest even. */
 int pcoll_pack_fp8(const float *src, uint8_t *dst, float *scales, size_t n,
                    void *stream);
+
+/* As pcoll_pack_fp8, to e5m2 codes: s = amax / 57344 (1 if that is not a
+ * normal number), dst[i] = e5m2(src[i] * (1 / s)), saturating at
+ * +-57344, round to nearest even. */
+int pcoll_pack_e5m2(const float *src, uint8_t *dst, float *scales, size_t n,
+                    void *stream);
 
 /* --------------------------------------------------- measurement probes */
 

@@ -22,6 +22,9 @@ hipError_t launch_reduce(const ReduceArgs& a, int dtype, int op, bool comp,
     case kE4M3:
       if (op != kSum) return hipErrorInvalidValue;
       return launch_reduce_e4m3(a, comp, nranks, groups, waves, s);
+    case kE5M2:
+      if (op != kSum) return hipErrorInvalidValue;
+      return launch_reduce_e5m2(a, comp, nranks, groups, waves, s);
     default:
       return hipErrorInvalidValue;
   }
@@ -153,10 +156,11 @@ hipError_t launch_pack_bf16(const float* src, uint16_t* dst, size_t n,
 }
 
 // One row of 16 lanes per block of 256 values, 16 values per lane.
-__global__ __launch_bounds__(256) void pack_e4m3_kernel(const float* src,
-                                                        uint8_t* dst,
-                                                        float* scales,
-                                                        size_t n) {
+template <class Fmt>
+__global__ __launch_bounds__(256) void pack_fp8_kernel(const float* src,
+                                                       uint8_t* dst,
+                                                       float* scales,
+                                                       size_t n) {
   const uint32_t lane = threadIdx.x & 63u;
   const size_t wave = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
   const size_t nwaves = (size_t)gridDim.x * blockDim.x / 64;
@@ -184,13 +188,13 @@ __global__ __launch_bounds__(256) void pack_e4m3_kernel(const float* src,
     amax = fmaxf(amax, __shfl_xor(amax, 4, 16));
     amax = fmaxf(amax, __shfl_xor(amax, 2, 16));
     amax = fmaxf(amax, __shfl_xor(amax, 1, 16));
-    float so = amax / 448.0f;
+    float so = amax / Fmt::kMax;
     if (!(so >= 0x1p-126f)) so = 1.0f;
     const float inv = 1.0f / so;
     uint32_t w[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
     for (int j = 0; j < 16; ++j)
-      w[j >> 2] |= dev::f_to_e4m3(x[j] * inv) << (8 * (j & 3));
+      w[j >> 2] |= Fmt::enc(x[j] * inv) << (8 * (j & 3));
     if (have == 16u) {
       dev::st_stream(reinterpret_cast<uint4*>(dst + el),
                      make_uint4(w[0], w[1], w[2], w[3]));
@@ -202,14 +206,25 @@ __global__ __launch_bounds__(256) void pack_e4m3_kernel(const float* src,
   }
 }
 
-hipError_t launch_pack_e4m3(const float* src, uint8_t* dst, float* scales,
-                            size_t n, hipStream_t s) {
+template <class Fmt>
+static hipError_t launch_pack_fp8(const float* src, uint8_t* dst,
+                                  float* scales, size_t n, hipStream_t s) {
   if (n == 0) return hipSuccess;
   size_t blocks = (n + 4095) / 4096;  // 4 waves x 1024 values
   if (blocks > 8192) blocks = 8192;
-  hipLaunchKernelGGL(pack_e4m3_kernel, dim3((unsigned)blocks), dim3(256), 0,
-                     s, src, dst, scales, n);
+  hipLaunchKernelGGL(pack_fp8_kernel<Fmt>, dim3((unsigned)blocks), dim3(256),
+                     0, s, src, dst, scales, n);
   return hipGetLastError();
+}
+
+hipError_t launch_pack_e4m3(const float* src, uint8_t* dst, float* scales,
+                            size_t n, hipStream_t s) {
+  return launch_pack_fp8<dev::Fp8E4M3>(src, dst, scales, n, s);
+}
+
+hipError_t launch_pack_e5m2(const float* src, uint8_t* dst, float* scales,
+                            size_t n, hipStream_t s) {
+  return launch_pack_fp8<dev::Fp8E5M2>(src, dst, scales, n, s);
 }
 
 // ------------------------------------------------------------------- probes

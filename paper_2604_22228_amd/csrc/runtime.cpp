@@ -90,12 +90,13 @@ const std::vector<TuneRow>& tune_rows() {
   return rows;
 }
 
-bool valid_dtype(int d) { return d >= PCOLL_INT32 && d <= PCOLL_FP8_E4M3; }
+bool valid_dtype(int d) { return d >= PCOLL_INT32 && d <= PCOLL_FP8_E5M2; }
+bool is_fp8(int d) { return d == PCOLL_FP8_E4M3 || d == PCOLL_FP8_E5M2; }
 bool valid_op(int o) { return o == PCOLL_SUM || o == PCOLL_MAX; }
 
 // Partition alignment in elements: whole 16-byte vectors, 256 for e4m3.
 uint64_t part_align(int dtype) {
-  return dtype == PCOLL_FP8_E4M3 ? 256u : 16u / (uint64_t)elem_bytes(dtype);
+  return is_fp8(dtype) ? 256u : 16u / (uint64_t)elem_bytes(dtype);
 }
 
 // Algorithm 1's chunk rule with the alignment above.
@@ -293,7 +294,7 @@ pcoll_config_t default_config(const pcoll_req_s* r) {
   c.groups_per_cu = env_int("PCOLL_GROUPS_PER_CU", t.groups_per_cu);
   const bool float_sum = r->op == PCOLL_SUM && r->dtype != PCOLL_INT32;
   // compensated accumulation: on for e4m3 and for 16 ranks or more
-  int comp = float_sum && (r->dtype == PCOLL_FP8_E4M3 || r->nranks >= 16);
+  int comp = float_sum && (is_fp8(r->dtype) || r->nranks >= 16);
   comp = env_int("PCOLL_COMP", comp);
   c.comp = float_sum && comp ? 1 : 0;
   c.timeout_ms = env_int("PCOLL_TIMEOUT_MS", 10000);
@@ -323,7 +324,7 @@ int create(const std::vector<uint64_t>& counts, int dtype, int op,
   if (!valid_dtype(dtype) || !valid_op(op)) return PCOLL_ERR_ARG;
   if (nparts < 1 || nranks < 1) return PCOLL_ERR_ARG;
   if (nranks > PCOLL_MAX_RANKS) return PCOLL_ERR_UNSUPPORTED;
-  if (dtype == PCOLL_FP8_E4M3 && op == PCOLL_MAX) return PCOLL_ERR_UNSUPPORTED;
+  if (is_fp8(dtype) && op == PCOLL_MAX) return PCOLL_ERR_UNSUPPORTED;
   const uint64_t np_total = (uint64_t)nparts * counts.size();
   if (np_total > (1u << 24)) return PCOLL_ERR_UNSUPPORTED;
   for (uint64_t c : counts)
@@ -677,7 +678,7 @@ int pcoll_bind(pcoll_req_t r, const void* const* rank_bufs, void* const* outs,
                void* stream) {
   if (check_req(r)) return PCOLL_ERR_ARG;
   if (!rank_bufs || !outs) return PCOLL_ERR_ARG;
-  const bool fp8 = r->dtype == PCOLL_FP8_E4M3;
+  const bool fp8 = is_fp8(r->dtype);
   if (fp8 != (rank_scales != nullptr) || fp8 != (out_scales != nullptr))
     return PCOLL_ERR_ARG;
   const int nb = r->nbuckets, P = r->nranks;
@@ -1036,6 +1037,16 @@ int pcoll_pack_fp8(const float* src, uint8_t* dst, float* scales, size_t n,
             ((uintptr_t)dst & 15u) || ((uintptr_t)scales & 3u)))
     return PCOLL_ERR_ARG;
   HIP_TRY(launch_pack_e4m3(src, dst, scales, n,
+                           static_cast<hipStream_t>(stream)));
+  return PCOLL_SUCCESS;
+}
+
+int pcoll_pack_e5m2(const float* src, uint8_t* dst, float* scales, size_t n,
+                    void* stream) {
+  if (n && (!src || !dst || !scales || ((uintptr_t)src & 15u) ||
+            ((uintptr_t)dst & 15u) || ((uintptr_t)scales & 3u)))
+    return PCOLL_ERR_ARG;
+  HIP_TRY(launch_pack_e5m2(src, dst, scales, n,
                            static_cast<hipStream_t>(stream)));
   return PCOLL_SUCCESS;
 }

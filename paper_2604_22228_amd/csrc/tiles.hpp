@@ -106,6 +106,46 @@ __device__ __forceinline__ uint32_t f_to_e4m3(float v) {
   return (a < 0x1p-6f ? cs : cn) | sign;
 }
 
+// e5m2 (OCP E5M2) encode of a binary32 value, round to nearest even,
+// saturating at +-57344; branch-free like f_to_e4m3.
+__device__ __forceinline__ uint32_t f_to_e5m2(float v) {
+  v = fminf(fmaxf(v, -57344.0f), 57344.0f);
+  const uint32_t u = __float_as_uint(v);
+  const uint32_t sign = (u >> 24) & 0x80u;
+  const uint32_t ua = u & 0x7fffffffu;
+  const float a = __uint_as_float(ua);
+  // normal range: keep 2 fraction bits, RNE on the binary32 encoding,
+  // rebias 127 -> 15
+  const uint32_t rn = ua + 0xfffffu + ((ua >> 21) & 1u);
+  const uint32_t cn = (rn >> 21) - (112u << 2);
+  // subnormal range: multiples of 2^-16 (a * 65536 is exact), RNE to integer
+  const uint32_t cs = (uint32_t)__builtin_rintf(a * 65536.0f);
+  return (a < 0x1p-14f ? cs : cn) | sign;
+}
+
+// The two 8-bit formats: largest finite value (the block scale maps a
+// block's amax onto it), the hardware decode of a code pair, the encode.
+struct Fp8E4M3 {
+  static constexpr float kMax = 448.0f;
+  template <bool HI>
+  __device__ __forceinline__ static auto dec_pair(uint32_t w) {
+    return __builtin_amdgcn_cvt_pk_f32_fp8((int)w, HI);
+  }
+  __device__ __forceinline__ static uint32_t enc(float v) {
+    return f_to_e4m3(v);
+  }
+};
+struct Fp8E5M2 {
+  static constexpr float kMax = 57344.0f;
+  template <bool HI>
+  __device__ __forceinline__ static auto dec_pair(uint32_t w) {
+    return __builtin_amdgcn_cvt_pk_f32_bf8((int)w, HI);
+  }
+  __device__ __forceinline__ static uint32_t enc(float v) {
+    return f_to_e5m2(v);
+  }
+};
+
 // ---------------------------------------------------- 16-byte vector tiles
 // Reduces one 16-byte vector per rank into one 16-byte output vector.
 template <class Acc, int P, int Kind>
@@ -319,20 +359,22 @@ struct VecTile {
   }
 };
 
-// ------------------------------------------------------------- e4m3 tiles
+// ------------------------------------------------------ 8-bit float tiles
 // Each lane owns 16 consecutive codes; a row of 16 lanes owns one block of
 // 256 elements and its scale.  Inputs: y = sum_r fl(dec(q_r) * s_r) in
-// binary32 (plain or Sum2), then per block amax = max |y|, s = fl(amax/448)
-// (s = 1 if that is not a normal number), codes e4m3(fl(y * fl(1/s))).
+// binary32 (plain or Sum2), then per block amax = max |y|, s = fl(amax /
+// max) (max = 448 for e4m3, 57344 for e5m2; s = 1 if that is not a normal
+// number), codes enc(fl(y * fl(1/s))).
 // Tiles start on block boundaries (tile and partition lengths are multiples
 // of 256); only a bucket's last block can be short.
+template <class Fmt>
 __device__ __forceinline__ void dec16(const uint4& raw, float scale,
                                       float (&o)[16]) {
   const uint32_t w[4] = {raw.x, raw.y, raw.z, raw.w};
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[k], false);
-    auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[k], true);
+    auto lo = Fmt::template dec_pair<false>(w[k]);
+    auto hi = Fmt::template dec_pair<true>(w[k]);
     o[4 * k + 0] = lo[0] * scale;
     o[4 * k + 1] = lo[1] * scale;
     o[4 * k + 2] = hi[0] * scale;
@@ -347,8 +389,8 @@ __device__ __forceinline__ uint4 load_codes(const uint8_t* p, uint32_t have) {
   return make_uint4(w[0], w[1], w[2], w[3]);
 }
 
-template <bool COMP>
-struct E4M3Tile {
+template <bool COMP, class Fmt>
+struct Fp8Tile {
   static constexpr uint32_t kRowElems = 1024;  // 64 lanes x 16 codes
 
   // One row: lane `lane` owns codes el .. el + 16 of block blk.  FULL: the
@@ -375,14 +417,14 @@ struct E4M3Tile {
     FSum<COMP> acc[16];
     {
       float d[16];
-      dec16(raw[0], s_in[0], d);
+      dec16<Fmt>(raw[0], s_in[0], d);
 #pragma unroll
       for (int j = 0; j < 16; ++j) acc[j].init(d[j]);
     }
 #pragma unroll
     for (int r = 1; r < P; ++r) {
       float d[16];
-      dec16(raw[r], s_in[r], d);
+      dec16<Fmt>(raw[r], s_in[r], d);
 #pragma unroll
       for (int j = 0; j < 16; ++j) acc[j].add(d[j]);
     }
@@ -398,13 +440,13 @@ struct E4M3Tile {
     amax = fmaxf(amax, __shfl_xor(amax, 4, 16));
     amax = fmaxf(amax, __shfl_xor(amax, 2, 16));
     amax = fmaxf(amax, __shfl_xor(amax, 1, 16));
-    float so = amax / 448.0f;
+    float so = amax / Fmt::kMax;
     if (!(so >= 0x1p-126f)) so = 1.0f;
     const float inv = 1.0f / so;
     uint32_t w[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
     for (int j = 0; j < 16; ++j)
-      w[j >> 2] |= f_to_e4m3(y[j] * inv) << (8 * (j & 3));
+      w[j >> 2] |= Fmt::enc(y[j] * inv) << (8 * (j & 3));
     if (FULL || have == 16u) {
       st_stream(reinterpret_cast<uint4*>(out + el),
                 make_uint4(w[0], w[1], w[2], w[3]));
@@ -446,6 +488,11 @@ struct E4M3Tile {
     }
   }
 };
+
+template <bool COMP>
+using E4M3Tile = Fp8Tile<COMP, Fp8E4M3>;
+template <bool COMP>
+using E5M2Tile = Fp8Tile<COMP, Fp8E5M2>;
 
 }  // namespace dev
 }  // namespace pcoll

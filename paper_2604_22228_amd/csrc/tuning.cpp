@@ -13,6 +13,7 @@ int parse_dtype(const std::string& s) {
   if (s == "f32") return 1;
   if (s == "bf16") return 2;
   if (s == "e4m3") return 3;
+  if (s == "e5m2") return 4;
   return -2;
 }
 
@@ -95,7 +96,7 @@ TuneChoice tune_lookup(const std::vector<TuneRow>& rows, int dtype, int op,
               r.publish_batch};
   }
   // built-in default: 16 KiB of output per tile, two groups per CU
-  int elem = dtype == 2 ? 2 : (dtype == 3 ? 1 : 4);
+  int elem = dtype == 2 ? 2 : (dtype >= 3 ? 1 : 4);
   return {16384 / elem, 2, 0, 4, 16};
 }
 

@@ -16,7 +16,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpcoll.so")
 
-INT32, FLOAT32, BFLOAT16, FP8_E4M3 = 0, 1, 2, 3
+INT32, FLOAT32, BFLOAT16, FP8_E4M3, FP8_E5M2 = 0, 1, 2, 3, 4
 SUM, MAX = 0, 1
 
 SUCCESS = 0
@@ -24,7 +24,7 @@ ERR_ARG, ERR_STATE, ERR_UNSUPPORTED, ERR_HIP = -1, -2, -3, -4
 ERR_TIMEOUT, ERR_NOMEM, ERR_ABORTED = -5, -6, -7
 MAX_RANKS = 16
 
-ELEM_BYTES = {INT32: 4, FLOAT32: 4, BFLOAT16: 2, FP8_E4M3: 1}
+ELEM_BYTES = {INT32: 4, FLOAT32: 4, BFLOAT16: 2, FP8_E4M3: 1, FP8_E5M2: 1}
 
 
 class PcollError(RuntimeError):
@@ -93,6 +93,7 @@ _SIGS = {
                    C.POINTER(_sz)],
     "pcoll_pack_bf16": [_p, _p, _sz, _p],
     "pcoll_pack_fp8": [_p, _p, _p, _sz, _p],
+    "pcoll_pack_e5m2": [_p, _p, _p, _sz, _p],
     "pcoll_probe_copy": [_p, _p, _sz, _p],
     "pcoll_probe_fill": [_p, _sz, C.c_uint32, _p],
     "pcoll_device_info": [C.POINTER(_i), C.POINTER(_i), C.c_char_p, _i],
@@ -307,6 +308,11 @@ def pcoll_pack_fp8(src, dst, scales, n, stream=None):
                                  _stream(stream)), "pcoll_pack_fp8")
 
 
+def pcoll_pack_e5m2(src, dst, scales, n, stream=None):
+    _check(load().pcoll_pack_e5m2(_ptr(src), _ptr(dst), _ptr(scales), n,
+                                  _stream(stream)), "pcoll_pack_e5m2")
+
+
 def pcoll_probe_copy(dst, src, nbytes, stream=None):
     _check(load().pcoll_probe_copy(_ptr(dst), _ptr(src), nbytes,
                                    _stream(stream)), "pcoll_probe_copy")
@@ -343,7 +349,7 @@ class Request:
     """A persistent partitioned-reduction request bound to torch tensors.
 
     buckets: list of per-bucket lists of P rank tensors (one bucket for the
-    plain form); outs: one output tensor per bucket; for FP8_E4M3 also the
+    plain form); outs: one output tensor per bucket; for the 8-bit dtypes also the
     per-256 scale tensors.  The tensors are kept referenced while bound."""
 
     def __init__(self, counts, dtype, op, nparts, nranks, batched=None):
