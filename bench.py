@@ -466,35 +466,42 @@ def extras(pc, torch, synth, warmup, reps):
     del xi, yi
     torch.cuda.empty_cache()
 
-    # workload 5: e4m3, 8 ranks, 128 buckets totalling 2^30 elements
+    # workload 5: 8-bit floats (e4m3, and e5m2 on the same values), 8
+    # ranks, 128 buckets totalling 2^30 elements
     counts5 = synth.fp8_bucket_counts()
-    q5, s5 = [], []
-    for b, c in enumerate(counts5):
-        qrow, srow = [], []
-        for t in synth.normal_with_outliers_f32(
-                8, c, synth.seed_for(5) * 1000 + b, 1e-2, device=dev):
-            q = torch.empty(c, dtype=torch.uint8, device=dev)
-            s = torch.empty((c + 255) // 256, dtype=torch.float32, device=dev)
-            pc.pcoll_pack_fp8(t, q, s, c, cur)
-            qrow.append(q)
-            srow.append(s)
-        q5.append(qrow)
-        s5.append(srow)
-    torch.cuda.synchronize()
-    y5 = [torch.empty(c, dtype=torch.uint8, device=dev) for c in counts5]
-    ys5 = [torch.empty((c + 255) // 256, dtype=torch.float32, device=dev)
-           for c in counts5]
-    r5 = pc.Request(counts5, pc.FP8_E4M3, pc.SUM, 32, 8, batched=True)
-    r5.bind(q5, y5, s5, ys5, stream=stream)
-    o5 = ready_array(synth.permutation(len(counts5) * 32, 5))
-    h, d = time_requests(torch, [r5], [o5], stream, warmup, reps)
     n5 = sum(counts5)
     b5 = 9 * n5 + 9 * 4 * sum((c + 255) // 256 for c in counts5)
-    out["fp8_batched_p8_1GiB"] = {"host_ms": round(h, 4),
-                                  "kernel_ms": round(d, 4),
-                                  "GBps": round(b5 / d / 1e6, 1),
-                                  "comp": r5.config().comp}
-    r5.free()
+    o5 = ready_array(synth.permutation(len(counts5) * 32, 5))
+    for dtype, pack, key in ((pc.FP8_E4M3, pc.pcoll_pack_fp8,
+                              "fp8_batched_p8_1GiB"),
+                             (pc.FP8_E5M2, pc.pcoll_pack_e5m2,
+                              "e5m2_batched_p8_1GiB")):
+        q5, s5 = [], []
+        for b, c in enumerate(counts5):
+            qrow, srow = [], []
+            for t in synth.normal_with_outliers_f32(
+                    8, c, synth.seed_for(5) * 1000 + b, 1e-2, device=dev):
+                q = torch.empty(c, dtype=torch.uint8, device=dev)
+                s = torch.empty((c + 255) // 256, dtype=torch.float32,
+                                device=dev)
+                pack(t, q, s, c, cur)
+                qrow.append(q)
+                srow.append(s)
+            q5.append(qrow)
+            s5.append(srow)
+        torch.cuda.synchronize()
+        y5 = [torch.empty(c, dtype=torch.uint8, device=dev) for c in counts5]
+        ys5 = [torch.empty((c + 255) // 256, dtype=torch.float32,
+                           device=dev) for c in counts5]
+        r5 = pc.Request(counts5, dtype, pc.SUM, 32, 8, batched=True)
+        r5.bind(q5, y5, s5, ys5, stream=stream)
+        h, d = time_requests(torch, [r5], [o5], stream, warmup, reps)
+        out[key] = {"host_ms": round(h, 4), "kernel_ms": round(d, 4),
+                    "GBps": round(b5 / d / 1e6, 1),
+                    "comp": r5.config().comp}
+        r5.free()
+        del q5, s5, y5, ys5
+        torch.cuda.empty_cache()
     return out
 
 

@@ -31,7 +31,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-DTYPE_NAMES = {0: "i32", 1: "f32", 2: "bf16", 3: "e4m3"}
+DTYPE_NAMES = {0: "i32", 1: "f32", 2: "bf16", 3: "e4m3", 4: "e5m2"}
 OP_NAMES = {0: "sum", 1: "max"}
 
 TILES = (4096, 8192, 16384, 32768)
@@ -55,6 +55,7 @@ def default_keys():
     keys.append((0, 1, 16, 0, [1 << 24], 256))      # int32 max
     keys.append((2, 0, 8, 0, list(synth.batched_bf16_counts()), 32))
     keys.append((3, 0, 8, 0, list(synth.fp8_bucket_counts()), 32))
+    keys.append((4, 0, 8, 0, list(synth.fp8_bucket_counts()), 32))
     return keys
 
 
@@ -89,10 +90,11 @@ def time_config(pc, torch, synth, dtype, op, ranks, graph, counts, nparts,
 def make_buffers(pc, torch, synth, dtype, ranks, counts):
     dev = torch.device("cuda:0")
     tdt = {0: torch.int32, 1: torch.float32, 2: torch.int16,
-           3: torch.uint8}[dtype]
+           3: torch.uint8, 4: torch.uint8}[dtype]
     ins, outs, rsc, osc = [], [], None, None
-    if dtype == 3:
+    if dtype in (3, 4):
         rsc, osc = [], []
+    pack8 = pc.pcoll_pack_e5m2 if dtype == 4 else pc.pcoll_pack_fp8
     for b, c in enumerate(counts):
         m = max(c, 16)
         if dtype == 0:
@@ -114,7 +116,7 @@ def make_buffers(pc, torch, synth, dtype, ranks, counts):
                     q = torch.empty(m, dtype=torch.uint8, device=dev)
                     s = torch.empty((m + 255) // 256, dtype=torch.float32,
                                     device=dev)
-                    pc.pcoll_pack_fp8(t, q, s, m, torch.cuda.current_stream())
+                    pack8(t, q, s, m, torch.cuda.current_stream())
                     bucket.append(q)
                     scales.append(s)
                 rsc.append(scales)
