@@ -122,7 +122,14 @@ int pcoll_bind(pcoll_req_t req, const void *const *rank_bufs,
 /* Starts an epoch: asynchronously launches the persistent reduce kernel on
  * the bound stream (or, in graph mode, replays the cached graph; the graph
  * is captured and instantiated lazily on first use, after Algorithm 1's
- * LaunchGraph).  PCOLL_ERR_STATE if unbound or an epoch is still active. */
+ * LaunchGraph).  PCOLL_ERR_STATE if unbound or an epoch is still active.
+ *
+ * The kernel occupies its stream until every partition is ready.  Work on
+ * a stream that HIP placed on the same hardware queue runs after it (HIP
+ * spreads a process's streams over GPU_MAX_HW_QUEUES queues, 4 by
+ * default): do not make the readiness of an epoch wait for such work, for
+ * example for another request's epoch whose stream shares the queue; the
+ * epoch would end at its deadline with PCOLL_ERR_ABORTED. */
 int pcoll_start(pcoll_req_t req);
 
 /* Marks partition `part` ready (host side, non-blocking, about a store to

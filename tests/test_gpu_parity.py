@@ -579,6 +579,39 @@ def test_epochs_alternate_streams_and_modes(orc, stream):
     req.free()
 
 
+def test_two_requests_run_concurrently(orc, stream):
+    """Two requests on two streams, both epochs started before either is
+    readied, readiness interleaved, then both waited for; both outputs
+    exact.  (Whether the two kernels run side by side depends on whether
+    HIP put the streams on different hardware queues; the readiness order
+    here lets the epochs complete either way: no epoch waits for the other
+    one's completion.)"""
+    P, n, nparts = 4, 120 * 1024 + 33, 5
+    say(f"case two concurrent requests P={P} n={n}")
+    xa, xb = synth.normal_f32(P, n, 91), synth.normal_f32(P, n, 92)
+    oa, ob = torch.empty(n, device=DEV), torch.empty(n, device=DEV)
+    sa, sb = torch.cuda.Stream(DEV), torch.cuda.Stream(DEV)
+    ra = new_request([n], pc.FLOAT32, pc.SUM, nparts, P, tile_elems=2048)
+    rb = new_request([n], pc.FLOAT32, pc.SUM, nparts, P, tile_elems=2048)
+    ra.bind([[x.to(DEV) for x in xa]], [oa], stream=sa)
+    rb.bind([[x.to(DEV) for x in xb]], [ob], stream=sb)
+    torch.cuda.synchronize()
+    for epoch in range(2):
+        ra.start()
+        rb.start()
+        ra.pready_list([0, 1])
+        rb.pready_list(list(range(nparts)))
+        ra.pready_list([2, 3, 4])
+        rb.wait()
+        ra.wait()
+        torch.cuda.synchronize()
+        for x, o in ((xa, oa), (xb, ob)):
+            want = as_u32(orc.sum_f32_f32([t.numpy() for t in x]))
+            assert np.array_equal(as_u32(o.cpu().numpy()), want), epoch
+    ra.free()
+    rb.free()
+
+
 def test_rebind_hits_cache(orc, stream):
     P, n = 2, 4096
     a = [x.to(DEV) for x in synth.normal_f32(P, n, 1)]
