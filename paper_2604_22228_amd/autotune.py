@@ -39,7 +39,17 @@ GROUPS_PER_CU = (1, 2)
 INTERLEAVE = (1,)
 WAVES = (4, 8)
 BATCH = (64,)
+# 8-bit payloads: the kernels are bound by instruction issue and hide
+# memory latency with more resident waves and longer tiles
+TILES_8BIT = (16384, 32768, 65536)
+GROUPS_PER_CU_8BIT = (2, 3)
 FALLBACK = "* * * * 0 63 8192 1 1 8 64"
+
+
+def grid_for(dtype):
+    if dtype in (3, 4):
+        return [TILES_8BIT, GROUPS_PER_CU_8BIT, INTERLEAVE, WAVES, BATCH]
+    return [TILES, GROUPS_PER_CU, INTERLEAVE, WAVES, BATCH]
 
 
 def default_keys():
@@ -129,6 +139,7 @@ def make_buffers(pc, torch, synth, dtype, ranks, counts):
 
 
 def tune(keys, grid, warmup, reps, log=print):
+    """grid: the search grid, or None for each key's dtype's grid."""
     import torch
 
     from paper_2604_22228_amd import pcoll as pc
@@ -141,7 +152,7 @@ def tune(keys, grid, warmup, reps, log=print):
         lg = int(math.floor(math.log2(max(nbytes, 1))))
         best = None
         parts_list = nparts if isinstance(nparts, tuple) else (nparts,)
-        for choice in itertools.product(*grid):
+        for choice in itertools.product(*(grid or grid_for(dtype))):
             ms = statistics.mean(
                 time_config(pc, torch, synth, dtype, op, ranks, graph,
                             counts, np_, choice, warmup, reps, bufs)
@@ -160,6 +171,23 @@ def tune(keys, grid, warmup, reps, log=print):
                      best[1], best[0]))
         del bufs
         torch.cuda.empty_cache()
+    return rows
+
+
+def read_table(path):
+    """The rows of an existing table (fallback excluded), in the form
+    tune() returns them, so that a partial run can keep the other keys."""
+    rows = []
+    with open(path) as f:
+        for line in f:
+            body, _, note = line.partition("#")
+            v = body.split()
+            if len(v) != 11 or v[0] == "*":
+                continue
+            lg = int(note.split("2^")[1].split()[0])
+            ms = float(note.split()[0])
+            rows.append((v[0], v[1], int(v[2]), v[3], lg,
+                         tuple(int(x) for x in v[6:11]), ms))
     return rows
 
 
@@ -194,13 +222,25 @@ def main():
     ap.add_argument("--reps", type=int, default=7)
     ap.add_argument("--quick", action="store_true",
                     help="a reduced grid (for a smoke run)")
+    ap.add_argument("--only", default="",
+                    help="comma-separated dtypes (f32, bf16, e4m3, ...) to "
+                         "tune; the other rows of --out are kept")
     args = ap.parse_args()
     keys = default_keys()
-    grid = [TILES, GROUPS_PER_CU, INTERLEAVE, WAVES, BATCH]
+    grid = None
     if args.quick:
         keys, grid = keys[-6:-4], [(16384, 131072), (1,), (1,), (4,), (64,)]
+    kept = []
+    if args.only:
+        only = set(args.only.split(","))
+        keys = [k for k in keys if DTYPE_NAMES[k[0]] in only]
+        kept = [r for r in read_table(args.out) if r[0] not in only]
     rows = tune(keys, grid, args.warmup, args.reps,
                 log=lambda s: print(s, flush=True))
+    order = [DTYPE_NAMES[k[0]] + OP_NAMES[k[1]] + str(k[2])
+             for k in default_keys()]
+    rows = sorted(kept + rows, key=lambda r: (order.index(
+        r[0] + r[1] + str(r[2])), r[4]))
     write_table(rows, args.out)
     print(f"wrote {args.out} ({len(rows)} rows)", flush=True)
 

@@ -191,10 +191,11 @@ __global__ __launch_bounds__(256) void pack_fp8_kernel(const float* src,
     float so = amax / Fmt::kMax;
     if (!(so >= 0x1p-126f)) so = 1.0f;
     const float inv = 1.0f / so;
-    uint32_t w[4] = {0u, 0u, 0u, 0u};
+    uint32_t w[4];
 #pragma unroll
-    for (int j = 0; j < 16; ++j)
-      w[j >> 2] |= Fmt::enc(x[j] * inv) << (8 * (j & 3));
+    for (int k = 0; k < 4; ++k)
+      w[k] = Fmt::enc4(x[4 * k] * inv, x[4 * k + 1] * inv, x[4 * k + 2] * inv,
+                       x[4 * k + 3] * inv);
     if (have == 16u) {
       dev::st_stream(reinterpret_cast<uint4*>(dst + el),
                      make_uint4(w[0], w[1], w[2], w[3]));

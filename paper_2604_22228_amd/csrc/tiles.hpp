@@ -87,52 +87,29 @@ __device__ __forceinline__ uint32_t f_to_bf16(float f) {
   return u >> 16;
 }
 
-// e4m3 (OCP E4M3FN) encode of a binary32 value, round to nearest even,
-// saturating at +-448.
-// Both ranges are computed and one is selected, so that the encode has no
-// branch (a wavefront's lanes mix both ranges).
-__device__ __forceinline__ uint32_t f_to_e4m3(float v) {
-  v = fminf(fmaxf(v, -448.0f), 448.0f);
-  const uint32_t u = __float_as_uint(v);
-  const uint32_t sign = (u >> 24) & 0x80u;
-  const uint32_t ua = u & 0x7fffffffu;
-  const float a = __uint_as_float(ua);
-  // normal range: keep 3 fraction bits, RNE on the binary32 encoding,
-  // rebias 127 -> 7
-  const uint32_t rn = ua + 0x7ffffu + ((ua >> 20) & 1u);
-  const uint32_t cn = (rn >> 20) - (120u << 3);
-  // subnormal range: multiples of 2^-9 (a * 512 is exact), RNE to integer
-  const uint32_t cs = (uint32_t)__builtin_rintf(a * 512.0f);
-  return (a < 0x1p-6f ? cs : cn) | sign;
-}
-
-// e5m2 (OCP E5M2) encode of a binary32 value, round to nearest even,
-// saturating at +-57344; branch-free like f_to_e4m3.
-__device__ __forceinline__ uint32_t f_to_e5m2(float v) {
-  v = fminf(fmaxf(v, -57344.0f), 57344.0f);
-  const uint32_t u = __float_as_uint(v);
-  const uint32_t sign = (u >> 24) & 0x80u;
-  const uint32_t ua = u & 0x7fffffffu;
-  const float a = __uint_as_float(ua);
-  // normal range: keep 2 fraction bits, RNE on the binary32 encoding,
-  // rebias 127 -> 15
-  const uint32_t rn = ua + 0xfffffu + ((ua >> 21) & 1u);
-  const uint32_t cn = (rn >> 21) - (112u << 2);
-  // subnormal range: multiples of 2^-16 (a * 65536 is exact), RNE to integer
-  const uint32_t cs = (uint32_t)__builtin_rintf(a * 65536.0f);
-  return (a < 0x1p-14f ? cs : cn) | sign;
-}
-
 // The two 8-bit formats: largest finite value (the block scale maps a
-// block's amax onto it), the hardware decode of a code pair, the encode.
+// block's amax onto it), the hardware decode of a code pair, and the encode
+// of four values into one word (code j in byte j).  The gfx950 conversions
+// round to nearest even, subnormals included, but do not saturate; values
+// are clamped to +-kMax first, so that the encode saturates as the formats'
+// definitions ask.
+__device__ __forceinline__ float clamp_abs(float v, float m) {
+  return __builtin_amdgcn_fmed3f(v, -m, m);
+}
+
 struct Fp8E4M3 {
   static constexpr float kMax = 448.0f;
   template <bool HI>
   __device__ __forceinline__ static auto dec_pair(uint32_t w) {
     return __builtin_amdgcn_cvt_pk_f32_fp8((int)w, HI);
   }
-  __device__ __forceinline__ static uint32_t enc(float v) {
-    return f_to_e4m3(v);
+  __device__ __forceinline__ static uint32_t enc4(float a, float b, float c,
+                                                  float d) {
+    int w = __builtin_amdgcn_cvt_pk_fp8_f32(clamp_abs(a, kMax),
+                                            clamp_abs(b, kMax), 0, false);
+    w = __builtin_amdgcn_cvt_pk_fp8_f32(clamp_abs(c, kMax), clamp_abs(d, kMax),
+                                        w, true);
+    return (uint32_t)w;
   }
 };
 struct Fp8E5M2 {
@@ -141,8 +118,13 @@ struct Fp8E5M2 {
   __device__ __forceinline__ static auto dec_pair(uint32_t w) {
     return __builtin_amdgcn_cvt_pk_f32_bf8((int)w, HI);
   }
-  __device__ __forceinline__ static uint32_t enc(float v) {
-    return f_to_e5m2(v);
+  __device__ __forceinline__ static uint32_t enc4(float a, float b, float c,
+                                                  float d) {
+    int w = __builtin_amdgcn_cvt_pk_bf8_f32(clamp_abs(a, kMax),
+                                            clamp_abs(b, kMax), 0, false);
+    w = __builtin_amdgcn_cvt_pk_bf8_f32(clamp_abs(c, kMax), clamp_abs(d, kMax),
+                                        w, true);
+    return (uint32_t)w;
   }
 };
 
@@ -414,6 +396,9 @@ struct Fp8Tile {
         s_in[r] = have ? sc[r][blk] : 0.0f;
       }
     }
+    // every rank's codes and scale are requested before the first is used,
+    // so that one memory latency covers the row
+    if (FULL) __builtin_amdgcn_sched_barrier(0);
     FSum<COMP> acc[16];
     {
       float d[16];
@@ -443,10 +428,11 @@ struct Fp8Tile {
     float so = amax / Fmt::kMax;
     if (!(so >= 0x1p-126f)) so = 1.0f;
     const float inv = 1.0f / so;
-    uint32_t w[4] = {0u, 0u, 0u, 0u};
+    uint32_t w[4];
 #pragma unroll
-    for (int j = 0; j < 16; ++j)
-      w[j >> 2] |= Fmt::enc(y[j] * inv) << (8 * (j & 3));
+    for (int k = 0; k < 4; ++k)
+      w[k] = Fmt::enc4(y[4 * k] * inv, y[4 * k + 1] * inv, y[4 * k + 2] * inv,
+                       y[4 * k + 3] * inv);
     if (FULL || have == 16u) {
       st_stream(reinterpret_cast<uint4*>(out + el),
                 make_uint4(w[0], w[1], w[2], w[3]));

@@ -17,3 +17,17 @@ def test_host_units(tmp_path):
     r = subprocess.run([exe], capture_output=True, text=True, timeout=60)
     assert r.returncode == 0, r.stdout + r.stderr
     assert r.stdout.strip() == "ok"
+
+
+def test_autotune_table_round_trip(tmp_path):
+    """A partial retune keeps the other rows: reading the shipped table and
+    writing it again reproduces it byte for byte."""
+    from paper_2604_22228_amd import autotune
+    src = os.path.join(ROOT, "paper_2604_22228_amd", "tuned_mi355x.txt")
+    rows = autotune.read_table(src)
+    assert rows and all(len(r[5]) == 5 for r in rows)
+    out = tmp_path / "t.txt"
+    autotune.write_table(rows, str(out))
+    assert out.read_text() == open(src).read()
+    assert autotune.grid_for(3)[0] == autotune.TILES_8BIT
+    assert autotune.grid_for(1)[0] == autotune.TILES
