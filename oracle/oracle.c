@@ -35,6 +35,12 @@
  *     2 fraction bits; S.11111.00 is infinity, S.11111.xx (xx != 0) NaN; max
  *     57344; subnormal quantum 2^-16.  Encoding rounds to nearest, ties to
  *     even, and saturates at +-57344.
+ *   - MX blocks (OCP Microscaling Formats v1.0, MXFP8 with E4M3 elements):
+ *     blocks of 32 e4m3 codes share one E8M0 scale byte b, which stands for
+ *     2^(b - 127) (b = 255 is NaN).  A value is dec(q) * 2^(b - 127), exact
+ *     in binary32.  The shared exponent of a block is read here as the
+ *     smallest e >= -127 with max |x| <= 448 * 2^e, so that no code of the
+ *     block saturates (parity pinned by closed forms and brute force).
  *
  * Build with -O2 -ffp-contract=off and SSE2 arithmetic (no x87, no fast-math)
  * so that every float / double operation is one IEEE-754 RNE operation.
@@ -467,5 +473,72 @@ void orc_sum_e5m2_f32(int P, int64_t n, const uint8_t *const *q,
       if (y32) y32[i] = blk[i - lo];
     }
     orc_e5m2_pack(hi - lo, blk, yq + lo, ys + b);
+  }
+}
+
+/* ------------------------------------------------------------------ */
+/* MX blocks: e4m3 codes, one E8M0 scale per block of 32 elements       */
+/* ------------------------------------------------------------------ */
+
+double orc_e8m0_decode(uint8_t b) {
+  if (b == 255) return NAN;
+  return ldexp(1.0, (int)b - 127);
+}
+
+/* Shared exponent of one block: the smallest e >= -127 with
+ * amax <= 448 * 2^e (amax = 0 gives -127).  Found by counting up, every
+ * comparison exact in double. */
+int orc_mx_exponent(float amax) {
+  int e = -127;
+  while (ldexp(448.0, e) < (double)amax) ++e;
+  return e;
+}
+
+/* Quantize n FP32 values to MX blocks of 32 (the last block may be short):
+ * e = orc_mx_exponent(max |x|), scale byte e + 127, q = e4m3(x / 2^e); the
+ * division is exact in double and the quotient is at most 448. */
+void orc_mx_pack(int64_t n, const float *x, uint8_t *q, uint8_t *sb) {
+  for (int64_t b = 0; b * 32 < n; ++b) {
+    int64_t lo = b * 32, hi = lo + 32 < n ? lo + 32 : n;
+    float amax = 0.0f;
+    for (int64_t i = lo; i < hi; ++i) {
+      float a = fabsf(x[i]);
+      if (a > amax) amax = a;
+    }
+    int e = orc_mx_exponent(amax);
+    sb[b] = (uint8_t)(e + 127);
+    for (int64_t i = lo; i < hi; ++i)
+      q[i] = orc_e4m3_encode((double)x[i] / ldexp(1.0, e));
+  }
+}
+
+/* FP64 reference: sum over ranks of dec(q_r[i]) * 2^(b_r[i / 32] - 127). */
+void orc_sum_mx_f64(int P, int64_t n, const uint8_t *const *q,
+                    const uint8_t *const *sb, double *y) {
+  for (int64_t i = 0; i < n; ++i) {
+    double acc = 0.0;
+    for (int r = 0; r < P; ++r)
+      acc += orc_e4m3_decode(q[r][i]) * orc_e8m0_decode(sb[r][i / 32]);
+    y[i] = acc;
+  }
+}
+
+/* FP32 mirror: the dequantized inputs (exact in binary32) accumulated left
+ * to right (comp = 0) or by Sum2 (comp = 1), then re-quantized with
+ * orc_mx_pack.  y32 (optional) receives the binary32 sums. */
+void orc_sum_mx_f32(int P, int64_t n, const uint8_t *const *q,
+                    const uint8_t *const *sb, int comp, uint8_t *yq,
+                    uint8_t *ysb, float *y32) {
+  float v[64];
+  float blk[32];
+  for (int64_t b = 0; b * 32 < n; ++b) {
+    int64_t lo = b * 32, hi = lo + 32 < n ? lo + 32 : n;
+    for (int64_t i = lo; i < hi; ++i) {
+      for (int r = 0; r < P; ++r)
+        v[r] = (float)(orc_e4m3_decode(q[r][i]) * orc_e8m0_decode(sb[r][b]));
+      blk[i - lo] = acc_f32(P, v, comp);
+      if (y32) y32[i] = blk[i - lo];
+    }
+    orc_mx_pack(hi - lo, blk, yq + lo, ysb + b);
   }
 }

@@ -51,6 +51,15 @@ void orc_sum_e5m2_f32(int P, int64_t n, const uint8_t *const *q,
                       const float *const *s, int comp, uint8_t *yq,
                       float *ys, float *y32);
 
+double orc_e8m0_decode(uint8_t b);
+int orc_mx_exponent(float amax);
+void orc_mx_pack(int64_t n, const float *x, uint8_t *q, uint8_t *sb);
+void orc_sum_mx_f64(int P, int64_t n, const uint8_t *const *q,
+                    const uint8_t *const *sb, double *y);
+void orc_sum_mx_f32(int P, int64_t n, const uint8_t *const *q,
+                    const uint8_t *const *sb, int comp, uint8_t *yq,
+                    uint8_t *ysb, float *y32);
+
 #ifdef __cplusplus
 }
 #endif

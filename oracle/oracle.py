@@ -47,6 +47,11 @@ def _load(path=None):
         "orc_e5m2_pack": (None, [i64, p, p, p]),
         "orc_sum_e5m2_f64": (None, [i32, i64, p, p, p]),
         "orc_sum_e5m2_f32": (None, [i32, i64, p, p, i32, p, p, p]),
+        "orc_e8m0_decode": (C.c_double, [C.c_uint8]),
+        "orc_mx_exponent": (i32, [C.c_float]),
+        "orc_mx_pack": (None, [i64, p, p, p]),
+        "orc_sum_mx_f64": (None, [i32, i64, p, p, p]),
+        "orc_sum_mx_f32": (None, [i32, i64, p, p, i32, p, p, p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -235,6 +240,48 @@ class Oracle:
                                   self._ptr(yq), self._ptr(ys),
                                   self._ptr(y32))
         return yq, ys, y32
+
+    # ---- MX blocks: e4m3 codes, one E8M0 scale byte per 32 elements ------
+    def e8m0_decode(self, b):
+        return float(self.lib.orc_e8m0_decode(int(b)))
+
+    def mx_exponent(self, amax):
+        return int(self.lib.orc_mx_exponent(float(amax)))
+
+    def mx_pack(self, x):
+        """Returns (e4m3 codes, E8M0 scale bytes, one per 32 elements)."""
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        n = len(x)
+        q = np.empty(n, np.uint8)
+        sb = np.empty((n + 31) // 32, np.uint8)
+        self.lib.orc_mx_pack(n, self._ptr(x), self._ptr(q), self._ptr(sb))
+        return q, sb
+
+    def mx_dequant(self, q, sb):
+        """dec(q) * 2^(b - 127) per element, in double (exact)."""
+        table = self.e4m3_decode_table()
+        sc = np.array([self.e8m0_decode(b) for b in range(256)])
+        q = np.asarray(q)
+        return table[q] * np.repeat(sc[np.asarray(sb)], 32)[:len(q)]
+
+    def sum_mx_f64(self, qs, sbs):
+        arrs, tab, n = self._ptrs(qs, np.uint8)
+        sarr, stab, _ = self._ptrs(sbs, np.uint8)
+        y = np.empty(n, np.float64)
+        self.lib.orc_sum_mx_f64(len(arrs), n, tab, stab, self._ptr(y))
+        return y
+
+    def sum_mx_f32(self, qs, sbs, comp=True):
+        """Returns (e4m3 codes, E8M0 scale bytes, binary32 sums)."""
+        arrs, tab, n = self._ptrs(qs, np.uint8)
+        sarr, stab, _ = self._ptrs(sbs, np.uint8)
+        yq = np.empty(n, np.uint8)
+        ysb = np.empty((n + 31) // 32, np.uint8)
+        y32 = np.empty(n, np.float32)
+        self.lib.orc_sum_mx_f32(len(arrs), n, tab, stab, int(comp),
+                                self._ptr(yq), self._ptr(ysb),
+                                self._ptr(y32))
+        return yq, ysb, y32
 
 
 # ---- arrival model (Section 4.5: disjoint regions, completion rule) ------

@@ -68,6 +68,20 @@ MUTANTS = {
         "if (ufp < -15) ufp = -15;"),
     "e5m2_scale_uses_448": (
         "float s = amax / 57344.0f;", "float s = amax / 448.0f;"),
+    "mx_exponent_rounds_down": (
+        "while (ldexp(448.0, e) < (double)amax) ++e;",
+        "while (ldexp(448.0, e) <= (double)amax) ++e;"),
+    "e8m0_bias_128": (
+        "return ldexp(1.0, (int)b - 127);", "return ldexp(1.0, (int)b - 128);"),
+    "mx_sum_wrong_block": (
+        "acc += orc_e4m3_decode(q[r][i]) * orc_e8m0_decode(sb[r][i / 32]);",
+        "acc += orc_e4m3_decode(q[r][i]) * orc_e8m0_decode(sb[r][i / 64]);"),
+    "mx_pack_multiplies_by_scale": (
+        "q[i] = orc_e4m3_encode((double)x[i] / ldexp(1.0, e));",
+        "q[i] = orc_e4m3_encode((double)x[i] * ldexp(1.0, e));"),
+    "mx_mirror_drops_last_rank_scale": (
+        "v[r] = (float)(orc_e4m3_decode(q[r][i]) * orc_e8m0_decode(sb[r][b]));",
+        "v[r] = (float)(orc_e4m3_decode(q[r][i]) * orc_e8m0_decode(sb[0][b]));"),
     "plan_floor_instead_of_ceil": (
         "int64_t psize = (count + nparts - 1) / nparts;",
         "int64_t psize = count / nparts + (count > 0);"),

@@ -673,3 +673,136 @@ def test_e5m2_sum_error_within_bound(orc):
         e = np.abs(yv - y64) / np.maximum(absum, tau)
         assert e.max() <= 1 / 9 + 16 * U32
         assert e.max() > 0.05  # the bound is approached, not vacuous
+
+
+# --------------------------------------------------------------------------
+# MX blocks: e4m3 codes sharing one E8M0 (power-of-two) scale per 32
+# --------------------------------------------------------------------------
+def _mx_rule(amax):
+    """The shared exponent in exact rational arithmetic: the smallest
+    e >= -127 with amax <= 448 * 2^e."""
+    a = Fraction(float(amax))
+    e = -127
+    while Fraction(448) * Fraction(2) ** e < a:
+        e += 1
+    return e
+
+
+def test_e8m0_golden_values(orc):
+    for line in _rows("mx_e8m0_values.txt"):
+        b, val = line.split()
+        v = orc.e8m0_decode(int(b, 16))
+        if val == "nan":
+            assert math.isnan(v)
+        else:
+            assert v == _num(val), line
+
+
+def test_mx_exponent_golden_values(orc):
+    for line in _rows("mx_exponents.txt"):
+        amax, e = line.split()
+        assert orc.mx_exponent(_num(amax)) == int(e), line
+
+
+def test_mx_exponent_brute_force(orc):
+    rng = np.random.default_rng(31)
+    mags = 2.0 ** rng.uniform(-149, 127.9, 3000)
+    for a in np.float32(mags):
+        e = orc.mx_exponent(float(a))
+        assert e == _mx_rule(a)
+        A = Fraction(float(a))
+        assert A <= 448 * Fraction(2) ** e
+        assert e == -127 or 448 * Fraction(2) ** (e - 1) < A
+
+
+def test_mx_pack_properties(orc):
+    rng = np.random.default_rng(32)
+    n = 32 * 300 + 13  # ragged last block
+    x = (rng.standard_normal(n) * np.exp(rng.uniform(-30, 30, n))) \
+        .astype(np.float32)
+    x[64:96] = 0.0                  # an all-zero block
+    x[96:128] = np.float32(1e-40)   # a block of binary32 subnormals
+    q, sb = orc.mx_pack(x)
+    table = orc.e4m3_decode_table()
+    assert len(sb) == (n + 31) // 32
+    for b in range(len(sb)):
+        blk = x[b * 32:(b + 1) * 32].astype(np.float64)
+        qb = q[b * 32:(b + 1) * 32]
+        e = _mx_rule(np.abs(blk).max())
+        assert int(sb[b]) == e + 127
+        X = 2.0 ** e
+        # the codes are the torch e4m3 cast of x / X (exact, at most 448)
+        ref = torch.from_numpy((blk / X).astype(np.float32)) \
+            .to(torch.float8_e4m3fn).view(torch.uint8).numpy()
+        assert np.array_equal(qb, ref), b
+        # no code saturates; the largest lands in (224, 448] unless the
+        # exponent is clamped at -127
+        m = np.abs(table[qb]).max()
+        assert m <= 448.0
+        if e > -127:
+            assert m >= 224.0
+        err = np.abs(table[qb] * X - blk)
+        assert (err <= np.abs(blk) * 2.0 ** -4 + X * 2.0 ** -10).all()
+
+
+def _mx_ranks(orc, xs32):
+    out = [orc.mx_pack(x) for x in xs32]
+    return [o[0] for o in out], [o[1] for o in out]
+
+
+def test_mx_sum_reference_exact(orc):
+    rng = np.random.default_rng(33)
+    P, n = 8, 32 * 40 + 7
+    xs32 = [(rng.standard_normal(n) * 1e-2).astype(np.float32)
+            for _ in range(P)]
+    qs, sbs = _mx_ranks(orc, xs32)
+    y64 = orc.sum_mx_f64(qs, sbs)
+    table = orc.e4m3_decode_table()
+    for i in range(0, n, 3):
+        exact = sum(Fraction(float(table[qs[r][i]])) *
+                    Fraction(2) ** (int(sbs[r][i // 32]) - 127)
+                    for r in range(P))
+        assert Fraction(float(y64[i])) == exact
+
+
+def test_mx_sum_identity_and_powers_of_two(orc):
+    rng = np.random.default_rng(34)
+    n = 32 * 50 + 9
+    x = (rng.standard_normal(n) * 1e-2).astype(np.float32)
+    q, sb = orc.mx_pack(x)
+    dq = orc.mx_dequant(q, sb)
+    for comp in (False, True):
+        yq, ysb, y32 = orc.sum_mx_f32([q], [sb], comp=comp)
+        # one rank: the dequantized inputs are exact in binary32 and come
+        # back unchanged
+        assert np.array_equal(y32.astype(np.float64), dq)
+        assert np.array_equal(orc.mx_dequant(yq, ysb), dq)
+        for k in (1, 2, 3, 4):
+            zq, zsb, _ = orc.sum_mx_f32([q] * 2 ** k, [sb] * 2 ** k,
+                                        comp=comp)
+            assert np.array_equal(zq, yq)
+            assert np.array_equal(zsb.astype(int), ysb.astype(int) + k)
+
+
+def test_mx_sum_error_within_tolerance(orc):
+    """Workload-5 shaped inputs: N(0, 1e-2) with 1% outliers at 50x."""
+    rng = np.random.default_rng(35)
+    P, n = 8, 32 * 512
+    xs32 = []
+    for _ in range(P):
+        x = rng.standard_normal(n) * 1e-2
+        m = rng.uniform(size=n) < 0.01
+        x[m] *= 50
+        xs32.append(x.astype(np.float32))
+    qs, sbs = _mx_ranks(orc, xs32)
+    y64 = orc.sum_mx_f64(qs, sbs)
+    absum = np.abs(np.stack([orc.mx_dequant(qs[r], sbs[r])
+                             for r in range(P)])).sum(axis=0)
+    for comp in (False, True):
+        yq, ysb, y32 = orc.sum_mx_f32(qs, sbs, comp=comp)
+        yv = orc.mx_dequant(yq, ysb)
+        X = np.repeat(2.0 ** (ysb.astype(np.float64) - 127), 32)[:n]
+        e = np.abs(yv - y64) / np.maximum(absum, X * 2.0 ** -6)
+        assert e.max() <= 6e-2
+        e32 = np.abs(y32 - y64) / np.maximum(absum, 1e-38)
+        assert e32.max() <= (_gamma(P - 1) + U32 if not comp else 3 * U32)
