@@ -502,6 +502,34 @@ def extras(pc, torch, synth, warmup, reps):
         r5.free()
         del q5, s5, y5, ys5
         torch.cuda.empty_cache()
+    # the same values as MX blocks (e4m3 codes, one E8M0 byte per 32)
+    bmx = 9 * n5 + 9 * sum((c + 31) // 32 for c in counts5)
+    q5, s5 = [], []
+    for b, c in enumerate(counts5):
+        qrow, srow = [], []
+        for t in synth.normal_with_outliers_f32(
+                8, c, synth.seed_for(5) * 1000 + b, 1e-2, device=dev):
+            q = torch.empty(c, dtype=torch.uint8, device=dev)
+            s = torch.empty((c + 31) // 32, dtype=torch.uint8, device=dev)
+            pc.pcoll_pack_mxfp8(t, q, s, c, cur)
+            qrow.append(q)
+            srow.append(s)
+        q5.append(qrow)
+        s5.append(srow)
+    torch.cuda.synchronize()
+    y5 = [torch.empty(c, dtype=torch.uint8, device=dev) for c in counts5]
+    ys5 = [torch.empty((c + 31) // 32, dtype=torch.uint8, device=dev)
+           for c in counts5]
+    r5 = pc.Request(counts5, pc.MXFP8_E4M3, pc.SUM, 32, 8, batched=True)
+    r5.bind(q5, y5, s5, ys5, stream=stream)
+    h, d = time_requests(torch, [r5], [o5], stream, warmup, reps)
+    out["mxfp8_batched_p8_1GiB"] = {"host_ms": round(h, 4),
+                                    "kernel_ms": round(d, 4),
+                                    "GBps": round(bmx / d / 1e6, 1),
+                                    "comp": r5.config().comp}
+    r5.free()
+    del q5, s5, y5, ys5
+    torch.cuda.empty_cache()
     return out
 
 

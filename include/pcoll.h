@@ -15,10 +15,10 @@
  *
  * Partitions.  Each message is cut into `nparts` partitions by the chunk
  * rule of Algorithm 1 (Section 4.3): every partition has the same length
- * psize = ceil(count / nparts) rounded up to whole 16-byte vectors (to 256
- * elements for the 8-bit dtypes, the scale block), offsets are fixed in
- * advance as running sums, and the last partitions are clipped (possibly to
- * zero length).  Destination regions are disjoint (Section 4.5, Ordering
+ * psize = ceil(count / nparts) rounded up to whole 16-byte vectors (to
+ * whole scale blocks for the 8-bit floats: 256 elements, 32 for MX blocks),
+ * offsets are fixed in advance as running sums, and the last partitions
+ * are clipped (possibly to zero length).  Destination regions are disjoint (Section 4.5, Ordering
  * Guarantee): each partition of the output is written exactly once per
  * epoch, whatever order partitions are readied in.
  *
@@ -65,8 +65,16 @@ typedef enum {
   PCOLL_FP8_E4M3 = 3,  /* OCP e4m3 codes + one binary32 scale per 256
                           elements (value = code * scale), binary32
                           accumulation, output re-quantized per 256 */
-  PCOLL_FP8_E5M2 = 4   /* OCP e5m2 codes (2 fraction bits, range 57344),
+  PCOLL_FP8_E5M2 = 4,  /* OCP e5m2 codes (2 fraction bits, range 57344),
                           otherwise as PCOLL_FP8_E4M3 */
+  PCOLL_MXFP8_E4M3 = 5 /* OCP MX blocks (Microscaling Formats v1.0, MXFP8
+                          with e4m3 elements): e4m3 codes, one E8M0 scale
+                          byte b per 32 elements (value = code * 2^(b-127),
+                          exact in binary32); binary32 accumulation; output
+                          re-quantized per 32 with the smallest power-of-two
+                          scale (>= 2^-127) under which no code exceeds 448.
+                          Scale byte 0xFF (NaN) is not accepted as input:
+                          such blocks give unspecified results. */
 } pcoll_dtype_t;
 
 typedef enum { PCOLL_SUM = 0, PCOLL_MAX = 1 } pcoll_op_t;
@@ -108,14 +116,16 @@ int pcoll_init_batch(int nbuckets, const size_t *counts, int dtype, int op,
  *   outs       nbuckets device pointers (may equal a rank buffer only if
  *              the caller accepts that rank's input being overwritten
  *              partition by partition).
- *   rank_scales / out_scales: 8-bit dtypes only (else NULL): per-256
- *              binary32 scales, laid out like rank_bufs / outs, with
- *              ceil(count / 256) entries per bucket.
+ *   rank_scales / out_scales: 8-bit dtypes only (else NULL), laid out
+ *              like rank_bufs / outs: for PCOLL_FP8_E4M3 / _E5M2 binary32
+ *              scales (4-byte aligned), ceil(count / 256) per bucket; for
+ *              PCOLL_MXFP8_E4M3 E8M0 bytes (any alignment), ceil(count /
+ *              32) per bucket.
  * Not allowed while an epoch is active.  A binding seen before (same
  * pointers and stream) reuses its cached descriptor table and graph. */
 int pcoll_bind(pcoll_req_t req, const void *const *rank_bufs,
-               void *const *outs, const float *const *rank_scales,
-               float *const *out_scales, void *stream);
+               void *const *outs, const void *const *rank_scales,
+               void *const *out_scales, void *stream);
 
 /* --------------------------------------------------------------- epochs */
 
@@ -335,6 +345,14 @@ int pcoll_pack_fp8(const float *src, uint8_t *dst, float *scales, size_t n,
  * +-57344, round to nearest even. */
 int pcoll_pack_e5m2(const float *src, uint8_t *dst, float *scales, size_t n,
                     void *stream);
+
+/* MX blocks of 32 (the last block may be short): scale byte b = e + 127
+ * for the smallest e >= -127 with max |src| <= 448 * 2^e (b = 0 for an
+ * all-zero block), dst[i] = e4m3(src[i] / 2^e), round to nearest even
+ * (never saturating).  scales holds ceil(n / 32) bytes; src and dst are
+ * 16-byte aligned. */
+int pcoll_pack_mxfp8(const float *src, uint8_t *dst, uint8_t *scales,
+                     size_t n, void *stream);
 
 /* --------------------------------------------------- measurement probes */
 

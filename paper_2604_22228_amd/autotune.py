@@ -31,7 +31,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-DTYPE_NAMES = {0: "i32", 1: "f32", 2: "bf16", 3: "e4m3", 4: "e5m2"}
+DTYPE_NAMES = {0: "i32", 1: "f32", 2: "bf16", 3: "e4m3", 4: "e5m2",
+               5: "mxfp8"}
 OP_NAMES = {0: "sum", 1: "max"}
 
 TILES = (4096, 8192, 16384, 32768)
@@ -47,7 +48,7 @@ FALLBACK = "* * * * 0 63 8192 1 1 8 64"
 
 
 def grid_for(dtype):
-    if dtype in (3, 4):
+    if dtype in (3, 4, 5):
         return [TILES_8BIT, GROUPS_PER_CU_8BIT, INTERLEAVE, WAVES, BATCH]
     return [TILES, GROUPS_PER_CU, INTERLEAVE, WAVES, BATCH]
 
@@ -66,6 +67,7 @@ def default_keys():
     keys.append((2, 0, 8, 0, list(synth.batched_bf16_counts()), 32))
     keys.append((3, 0, 8, 0, list(synth.fp8_bucket_counts()), 32))
     keys.append((4, 0, 8, 0, list(synth.fp8_bucket_counts()), 32))
+    keys.append((5, 0, 8, 0, list(synth.fp8_bucket_counts()), 32))
     return keys
 
 
@@ -100,11 +102,14 @@ def time_config(pc, torch, synth, dtype, op, ranks, graph, counts, nparts,
 def make_buffers(pc, torch, synth, dtype, ranks, counts):
     dev = torch.device("cuda:0")
     tdt = {0: torch.int32, 1: torch.float32, 2: torch.int16,
-           3: torch.uint8, 4: torch.uint8}[dtype]
+           3: torch.uint8, 4: torch.uint8, 5: torch.uint8}[dtype]
     ins, outs, rsc, osc = [], [], None, None
-    if dtype in (3, 4):
+    if dtype in (3, 4, 5):
         rsc, osc = [], []
-    pack8 = pc.pcoll_pack_e5m2 if dtype == 4 else pc.pcoll_pack_fp8
+    pack8 = {3: pc.pcoll_pack_fp8, 4: pc.pcoll_pack_e5m2,
+             5: pc.pcoll_pack_mxfp8}.get(dtype)
+    # scale blocks: binary32 per 256 elements, or E8M0 bytes per 32
+    blk, sdt = (32, torch.uint8) if dtype == 5 else (256, torch.float32)
     for b, c in enumerate(counts):
         m = max(c, 16)
         if dtype == 0:
@@ -124,13 +129,13 @@ def make_buffers(pc, torch, synth, dtype, ranks, counts):
                 bucket, scales = [], []
                 for t in x:
                     q = torch.empty(m, dtype=torch.uint8, device=dev)
-                    s = torch.empty((m + 255) // 256, dtype=torch.float32,
+                    s = torch.empty((m + blk - 1) // blk, dtype=sdt,
                                     device=dev)
                     pack8(t, q, s, m, torch.cuda.current_stream())
                     bucket.append(q)
                     scales.append(s)
                 rsc.append(scales)
-                osc.append(torch.empty((m + 255) // 256, dtype=torch.float32,
+                osc.append(torch.empty((m + blk - 1) // blk, dtype=sdt,
                                        device=dev))
         ins.append(bucket)
         outs.append(torch.empty(m, dtype=tdt, device=dev))

@@ -1,6 +1,7 @@
 // Dispatch of the reduce kernel, and the small kernels around it: the
 // device-side ready signal, the producer-side packers (FP32 -> bf16,
-// FP32 -> e4m3 with per-256 scales), and the measurement probes.
+// FP32 -> e4m3 / e5m2 with per-256 scales, FP32 -> MX blocks), and the
+// measurement probes.
 #include <hip/hip_runtime.h>
 
 #include "reduce_impl.hpp"
@@ -25,6 +26,9 @@ hipError_t launch_reduce(const ReduceArgs& a, int dtype, int op, bool comp,
     case kE5M2:
       if (op != kSum) return hipErrorInvalidValue;
       return launch_reduce_e5m2(a, comp, nranks, groups, waves, s);
+    case kMX:
+      if (op != kSum) return hipErrorInvalidValue;
+      return launch_reduce_mx(a, comp, nranks, groups, waves, s);
     default:
       return hipErrorInvalidValue;
   }
@@ -226,6 +230,58 @@ hipError_t launch_pack_e4m3(const float* src, uint8_t* dst, float* scales,
 hipError_t launch_pack_e5m2(const float* src, uint8_t* dst, float* scales,
                             size_t n, hipStream_t s) {
   return launch_pack_fp8<dev::Fp8E5M2>(src, dst, scales, n, s);
+}
+
+// One pair of lanes per MX block of 32 values, 16 values per lane.
+__global__ __launch_bounds__(256) void pack_mx_kernel(const float* src,
+                                                      uint8_t* dst,
+                                                      uint8_t* scales,
+                                                      size_t n) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const size_t wave = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+  const size_t nwaves = (size_t)gridDim.x * blockDim.x / 64;
+  for (size_t base = wave * 1024; base < n; base += nwaves * 1024) {
+    const size_t el = base + (size_t)lane * 16;
+    const uint32_t have = el < n ? (n - el < 16 ? (uint32_t)(n - el) : 16u) : 0u;
+    float x[16];
+    if (have == 16u) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint4 v = dev::ld_stream(reinterpret_cast<const uint4*>(src + el) + k);
+        x[4 * k + 0] = __uint_as_float(v.x);
+        x[4 * k + 1] = __uint_as_float(v.y);
+        x[4 * k + 2] = __uint_as_float(v.z);
+        x[4 * k + 3] = __uint_as_float(v.w);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) x[j] = (uint32_t)j < have ? src[el + j] : 0.0f;
+    }
+    float amax = 0.0f;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) amax = fmaxf(amax, fabsf(x[j]));
+    amax = dev::pair_max(amax);
+    const uint32_t b = dev::mx_scale_byte(amax);
+    const uint4 codes = dev::mx_enc16(x, dev::e8m0_operand(b));
+    if (have == 16u) {
+      dev::st_stream(reinterpret_cast<uint4*>(dst + el), codes);
+    } else if (have) {
+      const uint32_t w[4] = {codes.x, codes.y, codes.z, codes.w};
+      for (uint32_t j = 0; j < have; ++j)
+        dst[el + j] = (uint8_t)(w[j >> 2] >> (8 * (j & 3)));
+    }
+    if (have && (lane & 1u) == 0u) scales[el / 32] = (uint8_t)b;
+  }
+}
+
+hipError_t launch_pack_mx(const float* src, uint8_t* dst, uint8_t* scales,
+                          size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  size_t blocks = (n + 4095) / 4096;  // 4 waves x 1024 values
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(pack_mx_kernel, dim3((unsigned)blocks), dim3(256), 0, s,
+                     src, dst, scales, n);
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------------------- probes

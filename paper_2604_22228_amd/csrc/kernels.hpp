@@ -14,12 +14,17 @@ namespace pcoll {
 constexpr int kMaxWavesPerGroup = 8;
 
 // Dtype / op codes, equal to the public enums of pcoll.h.
-enum Dtype : int { kI32 = 0, kF32 = 1, kBF16 = 2, kE4M3 = 3, kE5M2 = 4 };
+enum Dtype : int {
+  kI32 = 0, kF32 = 1, kBF16 = 2, kE4M3 = 3, kE5M2 = 4, kMX = 5
+};
 enum Op : int { kSum = 0, kMax = 1 };
 
 // Elements per 16-byte vector and alignment unit of partitions.
 inline int elem_bytes(int dtype) {
-  return dtype == kBF16 ? 2 : (dtype == kE4M3 || dtype == kE5M2 ? 1 : 4);
+  return dtype == kBF16 ? 2
+                        : (dtype == kE4M3 || dtype == kE5M2 || dtype == kMX
+                               ? 1
+                               : 4);
 }
 
 // The persistent partitioned-reduce kernel: `groups` workgroups of `waves`
@@ -42,6 +47,9 @@ hipError_t launch_pack_e4m3(const float* src, uint8_t* dst, float* scales,
                             size_t n, hipStream_t s);
 hipError_t launch_pack_e5m2(const float* src, uint8_t* dst, float* scales,
                             size_t n, hipStream_t s);
+// FP32 -> MX blocks: e4m3 codes and one E8M0 scale byte per 32 elements.
+hipError_t launch_pack_mx(const float* src, uint8_t* dst, uint8_t* scales,
+                          size_t n, hipStream_t s);
 // Measurement probes: a dwordx4 streaming copy and a fill.
 hipError_t launch_copy(void* dst, const void* src, size_t bytes,
                        hipStream_t s);

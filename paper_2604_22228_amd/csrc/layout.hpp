@@ -23,9 +23,11 @@ constexpr int kMaxPublishBatch = 64;
 // kernels.
 struct BucketDesc {
   const void* in[kMaxRanks];        // rank contributions (device pointers)
-  const float* in_scale[kMaxRanks]; // e4m3 only: per-256 block scales
+  const void* in_scale[kMaxRanks];  // 8-bit floats only: block scales
+                                    // (binary32 per 256 elements, or E8M0
+                                    // bytes per 32 for MX blocks)
   void* out;                        // reduced message
-  float* out_scale;                 // e4m3 only: per-256 output scales
+  void* out_scale;                  // 8-bit floats only: output scales
   uint64_t count;                   // elements in the bucket
   uint64_t reserved;
 };

@@ -90,12 +90,18 @@ const std::vector<TuneRow>& tune_rows() {
   return rows;
 }
 
-bool valid_dtype(int d) { return d >= PCOLL_INT32 && d <= PCOLL_FP8_E5M2; }
-bool is_fp8(int d) { return d == PCOLL_FP8_E4M3 || d == PCOLL_FP8_E5M2; }
+bool valid_dtype(int d) { return d >= PCOLL_INT32 && d <= PCOLL_MXFP8_E4M3; }
+// 8-bit floats: codes plus block scales (binary32 per 256 elements, or
+// E8M0 bytes per 32 for MX blocks)
+bool is_fp8(int d) {
+  return d == PCOLL_FP8_E4M3 || d == PCOLL_FP8_E5M2 || d == PCOLL_MXFP8_E4M3;
+}
 bool valid_op(int o) { return o == PCOLL_SUM || o == PCOLL_MAX; }
 
-// Partition alignment in elements: whole 16-byte vectors, 256 for e4m3.
+// Partition alignment in elements: whole 16-byte vectors, whole scale
+// blocks for the 8-bit floats (256 elements, 32 for MX blocks).
 uint64_t part_align(int dtype) {
+  if (dtype == PCOLL_MXFP8_E4M3) return 32u;
   return is_fp8(dtype) ? 256u : 16u / (uint64_t)elem_bytes(dtype);
 }
 
@@ -674,7 +680,7 @@ int pcoll_init_batch(int nbuckets, const size_t* counts, int dtype, int op,
 }
 
 int pcoll_bind(pcoll_req_t r, const void* const* rank_bufs, void* const* outs,
-               const float* const* rank_scales, float* const* out_scales,
+               const void* const* rank_scales, void* const* out_scales,
                void* stream) {
   if (check_req(r)) return PCOLL_ERR_ARG;
   if (!rank_bufs || !outs) return PCOLL_ERR_ARG;
@@ -691,10 +697,11 @@ int pcoll_bind(pcoll_req_t r, const void* const* rank_bufs, void* const* outs,
   for (int b = 0; b < nb; ++b)
     if (bad(outs[b], b, 16)) return PCOLL_ERR_ARG;
   if (fp8) {
+    const uintptr_t sa = r->dtype == PCOLL_MXFP8_E4M3 ? 1 : 4;  // E8M0 bytes
     for (int i = 0; i < nb * P; ++i)
-      if (bad(rank_scales[i], i / P, 4)) return PCOLL_ERR_ARG;
+      if (bad(rank_scales[i], i / P, sa)) return PCOLL_ERR_ARG;
     for (int b = 0; b < nb; ++b)
-      if (bad(out_scales[b], b, 4)) return PCOLL_ERR_ARG;
+      if (bad(out_scales[b], b, sa)) return PCOLL_ERR_ARG;
   }
   if (r->active) return PCOLL_ERR_STATE;
   try {
@@ -1048,6 +1055,16 @@ int pcoll_pack_e5m2(const float* src, uint8_t* dst, float* scales, size_t n,
     return PCOLL_ERR_ARG;
   HIP_TRY(launch_pack_e5m2(src, dst, scales, n,
                            static_cast<hipStream_t>(stream)));
+  return PCOLL_SUCCESS;
+}
+
+int pcoll_pack_mxfp8(const float* src, uint8_t* dst, uint8_t* scales,
+                     size_t n, void* stream) {
+  if (n && (!src || !dst || !scales || ((uintptr_t)src & 15u) ||
+            ((uintptr_t)dst & 15u)))
+    return PCOLL_ERR_ARG;
+  HIP_TRY(launch_pack_mx(src, dst, scales, n,
+                         static_cast<hipStream_t>(stream)));
   return PCOLL_SUCCESS;
 }
 

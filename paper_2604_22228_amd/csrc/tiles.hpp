@@ -455,10 +455,10 @@ struct Fp8Tile {
 #pragma unroll
     for (int r = 0; r < P; ++r) {
       in[r] = static_cast<const uint8_t*>(bd->in[r]) + poff;
-      sc[r] = bd->in_scale[r] + poff / 256u;
+      sc[r] = static_cast<const float*>(bd->in_scale[r]) + poff / 256u;
     }
     uint8_t* out = static_cast<uint8_t*>(bd->out) + poff;
-    float* osc = bd->out_scale + poff / 256u;
+    float* osc = static_cast<float*>(bd->out_scale) + poff / 256u;
     const uint32_t n = (uint32_t)plen;
     const uint32_t nrows = (n + kRowElems - 1) / kRowElems;
     const RowSet rows(lt, nt, (nrows + nt - 1) / nt, inter, nrows);
@@ -479,6 +479,164 @@ template <bool COMP>
 using E4M3Tile = Fp8Tile<COMP, Fp8E4M3>;
 template <bool COMP>
 using E5M2Tile = Fp8Tile<COMP, Fp8E5M2>;
+
+// ------------------------------------------------------------- MX blocks
+// OCP MX blocks with e4m3 elements: 32 codes share one E8M0 scale byte b,
+// the value of a code being dec(q) * 2^(b - 127) (exact in binary32).  The
+// gfx950 scaled conversions take such a scale as a binary32 operand whose
+// exponent field is b: v_cvt_scalef32_pk_f32_fp8 multiplies a decoded pair
+// by 2^(b - 127), v_cvt_scalef32_pk_fp8_f32 divides a pair by it and rounds
+// to nearest even (without saturating).
+typedef float mx_f32x2 __attribute__((ext_vector_type(2)));
+typedef short mx_i16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ float e8m0_operand(uint32_t b) {
+  return __uint_as_float(b << 23);
+}
+
+// Scale byte of a block whose largest magnitude is amax: e + 127 for the
+// smallest e >= -127 with amax <= 448 * 2^e = 1.75 * 2^(e + 8).  For
+// amax = f * 2^E (f in [1, 2)) that is e = E - 8 when f <= 1.75 (fraction
+// field <= 0x600000), else E - 7; zero and subnormal amax (E < -126) give
+// -127.  The codes of the block then never exceed 448 in magnitude.
+__device__ __forceinline__ uint32_t mx_scale_byte(float amax) {
+  const uint32_t u = __float_as_uint(amax);
+  const int e = (int)(u >> 23) - 135 + ((u & 0x7fffffu) > 0x600000u ? 1 : 0);
+  return u < 0x00800000u ? 0u : (uint32_t)(max(e, -127) + 127);
+}
+
+// 16 codes (one lane's half block) scaled by the operand of byte b.
+__device__ __forceinline__ void mx_dec16(const uint4& raw, float scale,
+                                         float (&o)[16]) {
+  const uint32_t w[4] = {raw.x, raw.y, raw.z, raw.w};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const mx_f32x2 lo =
+        __builtin_amdgcn_cvt_scalef32_pk_f32_fp8(w[k], scale, false);
+    const mx_f32x2 hi =
+        __builtin_amdgcn_cvt_scalef32_pk_f32_fp8(w[k], scale, true);
+    o[4 * k + 0] = lo[0];
+    o[4 * k + 1] = lo[1];
+    o[4 * k + 2] = hi[0];
+    o[4 * k + 3] = hi[1];
+  }
+}
+
+// Codes of y[0..16) / 2^(b - 127), four per word (code j in byte j).
+__device__ __forceinline__ uint4 mx_enc16(const float (&y)[16], float scale) {
+  uint32_t w[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    mx_i16x2 t = __builtin_amdgcn_cvt_scalef32_pk_fp8_f32(
+        mx_i16x2{0, 0}, y[4 * k], y[4 * k + 1], scale, false);
+    t = __builtin_amdgcn_cvt_scalef32_pk_fp8_f32(t, y[4 * k + 2],
+                                                 y[4 * k + 3], scale, true);
+    w[k] = __builtin_bit_cast(uint32_t, t);
+  }
+  return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+// Largest magnitude over a pair of lanes (2j, 2j + 1): one block.
+__device__ __forceinline__ float pair_max(float v) {
+  const int o = __builtin_amdgcn_mov_dpp(__float_as_int(v), 0xb1, 0xf, 0xf,
+                                         false);  // quad_perm [1, 0, 3, 2]
+  return fmaxf(v, __int_as_float(o));
+}
+
+// Each lane owns 16 consecutive codes, half of a block; lanes 2j and 2j + 1
+// of a row share block j and its scale byte.  y = sum_r dec(q_r) *
+// 2^(b_r - 127) in binary32 (plain or Sum2), per block the scale byte of
+// max |y| (mx_scale_byte), codes RNE(y / 2^(b - 127)).  Partitions start on
+// block boundaries (their lengths are multiples of 32); only a bucket's
+// last block can be short.
+template <bool COMP>
+struct MxTile {
+  static constexpr uint32_t kRowElems = 1024;  // 64 lanes x 16 codes
+
+  template <int P, bool FULL>
+  __device__ __forceinline__ static void row(const uint8_t* const (&in)[P],
+                                             const uint8_t* const (&sc)[P],
+                                             uint8_t* out, uint8_t* osc,
+                                             uint32_t el, uint32_t have) {
+    const uint32_t blk = el / 32u;
+    uint4 raw[P];
+    uint32_t b_in[P];
+#pragma unroll
+    for (int r = 0; r < P; ++r) {
+      if (FULL) {
+        raw[r] = ld_stream(reinterpret_cast<const uint4*>(in[r] + el));
+        b_in[r] = sc[r][blk];
+      } else {
+        raw[r] = have ? load_codes(in[r] + el, have) : make_uint4(0, 0, 0, 0);
+        b_in[r] = have ? sc[r][blk] : 0u;
+      }
+    }
+    if (FULL) __builtin_amdgcn_sched_barrier(0);
+    FSum<COMP> acc[16];
+    {
+      float d[16];
+      mx_dec16(raw[0], e8m0_operand(b_in[0]), d);
+#pragma unroll
+      for (int j = 0; j < 16; ++j) acc[j].init(d[j]);
+    }
+#pragma unroll
+    for (int r = 1; r < P; ++r) {
+      float d[16];
+      mx_dec16(raw[r], e8m0_operand(b_in[r]), d);
+#pragma unroll
+      for (int j = 0; j < 16; ++j) acc[j].add(d[j]);
+    }
+    float y[16];
+    float amax = 0.0f;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      y[j] = acc[j].get();
+      if (FULL || (uint32_t)j < have) amax = fmaxf(amax, fabsf(y[j]));
+    }
+    amax = pair_max(amax);
+    const uint32_t b = mx_scale_byte(amax);
+    const uint4 codes = mx_enc16(y, e8m0_operand(b));
+    if (FULL || have == 16u) {
+      st_stream(reinterpret_cast<uint4*>(out + el), codes);
+    } else if (have) {
+      const uint32_t w[4] = {codes.x, codes.y, codes.z, codes.w};
+      for (uint32_t j = 0; j < have; ++j)
+        out[el + j] = (uint8_t)(w[j >> 2] >> (8 * (j & 3)));
+    }
+    if ((FULL || have) && (lane_id() & 1u) == 0u) osc[blk] = (uint8_t)b;
+  }
+
+  template <int P>
+  __device__ __forceinline__ static void run(const_ptr<BucketDesc> bd,
+                                             uint64_t poff, uint64_t plen,
+                                             uint32_t lt, uint32_t nt,
+                                             uint32_t inter, uint32_t wave,
+                                             uint32_t nwaves) {
+    const uint32_t lane = lane_id();
+    const uint8_t* in[P];
+    const uint8_t* sc[P];
+#pragma unroll
+    for (int r = 0; r < P; ++r) {
+      in[r] = static_cast<const uint8_t*>(bd->in[r]) + poff;
+      sc[r] = static_cast<const uint8_t*>(bd->in_scale[r]) + poff / 32u;
+    }
+    uint8_t* out = static_cast<uint8_t*>(bd->out) + poff;
+    uint8_t* osc = static_cast<uint8_t*>(bd->out_scale) + poff / 32u;
+    const uint32_t n = (uint32_t)plen;
+    const uint32_t nrows = (n + kRowElems - 1) / kRowElems;
+    const RowSet rows(lt, nt, (nrows + nt - 1) / nt, inter, nrows);
+    for (uint32_t k = wave; k < rows.limit; k += nwaves) {
+      const uint32_t q = rows.row(k);
+      const uint32_t el = q * kRowElems + lane * 16u;
+      if ((q + 1u) * kRowElems <= n) {  // uniform: the row is whole
+        row<P, true>(in, sc, out, osc, el, 16u);
+      } else {
+        const uint32_t have = el < n ? (n - el < 16u ? n - el : 16u) : 0u;
+        row<P, false>(in, sc, out, osc, el, have);
+      }
+    }
+  }
+};
 
 }  // namespace dev
 }  // namespace pcoll

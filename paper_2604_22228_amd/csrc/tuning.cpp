@@ -14,6 +14,7 @@ int parse_dtype(const std::string& s) {
   if (s == "bf16") return 2;
   if (s == "e4m3") return 3;
   if (s == "e5m2") return 4;
+  if (s == "mxfp8") return 5;
   return -2;
 }
 

@@ -16,7 +16,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpcoll.so")
 
-INT32, FLOAT32, BFLOAT16, FP8_E4M3, FP8_E5M2 = 0, 1, 2, 3, 4
+INT32, FLOAT32, BFLOAT16, FP8_E4M3, FP8_E5M2, MXFP8_E4M3 = 0, 1, 2, 3, 4, 5
 SUM, MAX = 0, 1
 
 SUCCESS = 0
@@ -24,7 +24,8 @@ ERR_ARG, ERR_STATE, ERR_UNSUPPORTED, ERR_HIP = -1, -2, -3, -4
 ERR_TIMEOUT, ERR_NOMEM, ERR_ABORTED = -5, -6, -7
 MAX_RANKS = 16
 
-ELEM_BYTES = {INT32: 4, FLOAT32: 4, BFLOAT16: 2, FP8_E4M3: 1, FP8_E5M2: 1}
+ELEM_BYTES = {INT32: 4, FLOAT32: 4, BFLOAT16: 2, FP8_E4M3: 1, FP8_E5M2: 1,
+              MXFP8_E4M3: 1}
 
 
 class PcollError(RuntimeError):
@@ -94,6 +95,7 @@ _SIGS = {
     "pcoll_pack_bf16": [_p, _p, _sz, _p],
     "pcoll_pack_fp8": [_p, _p, _p, _sz, _p],
     "pcoll_pack_e5m2": [_p, _p, _p, _sz, _p],
+    "pcoll_pack_mxfp8": [_p, _p, _p, _sz, _p],
     "pcoll_probe_copy": [_p, _p, _sz, _p],
     "pcoll_probe_fill": [_p, _sz, C.c_uint32, _p],
     "pcoll_device_info": [C.POINTER(_i), C.POINTER(_i), C.c_char_p, _i],
@@ -311,6 +313,13 @@ def pcoll_pack_fp8(src, dst, scales, n, stream=None):
 def pcoll_pack_e5m2(src, dst, scales, n, stream=None):
     _check(load().pcoll_pack_e5m2(_ptr(src), _ptr(dst), _ptr(scales), n,
                                   _stream(stream)), "pcoll_pack_e5m2")
+
+
+def pcoll_pack_mxfp8(src, dst, scales, n, stream=None):
+    """MX blocks: e4m3 codes to dst, one E8M0 scale byte per 32 elements
+    to scales (uint8)."""
+    _check(load().pcoll_pack_mxfp8(_ptr(src), _ptr(dst), _ptr(scales), n,
+                                   _stream(stream)), "pcoll_pack_mxfp8")
 
 
 def pcoll_probe_copy(dst, src, nbytes, stream=None):

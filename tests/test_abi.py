@@ -62,7 +62,8 @@ def test_version_and_strerror():
 @pytest.mark.parametrize("dtype,align", [(pc.INT32, 4), (pc.FLOAT32, 4),
                                          (pc.BFLOAT16, 8),
                                          (pc.FP8_E4M3, 256),
-                                         (pc.FP8_E5M2, 256)])
+                                         (pc.FP8_E5M2, 256),
+                                         (pc.MXFP8_E4M3, 32)])
 def test_plan_matches_oracle(dtype, align):
     orc = get_oracle()
     for count in list(range(0, 70)) + [255, 256, 1000, 262144, 262144 + 37,
@@ -90,7 +91,8 @@ def test_plan_rejects_bad_arguments():
     ((100, pc.FLOAT32, pc.SUM, 4, 17), pc.ERR_UNSUPPORTED),
     ((100, pc.FP8_E4M3, pc.MAX, 4, 4), pc.ERR_UNSUPPORTED),
     ((100, pc.FP8_E5M2, pc.MAX, 4, 4), pc.ERR_UNSUPPORTED),
-    ((100, 5, pc.SUM, 4, 4), pc.ERR_ARG),           # no dtype 5
+    ((100, pc.MXFP8_E4M3, pc.MAX, 4, 4), pc.ERR_UNSUPPORTED),
+    ((100, 6, pc.SUM, 4, 4), pc.ERR_ARG),           # no dtype 6
     # a partition beyond 2^31 elements (the kernels' 32-bit row indices)
     ((1 << 33, pc.FLOAT32, pc.SUM, 1, 4), pc.ERR_UNSUPPORTED),
     ((1 << 41, pc.INT32, pc.SUM, 4096, 4), pc.ERR_UNSUPPORTED),
@@ -129,17 +131,19 @@ def test_probe_and_pack_reject_unaligned_sizes():
     assert lib.pcoll_probe_fill(None, 17, 0, None) == pc.ERR_ARG
     assert lib.pcoll_pack_bf16(None, None, 8, None) == pc.ERR_ARG
     assert lib.pcoll_pack_fp8(None, None, None, 8, None) == pc.ERR_ARG
+    assert lib.pcoll_pack_mxfp8(None, None, None, 8, None) == pc.ERR_ARG
+    assert lib.pcoll_pack_mxfp8(None, None, None, 0, None) == 0
     # zero-length packs are no-ops that need no device
     assert lib.pcoll_pack_bf16(None, None, 0, None) == 0
 
 
 def test_plan_partitions_are_aligned_for_vectors():
     for dtype in (pc.INT32, pc.FLOAT32, pc.BFLOAT16, pc.FP8_E4M3,
-                  pc.FP8_E5M2):
+                  pc.FP8_E5M2, pc.MXFP8_E4M3):
         for count in (1, 7, 1000, 123457):
             ps, offs, lens = pc.pcoll_plan(count, dtype, 8)
-            unit = 256 if dtype in (pc.FP8_E4M3, pc.FP8_E5M2) \
-                else 16 // pc.ELEM_BYTES[dtype]
+            unit = {pc.FP8_E4M3: 256, pc.FP8_E5M2: 256,
+                    pc.MXFP8_E4M3: 32}.get(dtype, 16 // pc.ELEM_BYTES[dtype])
             assert all(o % unit == 0 for o, n in zip(offs, lens) if n)
             assert sum(lens) == count
             assert np.all(np.diff(offs) >= 0)

@@ -215,3 +215,59 @@ def test_workload5_fp8_full(orc):
                                 "max_norm_err": worst}))
     assert worst <= 6e-2
     req.free()
+
+
+def test_workload5_mx_full(orc):
+    """The fp8 workload's shape (8 ranks, 128 buckets, 2^30 elements per
+    rank, N(0, 1e-2) with 1% outliers at 50x) as MX blocks, at library
+    defaults; sampled whole 32-element blocks against the oracle."""
+    counts = synth.fp8_bucket_counts()
+    P, nparts = 8, 32
+    say(f"case mx full buckets={len(counts)} elements/rank={sum(counts)}")
+    stream = torch.cuda.Stream(DEV)
+    cur = torch.cuda.current_stream(DEV)
+    qs, ss, oq, osb = [], [], [], []
+    for b, c in enumerate(counts):
+        qrow, srow = [], []
+        for t in synth.normal_with_outliers_f32(
+                P, c, synth.seed_for(5) * 1000 + b, 1e-2, device=DEV):
+            q = torch.empty(c, dtype=torch.uint8, device=DEV)
+            s = torch.empty((c + 31) // 32, dtype=torch.uint8, device=DEV)
+            pc.pcoll_pack_mxfp8(t, q, s, c, cur)
+            qrow.append(q)
+            srow.append(s)
+        qs.append(qrow)
+        ss.append(srow)
+        oq.append(torch.full((c,), 0x7F, dtype=torch.uint8, device=DEV))
+        osb.append(torch.full(((c + 31) // 32,), 0xFF, dtype=torch.uint8,
+                              device=DEV))
+    torch.cuda.synchronize()
+    req = pc.Request(counts, pc.MXFP8_E4M3, pc.SUM, nparts, P, batched=True)
+    req.bind(qs, oq, ss, osb, stream=stream)
+    assert req.config().comp == 1
+    _run(req, len(counts) * nparts, 5, stream)
+    worst = 0.0
+    for b, c in enumerate(counts):
+        nb = (c + 31) // 32
+        blocks = _sample_idx(nb, 64, b, [0, nb - 1])
+        idx = np.concatenate([np.arange(k * 32, min(c, k * 32 + 32))
+                              for k in blocks])
+        qsam = _gather(qs[b], idx)
+        ssam = _gather(ss[b], blocks)
+        gq = oq[b].index_select(0, torch.from_numpy(idx).to(DEV)).cpu().numpy()
+        gs = osb[b].index_select(0, torch.from_numpy(blocks).to(DEV)).cpu() \
+            .numpy()
+        wq, ws, _ = orc.sum_mx_f32(qsam, ssam, comp=True)
+        assert np.array_equal(gq, wq), b
+        assert np.array_equal(gs, ws), b
+        y64 = orc.sum_mx_f64(qsam, ssam)
+        absum = np.abs(np.stack([orc.mx_dequant(q, s) for q, s in
+                                 zip(qsam, ssam)])).sum(axis=0)
+        X = np.repeat(2.0 ** (gs.astype(np.float64) - 127), 32)[:len(idx)]
+        e = np.abs(orc.mx_dequant(gq, gs) - y64) / np.maximum(absum,
+                                                              X * 2.0 ** -6)
+        worst = max(worst, float(e.max()))
+    say("errors " + json.dumps({"workload": "mx batched",
+                                "max_norm_err": worst}))
+    assert worst <= 6e-2
+    req.free()

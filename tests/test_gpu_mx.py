@@ -1,0 +1,179 @@
+"""MX blocks (OCP Microscaling, e4m3 elements, one E8M0 scale byte per 32
+elements) through the C ABI: producer packing, the identity over every
+finite code at extreme scales, sums (plain and Sum2) bitwise against the
+oracle's binary32 mirror and within 6e-2 of the FP64 reference, tile
+layouts, batched launches."""
+import numpy as np
+import pytest
+import torch
+
+from _gpu import DEV, new_request, run_epoch, say
+from oracle import get as get_oracle
+from paper_2604_22228_amd import pcoll as pc
+from paper_2604_22228_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def orc():
+    return get_oracle()
+
+
+@pytest.fixture(scope="module")
+def stream():
+    assert torch.cuda.is_available()
+    pc.load()
+    return torch.cuda.current_stream(DEV)
+
+
+def _pack(x_dev):
+    n = x_dev.numel()
+    q = torch.empty(max(n, 16), dtype=torch.uint8, device=DEV)
+    s = torch.empty(max((n + 31) // 32, 1), dtype=torch.uint8, device=DEV)
+    pc.pcoll_pack_mxfp8(x_dev, q, s, n, torch.cuda.current_stream(DEV))
+    return q, s
+
+
+def _extreme_values(n, seed):
+    """N(0, 1e-2) with blocks far out in both directions: binary32
+    subnormals, tiny normals, huge values, zeros, a lone nonzero."""
+    x = synth.normal_with_outliers_f32(1, n, seed, 1e-2)[0].numpy().copy()
+    x[0:32] *= np.float32(1e30)
+    x[32:64] *= np.float32(1e-36)
+    x[64:96] = np.float32(1e-40) * np.sign(x[64:96])
+    x[96:128] = 0.0
+    x[128:160] = 0.0
+    x[150] = np.float32(-3.0)
+    return x
+
+
+def test_pack_mx_matches_oracle(orc, stream):
+    n = 32 * 3000 + 13
+    x = _extreme_values(n, synth.seed_for(5))
+    q, s = _pack(torch.from_numpy(x).to(DEV))
+    oq, os_ = orc.mx_pack(x)
+    assert np.array_equal(q[:n].cpu().numpy(), oq)
+    assert np.array_equal(s[:len(os_)].cpu().numpy(), os_)
+
+
+@pytest.mark.parametrize("comp", [False, True])
+def test_mx_identity_covers_every_finite_code(orc, stream, comp):
+    """P = 1 over blocks holding all 254 finite e4m3 codes, at scale bytes
+    from 0 (2^-127: binary32 subnormal values) to 246 (the largest whose
+    block fits binary32: 448 * 2^119 < 2^128): the output decodes to the
+    input exactly."""
+    finite = np.array([c for c in range(256) if (c & 0x7F) != 0x7F],
+                      dtype=np.uint8)
+    nblk = 8 * 6
+    q = np.resize(finite, nblk * 32)
+    sb = np.resize(np.array([0, 1, 20, 100, 127, 128, 200, 246],
+                            dtype=np.uint8), nblk)
+    n = len(q)
+    oq = torch.full((n,), 0x7F, dtype=torch.uint8, device=DEV)
+    osb = torch.full((nblk,), 0xFF, dtype=torch.uint8, device=DEV)
+    req = new_request([n], pc.MXFP8_E4M3, pc.SUM, 3, 1, comp=int(comp))
+    req.bind([[torch.from_numpy(q).to(DEV)]], [oq],
+             rank_scales=[[torch.from_numpy(sb).to(DEV)]],
+             out_scales=[osb], stream=stream)
+    run_epoch(req, [2, 0, 1], stream)
+    gq, gs = oq.cpu().numpy(), osb.cpu().numpy()
+    req.free()
+    wq, ws, _ = orc.sum_mx_f32([q], [sb], comp=comp)
+    assert np.array_equal(gq, wq)
+    assert np.array_equal(gs, ws)
+    assert np.array_equal(orc.mx_dequant(gq, gs), orc.mx_dequant(q, sb))
+
+
+def _reduce(orc, stream, P, n, nparts, comp, seed, **cfg):
+    xs = [_extreme_values(n, seed + r) for r in range(P)]
+    packs = [_pack(torch.from_numpy(x).to(DEV)) for x in xs]
+    opacks = [orc.mx_pack(x) for x in xs]
+    for (gq, gs), (oq, os_) in zip(packs, opacks):
+        assert np.array_equal(gq[:n].cpu().numpy(), oq)
+        assert np.array_equal(gs[:len(os_)].cpu().numpy(), os_)
+    nb = (n + 31) // 32
+    out = torch.full((n,), 0x7F, dtype=torch.uint8, device=DEV)
+    osb = torch.full((nb,), 0xFF, dtype=torch.uint8, device=DEV)
+    req = new_request([n], pc.MXFP8_E4M3, pc.SUM, nparts, P, comp=int(comp),
+                      **cfg)
+    req.bind([[q for q, _ in packs]], [out],
+             rank_scales=[[s for _, s in packs]], out_scales=[osb],
+             stream=stream)
+    run_epoch(req, synth.permutation(nparts, seed), stream)
+    gq, gs = out.cpu().numpy(), osb.cpu().numpy()
+    req.free()
+    oq = [q for q, _ in opacks]
+    os_ = [s for _, s in opacks]
+    wq, ws, _ = orc.sum_mx_f32(oq, os_, comp=comp)
+    assert np.array_equal(gq, wq)
+    assert np.array_equal(gs, ws)
+    return gq, gs, oq, os_
+
+
+@pytest.mark.parametrize("comp", [True, False])
+def test_mx_reduce(orc, stream, comp):
+    P, n, nparts = 8, 32 * 7919 + 19, 32
+    say(f"case mx comp={comp} P={P} n={n}")
+    gq, gs, oq, os_ = _reduce(orc, stream, P, n, nparts, comp,
+                              synth.seed_for(5) + 11)
+    y64 = orc.sum_mx_f64(oq, os_)
+    absum = np.abs(np.stack([orc.mx_dequant(q, s)
+                             for q, s in zip(oq, os_)])).sum(axis=0)
+    X = np.repeat(2.0 ** (gs.astype(np.float64) - 127), 32)[:n]
+    e = np.abs(orc.mx_dequant(gq, gs) - y64) / np.maximum(absum,
+                                                          X * 2.0 ** -6)
+    say(f"mx max normalized error {e.max():.4g}")
+    assert e.max() <= 6e-2
+
+
+@pytest.mark.parametrize("band", [0, 1, 3])
+def test_mx_tile_layouts(orc, stream, band):
+    """Small tiles (many per partition), ragged rows and partitions, every
+    tile layout."""
+    say(f"case mx layout band={band}")
+    _reduce(orc, stream, 5, 32 * 1500 + 7, 7, True, 41 + band,
+            tile_elems=2048, interleave=band)
+
+
+@pytest.mark.parametrize("graph", [0, 1])
+def test_mx_batched(orc, stream, graph):
+    P, nparts = 4, 8
+    counts = [32 * 400 + 3, 100, 32 * 70, 5000, 0]
+    say(f"case mx batched graph={graph} counts={counts}")
+    qs, ss, oqs, oss, want = [], [], [], [], []
+    for b, c in enumerate(counts):
+        xs = synth.normal_f32(P, c, 950 + b, std=1e-2)
+        row = [_pack(x.to(DEV)) for x in xs]
+        qs.append([q for q, _ in row])
+        ss.append([s for _, s in row])
+        nb = (c + 31) // 32
+        oqs.append(torch.full((max(c, 16),), 0x7F, dtype=torch.uint8,
+                              device=DEV))
+        oss.append(torch.full((max(nb, 1),), 0xFF, dtype=torch.uint8,
+                              device=DEV))
+        op = [orc.mx_pack(x.numpy()) for x in xs]
+        want.append(orc.sum_mx_f32([q for q, _ in op], [s for _, s in op],
+                                   comp=True)[:2])
+    torch.cuda.synchronize()
+    req = new_request(counts, pc.MXFP8_E4M3, pc.SUM, nparts, P, graph=graph)
+    req.bind(qs, oqs, ss, oss, stream=stream)
+    for epoch in range(2):
+        run_epoch(req, synth.permutation(req.nparts_total, 7 + epoch),
+                  stream)
+        for b, c in enumerate(counts):
+            assert np.array_equal(oqs[b][:c].cpu().numpy(), want[b][0]), b
+            nb = (c + 31) // 32
+            assert np.array_equal(oss[b][:nb].cpu().numpy(), want[b][1]), b
+    req.free()
+
+
+def test_mx_rejects_max_and_bad_scales(stream):
+    with pytest.raises(pc.PcollError) as e:
+        pc.Request([64], pc.MXFP8_E4M3, pc.MAX, 1, 2)
+    assert e.value.code == pc.ERR_UNSUPPORTED
+    req = pc.Request([64], pc.MXFP8_E4M3, pc.SUM, 1, 2)
+    q = torch.zeros(64, dtype=torch.uint8, device=DEV)
+    with pytest.raises(pc.PcollError):
+        req.bind([[q, q]], [q], stream=stream)  # scales are required
+    req.free()
