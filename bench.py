@@ -71,6 +71,9 @@ def parse():
     ap.add_argument("--probe-copy", action="store_true",
                     help="only run the streaming-copy probe (counter "
                          "calibration) and exit")
+    ap.add_argument("--only-8bit", choices=sorted(EIGHT_BIT),
+                    help="only time the 8-bit workload in this format "
+                         "(for profiling) and exit")
     return ap.parse_args()
 
 
@@ -353,6 +356,54 @@ def graph_lifecycle(pc, torch, reps=20):
     return rows
 
 
+EIGHT_BIT = {"e4m3": ("FP8_E4M3", "pcoll_pack_fp8", 256, "fp8_batched_p8_1GiB"),
+             "e5m2": ("FP8_E5M2", "pcoll_pack_e5m2", 256,
+                      "e5m2_batched_p8_1GiB"),
+             "mxfp8": ("MXFP8_E4M3", "pcoll_pack_mxfp8", 32,
+                       "mxfp8_batched_p8_1GiB")}
+
+
+def eight_bit(pc, torch, synth, fmt, stream, warmup, reps):
+    """The 8-bit workload: 8 ranks, 128 buckets totalling 2^30 elements per
+    rank, N(0, 1e-2) with 1% outliers at 50x, packed to `fmt` (binary32
+    scales per 256 elements, or E8M0 bytes per 32 for MX blocks)."""
+    dev = torch.device("cuda:0")
+    cur = torch.cuda.current_stream(dev)
+    dname, pname, blk, key = EIGHT_BIT[fmt]
+    dtype, pack = getattr(pc, dname), getattr(pc, pname)
+    sdt, sbytes = (torch.uint8, 1) if blk == 32 else (torch.float32, 4)
+    counts = synth.fp8_bucket_counts()
+    n = sum(counts)
+    nbytes = 9 * n + 9 * sbytes * sum((c + blk - 1) // blk for c in counts)
+    order = ready_array(synth.permutation(len(counts) * 32, 5))
+    qs, ss = [], []
+    for b, c in enumerate(counts):
+        qrow, srow = [], []
+        for t in synth.normal_with_outliers_f32(
+                8, c, synth.seed_for(5) * 1000 + b, 1e-2, device=dev):
+            q = torch.empty(c, dtype=torch.uint8, device=dev)
+            s = torch.empty((c + blk - 1) // blk, dtype=sdt, device=dev)
+            pack(t, q, s, c, cur)
+            qrow.append(q)
+            srow.append(s)
+        qs.append(qrow)
+        ss.append(srow)
+    torch.cuda.synchronize()
+    ys = [torch.empty(c, dtype=torch.uint8, device=dev) for c in counts]
+    yss = [torch.empty((c + blk - 1) // blk, dtype=sdt, device=dev)
+           for c in counts]
+    req = pc.Request(counts, dtype, pc.SUM, 32, 8, batched=True)
+    req.bind(qs, ys, ss, yss, stream=stream)
+    h, d = time_requests(torch, [req], [order], stream, warmup, reps)
+    res = {"host_ms": round(h, 4), "kernel_ms": round(d, 4),
+           "GBps": round(nbytes / d / 1e6, 1), "comp": req.config().comp}
+    req.free()
+    del qs, ss, ys, yss
+    torch.cuda.empty_cache()
+    return key, res
+
+
+
 def extras(pc, torch, synth, warmup, reps):
     """The other workloads, timed (correctness and error are the tests'
     job: the full-size GPU tests check them against the oracle)."""
@@ -466,70 +517,11 @@ def extras(pc, torch, synth, warmup, reps):
     del xi, yi
     torch.cuda.empty_cache()
 
-    # workload 5: 8-bit floats (e4m3, and e5m2 on the same values), 8
-    # ranks, 128 buckets totalling 2^30 elements
-    counts5 = synth.fp8_bucket_counts()
-    n5 = sum(counts5)
-    b5 = 9 * n5 + 9 * 4 * sum((c + 255) // 256 for c in counts5)
-    o5 = ready_array(synth.permutation(len(counts5) * 32, 5))
-    for dtype, pack, key in ((pc.FP8_E4M3, pc.pcoll_pack_fp8,
-                              "fp8_batched_p8_1GiB"),
-                             (pc.FP8_E5M2, pc.pcoll_pack_e5m2,
-                              "e5m2_batched_p8_1GiB")):
-        q5, s5 = [], []
-        for b, c in enumerate(counts5):
-            qrow, srow = [], []
-            for t in synth.normal_with_outliers_f32(
-                    8, c, synth.seed_for(5) * 1000 + b, 1e-2, device=dev):
-                q = torch.empty(c, dtype=torch.uint8, device=dev)
-                s = torch.empty((c + 255) // 256, dtype=torch.float32,
-                                device=dev)
-                pack(t, q, s, c, cur)
-                qrow.append(q)
-                srow.append(s)
-            q5.append(qrow)
-            s5.append(srow)
-        torch.cuda.synchronize()
-        y5 = [torch.empty(c, dtype=torch.uint8, device=dev) for c in counts5]
-        ys5 = [torch.empty((c + 255) // 256, dtype=torch.float32,
-                           device=dev) for c in counts5]
-        r5 = pc.Request(counts5, dtype, pc.SUM, 32, 8, batched=True)
-        r5.bind(q5, y5, s5, ys5, stream=stream)
-        h, d = time_requests(torch, [r5], [o5], stream, warmup, reps)
-        out[key] = {"host_ms": round(h, 4), "kernel_ms": round(d, 4),
-                    "GBps": round(b5 / d / 1e6, 1),
-                    "comp": r5.config().comp}
-        r5.free()
-        del q5, s5, y5, ys5
-        torch.cuda.empty_cache()
-    # the same values as MX blocks (e4m3 codes, one E8M0 byte per 32)
-    bmx = 9 * n5 + 9 * sum((c + 31) // 32 for c in counts5)
-    q5, s5 = [], []
-    for b, c in enumerate(counts5):
-        qrow, srow = [], []
-        for t in synth.normal_with_outliers_f32(
-                8, c, synth.seed_for(5) * 1000 + b, 1e-2, device=dev):
-            q = torch.empty(c, dtype=torch.uint8, device=dev)
-            s = torch.empty((c + 31) // 32, dtype=torch.uint8, device=dev)
-            pc.pcoll_pack_mxfp8(t, q, s, c, cur)
-            qrow.append(q)
-            srow.append(s)
-        q5.append(qrow)
-        s5.append(srow)
-    torch.cuda.synchronize()
-    y5 = [torch.empty(c, dtype=torch.uint8, device=dev) for c in counts5]
-    ys5 = [torch.empty((c + 31) // 32, dtype=torch.uint8, device=dev)
-           for c in counts5]
-    r5 = pc.Request(counts5, pc.MXFP8_E4M3, pc.SUM, 32, 8, batched=True)
-    r5.bind(q5, y5, s5, ys5, stream=stream)
-    h, d = time_requests(torch, [r5], [o5], stream, warmup, reps)
-    out["mxfp8_batched_p8_1GiB"] = {"host_ms": round(h, 4),
-                                    "kernel_ms": round(d, 4),
-                                    "GBps": round(bmx / d / 1e6, 1),
-                                    "comp": r5.config().comp}
-    r5.free()
-    del q5, s5, y5, ys5
-    torch.cuda.empty_cache()
+    # workload 5: 8-bit floats (e4m3; e5m2 and MX blocks on the same
+    # values), 8 ranks, 128 buckets totalling 2^30 elements
+    for fmt in ("e4m3", "e5m2", "mxfp8"):
+        key, res = eight_bit(pc, torch, synth, fmt, stream, warmup, reps)
+        out[key] = res
     return out
 
 
@@ -551,6 +543,11 @@ def main():
     if args.probe_copy:
         print(json.dumps({"probe_copy": probe_copy(pc, torch, args.steps)}),
               flush=True)
+        return
+    if args.only_8bit:
+        key, res = eight_bit(pc, torch, synth, args.only_8bit,
+                             torch.cuda.Stream(dev), args.warmup, args.steps)
+        print(json.dumps({key: res}), flush=True)
         return
 
     P, n, nparts = args.ranks, 1 << args.log2n, args.nparts
