@@ -248,6 +248,21 @@ void orc_sum_bf16_f32(int P, int64_t n, const uint16_t *const *x, int comp,
   }
 }
 
+/* bf16 pair output of the same sum: hi = bf16(y32), lo = bf16(y32 - hi),
+ * y32 the binary32 sum above (left to right or Sum2).  The difference is
+ * exact in double (and in binary32: hi is y32 rounded to fewer bits in the
+ * same binade), so hi + lo carries y32 to 16 significant bits. */
+void orc_sum_bf16_hilo(int P, int64_t n, const uint16_t *const *x, int comp,
+                       uint16_t *hi, uint16_t *lo) {
+  float v[64];
+  for (int64_t i = 0; i < n; ++i) {
+    for (int r = 0; r < P; ++r) v[r] = (float)orc_bf16_decode(x[r][i]);
+    float acc = acc_f32(P, v, comp);
+    hi[i] = orc_bf16_encode((double)acc);
+    lo[i] = orc_bf16_encode((double)acc - orc_bf16_decode(hi[i]));
+  }
+}
+
 void orc_max_bf16(int P, int64_t n, const uint16_t *const *x, uint16_t *y) {
   for (int64_t i = 0; i < n; ++i) {
     double m = orc_bf16_decode(x[0][i]);

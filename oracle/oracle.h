@@ -32,6 +32,8 @@ uint16_t orc_bf16_encode(double v);
 void orc_sum_bf16_f64(int P, int64_t n, const uint16_t *const *x, double *y);
 void orc_sum_bf16_f32(int P, int64_t n, const uint16_t *const *x, int comp,
                       uint16_t *y, float *y32);
+void orc_sum_bf16_hilo(int P, int64_t n, const uint16_t *const *x, int comp,
+                       uint16_t *hi, uint16_t *lo);
 void orc_max_bf16(int P, int64_t n, const uint16_t *const *x, uint16_t *y);
 
 double orc_e4m3_decode(uint8_t q);

@@ -36,6 +36,7 @@ def _load(path=None):
         "orc_bf16_encode": (C.c_uint16, [C.c_double]),
         "orc_sum_bf16_f64": (None, [i32, i64, p, p]),
         "orc_sum_bf16_f32": (None, [i32, i64, p, i32, p, p]),
+        "orc_sum_bf16_hilo": (None, [i32, i64, p, i32, p, p]),
         "orc_max_bf16": (None, [i32, i64, p, p]),
         "orc_e4m3_decode": (C.c_double, [C.c_uint8]),
         "orc_e4m3_encode": (C.c_uint8, [C.c_double]),
@@ -157,6 +158,15 @@ class Oracle:
         self.lib.orc_sum_bf16_f32(len(arrs), n, tab, int(comp), self._ptr(y),
                                   self._ptr(y32))
         return y, y32
+
+    def sum_bf16_hilo(self, xs, comp=True):
+        """Returns (hi, lo) bf16 codes: hi = bf16(y32), lo = bf16(y32 - hi)."""
+        arrs, tab, n = self._ptrs(xs, np.uint16)
+        hi = np.empty(n, np.uint16)
+        lo = np.empty(n, np.uint16)
+        self.lib.orc_sum_bf16_hilo(len(arrs), n, tab, int(comp),
+                                   self._ptr(hi), self._ptr(lo))
+        return hi, lo
 
     def max_bf16(self, xs):
         arrs, tab, n = self._ptrs(xs, np.uint16)

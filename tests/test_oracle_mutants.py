@@ -82,6 +82,12 @@ MUTANTS = {
     "mx_mirror_drops_last_rank_scale": (
         "v[r] = (float)(orc_e4m3_decode(q[r][i]) * orc_e8m0_decode(sb[r][b]));",
         "v[r] = (float)(orc_e4m3_decode(q[r][i]) * orc_e8m0_decode(sb[0][b]));"),
+    "bf16_hilo_drops_low_part": (
+        "lo[i] = orc_bf16_encode((double)acc - orc_bf16_decode(hi[i]));",
+        "lo[i] = orc_bf16_encode(0.0);"),
+    "bf16_hilo_low_part_sign": (
+        "lo[i] = orc_bf16_encode((double)acc - orc_bf16_decode(hi[i]));",
+        "lo[i] = orc_bf16_encode(orc_bf16_decode(hi[i]) - (double)acc);"),
     "plan_floor_instead_of_ceil": (
         "int64_t psize = (count + nparts - 1) / nparts;",
         "int64_t psize = count / nparts + (count > 0);"),

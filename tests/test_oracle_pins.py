@@ -351,6 +351,76 @@ def test_bf16_sums(orc):
                               .numpy().view(np.uint16))
 
 
+def _bf16_codes(x64):
+    """bf16 codes of float64 values (torch's round-to-nearest-even cast)."""
+    return torch.from_numpy(np.asarray(x64, np.float64)).to(torch.bfloat16) \
+        .view(torch.int16).numpy().view(np.uint16)
+
+
+def _bf16_values(codes):
+    return (np.asarray(codes, np.uint16).astype(np.uint32) << 16) \
+        .view(np.float32).astype(np.float64)
+
+
+def test_bf16_hilo_exact_for_two_close_terms(orc):
+    """Two bf16 terms whose exponents differ by at most 7: their sum spans at
+    most 16 bits, binary32 adds it exactly, and the pair (hi, lo) holds it
+    exactly (exact rationals)."""
+    rng = np.random.default_rng(40)
+    n = 4000
+    e = rng.integers(-60, 60, n)
+    d = rng.integers(0, 8, n)
+    sa = rng.choice([-1.0, 1.0], n)
+    sb = rng.choice([-1.0, 1.0], n)
+    a = sa * (1 + rng.integers(0, 128, n) / 128) * 2.0 ** e
+    b = sb * (1 + rng.integers(0, 128, n) / 128) * 2.0 ** (e - d)
+    ca, cb = _bf16_codes(a), _bf16_codes(b)
+    assert np.array_equal(_bf16_values(ca), a)  # representable as given
+    for comp in (False, True):
+        hi, lo = orc.sum_bf16_hilo([ca, cb], comp=comp)
+        hv, lv = _bf16_values(hi), _bf16_values(lo)
+        for i in range(n):
+            assert Fraction(hv[i]) + Fraction(lv[i]) == \
+                Fraction(a[i]) + Fraction(b[i]), i
+
+
+def test_bf16_hilo_pair_of_the_binary32_sum(orc):
+    """hi is the bf16 output of the plain path, lo the nearest-even bf16 of
+    the exact remainder, and the pair is within 2^-9 of the remainder
+    (2^-17 relative) of the binary32 sum."""
+    rng = np.random.default_rng(41)
+    P, n = 8, 3000
+    xs = [_bf16_codes(rng.standard_normal(n) * 1e-3) for _ in range(P)]
+    for comp in (False, True):
+        hi, lo = orc.sum_bf16_hilo(xs, comp=comp)
+        yq, y32 = orc.sum_bf16_f32(xs, comp=comp)
+        assert np.array_equal(hi, yq)
+        rem = y32.astype(np.float64) - _bf16_values(hi)  # exact
+        assert np.array_equal(lo, _bf16_codes(rem))
+        for i in range(0, n, 7):
+            Y, H, L = (Fraction(float(y32[i])), Fraction(_bf16_values(hi)[i]),
+                       Fraction(_bf16_values(lo)[i]))
+            assert abs(H + L - Y) <= abs(Y - H) / 2 ** 8
+            assert abs(H + L - Y) <= abs(Y) / 2 ** 16
+
+
+def test_bf16_hilo_error_within_bound(orc):
+    """Workload-3 shaped inputs (N(0, 1e-3) in bf16, 8 ranks): the pair is
+    within 2^-16 + the binary32 sum's own error of the FP64 reference,
+    normalized by sum |x|."""
+    rng = np.random.default_rng(42)
+    P, n = 8, 20000
+    xs = [_bf16_codes(rng.standard_normal(n) * 1e-3) for _ in range(P)]
+    y64 = orc.sum_bf16_f64(xs)
+    absum = np.abs(np.stack([_bf16_values(x) for x in xs])).sum(axis=0)
+    for comp in (False, True):
+        hi, lo = orc.sum_bf16_hilo(xs, comp=comp)
+        pair = _bf16_values(hi) + _bf16_values(lo)
+        e = np.abs(pair - y64) / np.maximum(absum, 1e-38)
+        assert e.max() <= 2.0 ** -16 + (_gamma(P - 1) if not comp
+                                        else 3 * U32)
+
+
 def test_bf16_max(orc):
     rng = np.random.default_rng(14)
     xs32 = [rng.standard_normal(3000).astype(np.float32) for _ in range(6)]
