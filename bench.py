@@ -220,9 +220,11 @@ def rank_readiness(pc, torch, synth, reps=5):
     outside the library), ranks spread over two streams.  overlapped: the
     reduction starts first and each (rank, partition) is marked on the
     device right after its product, so the kernel reduces each partition
-    while later ones are produced; run with the default grid and with 64
-    workgroups (a persistent kernel that waits holds registers the
-    producers could use).  bulk: every product first, then start, ready
+    while later ones are produced; run with 4-wave workgroups (one wave per
+    SIMD: the products' matrix-core waves must start beside the resident
+    reduce kernel, and the tuned 8-wave groups of this size leave them no
+    room) on every compute unit and on 64 of them (a persistent kernel that
+    waits holds registers the producers could use).  bulk: every product first, then start, ready
     everything, wait.  Host ms from the first product to the return of wait
     (median); `identical`: every run gives the same output bits."""
     import statistics
@@ -273,7 +275,7 @@ def rank_readiness(pc, torch, synth, reps=5):
     for name, fn, groups in (("overlapped_ms", overlapped, 0),
                              ("overlapped_64_groups_ms", overlapped, 64),
                              ("bulk_ms", bulk, 0)):
-        req.set_config(groups=groups)
+        req.set_config(groups=groups, group_waves=4)
         ts = []
         for it in range(2 + reps):
             torch.cuda.synchronize()
@@ -291,6 +293,7 @@ def rank_readiness(pc, torch, synth, reps=5):
         res["overlapped_ms"], res["overlapped_64_groups_ms"]), 3)
     res["workload"] = ("8 ranks, FP32, 2^26 elements per rank, 8 partitions, "
                        "an 8.6 GFLOP FP32 product per rank and partition")
+    res["reduce_group_waves"] = 4
     return res
 
 
@@ -464,6 +467,17 @@ def extras(pc, torch, synth, warmup, reps):
                              "instantiate_ms": round(st.last_instantiate_ms,
                                                      3)})
         rb.free()
+    # (a') the same bf16 buckets with the compensated pair output (hi, lo)
+    ylo = [torch.empty(c, dtype=torch.int16, device=dev) for c in counts]
+    rp = pc.Request(counts, pc.BF16_PAIR, pc.SUM, nparts, P, batched=True)
+    rp.bind(bf, yb, out_scales=ylo, stream=stream)
+    h, d = time_requests(torch, [rp], [order], stream, warmup, reps)
+    res["batched_bf16_pair"] = {"host_ms": round(h, 4),
+                                "kernel_ms": round(d, 4),
+                                "GBps": round(n_el * (2 * P + 4) / d / 1e6, 1),
+                                "comp": rp.config().comp}
+    rp.free()
+    del ylo
     # (b) plain fp32: one request per bucket, no graph
     yf = [torch.empty(c, device=dev) for c in counts]
     reqs, orders = [], []

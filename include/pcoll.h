@@ -67,7 +67,7 @@ typedef enum {
                           accumulation, output re-quantized per 256 */
   PCOLL_FP8_E5M2 = 4,  /* OCP e5m2 codes (2 fraction bits, range 57344),
                           otherwise as PCOLL_FP8_E4M3 */
-  PCOLL_MXFP8_E4M3 = 5 /* OCP MX blocks (Microscaling Formats v1.0, MXFP8
+  PCOLL_MXFP8_E4M3 = 5, /* OCP MX blocks (Microscaling Formats v1.0, MXFP8
                           with e4m3 elements): e4m3 codes, one E8M0 scale
                           byte b per 32 elements (value = code * 2^(b-127),
                           exact in binary32); binary32 accumulation; output
@@ -75,6 +75,12 @@ typedef enum {
                           scale (>= 2^-127) under which no code exceeds 448.
                           Scale byte 0xFF (NaN) is not accepted as input:
                           such blocks give unspecified results. */
+  PCOLL_BF16_PAIR = 6  /* bf16 in; out: a pair of bf16 arrays, hi = bf16(y)
+                          and lo = bf16(y - hi) for the binary32 sum y (Sum2
+                          by default), so hi + lo carries y to 16
+                          significant bits (compensated bf16 output).  The
+                          lo arrays are passed as pcoll_bind's out_scales.
+                          Sum only. */
 } pcoll_dtype_t;
 
 typedef enum { PCOLL_SUM = 0, PCOLL_MAX = 1 } pcoll_op_t;
@@ -120,7 +126,9 @@ int pcoll_init_batch(int nbuckets, const size_t *counts, int dtype, int op,
  *              like rank_bufs / outs: for PCOLL_FP8_E4M3 / _E5M2 binary32
  *              scales (4-byte aligned), ceil(count / 256) per bucket; for
  *              PCOLL_MXFP8_E4M3 E8M0 bytes (any alignment), ceil(count /
- *              32) per bucket.
+ *              32) per bucket.  For PCOLL_BF16_PAIR rank_scales is NULL
+ *              and out_scales holds the nbuckets lo arrays (bf16, count
+ *              elements each, 16-byte aligned).
  * Not allowed while an epoch is active.  A binding seen before (same
  * pointers and stream) reuses its cached descriptor table and graph. */
 int pcoll_bind(pcoll_req_t req, const void *const *rank_bufs,
@@ -170,7 +178,16 @@ int pcoll_pready_list(pcoll_req_t req, int n, const int *parts);
  * queue waits for it.  Keep the streams that signal during an epoch fewer
  * than that limit.  A signal that cannot run leaves its partitions
  * unready: the kernel reaches its deadline and the epoch fails with
- * PCOLL_ERR_ABORTED; it does not hang. */
+ * PCOLL_ERR_ABORTED; it does not hang.
+ *
+ * Likewise the kernels that produce the data and precede the signal on
+ * its stream must find room on the compute units beside the resident
+ * reduce kernel, whose workgroups of `group_waves` waves (groups_per_cu of
+ * them per unit) stay until the epoch ends.  A producer wave that needs
+ * more registers or LDS than a unit has left cannot start, so readiness
+ * never comes; with matrix-core (MFMA) producers, which can take a SIMD's
+ * whole register file, leave SIMDs room with pcoll_set_config: fewer
+ * groups, or group_waves = 4 (one wave per SIMD). */
 int pcoll_pready_on_stream(pcoll_req_t req, const int *parts_dev, int n,
                            void *stream);
 

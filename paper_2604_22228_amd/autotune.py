@@ -32,19 +32,20 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 DTYPE_NAMES = {0: "i32", 1: "f32", 2: "bf16", 3: "e4m3", 4: "e5m2",
-               5: "mxfp8"}
+               5: "mxfp8", 6: "bf16pair"}
 OP_NAMES = {0: "sum", 1: "max"}
 
 TILES = (4096, 8192, 16384, 32768)
 GROUPS_PER_CU = (1, 2)
-INTERLEAVE = (1,)
+# tile layout: bands of one launch's worth of tiles, or of 4, 8, 16 tiles
+INTERLEAVE = (1, 4, 8, 16)
 WAVES = (4, 8)
 BATCH = (64,)
 # 8-bit payloads: the kernels are bound by instruction issue and hide
 # memory latency with more resident waves and longer tiles
 TILES_8BIT = (16384, 32768, 65536)
 GROUPS_PER_CU_8BIT = (2, 3)
-FALLBACK = "* * * * 0 63 8192 1 1 8 64"
+FALLBACK = "* * * * 0 63 8192 1 16 8 64"
 
 
 def grid_for(dtype):
@@ -65,6 +66,7 @@ def default_keys():
     keys.append((0, 0, 16, 0, [1 << 24], 256))      # int32 sum
     keys.append((0, 1, 16, 0, [1 << 24], 256))      # int32 max
     keys.append((2, 0, 8, 0, list(synth.batched_bf16_counts()), 32))
+    keys.append((6, 0, 8, 0, list(synth.batched_bf16_counts()), 32))
     keys.append((3, 0, 8, 0, list(synth.fp8_bucket_counts()), 32))
     keys.append((4, 0, 8, 0, list(synth.fp8_bucket_counts()), 32))
     keys.append((5, 0, 8, 0, list(synth.fp8_bucket_counts()), 32))
@@ -102,10 +104,13 @@ def time_config(pc, torch, synth, dtype, op, ranks, graph, counts, nparts,
 def make_buffers(pc, torch, synth, dtype, ranks, counts):
     dev = torch.device("cuda:0")
     tdt = {0: torch.int32, 1: torch.float32, 2: torch.int16,
-           3: torch.uint8, 4: torch.uint8, 5: torch.uint8}[dtype]
+           3: torch.uint8, 4: torch.uint8, 5: torch.uint8,
+           6: torch.int16}[dtype]
     ins, outs, rsc, osc = [], [], None, None
     if dtype in (3, 4, 5):
         rsc, osc = [], []
+    elif dtype == 6:  # the low halves of the bf16 pairs
+        osc = []
     pack8 = {3: pc.pcoll_pack_fp8, 4: pc.pcoll_pack_e5m2,
              5: pc.pcoll_pack_mxfp8}.get(dtype)
     # scale blocks: binary32 per 256 elements, or E8M0 bytes per 32
@@ -119,7 +124,7 @@ def make_buffers(pc, torch, synth, dtype, ranks, counts):
             x = synth.normal_f32(ranks, m, 10 + b, device=dev)
             if dtype == 1:
                 bucket = x
-            elif dtype == 2:
+            elif dtype in (2, 6):
                 bucket = []
                 for t in x:
                     o = torch.empty(m, dtype=torch.int16, device=dev)
@@ -139,6 +144,8 @@ def make_buffers(pc, torch, synth, dtype, ranks, counts):
                                        device=dev))
         ins.append(bucket)
         outs.append(torch.empty(m, dtype=tdt, device=dev))
+        if dtype == 6:
+            osc.append(torch.empty(m, dtype=tdt, device=dev))
     torch.cuda.synchronize()
     return ins, outs, rsc, osc, torch.cuda.Stream(dev)
 

@@ -29,6 +29,9 @@ hipError_t launch_reduce(const ReduceArgs& a, int dtype, int op, bool comp,
     case kMX:
       if (op != kSum) return hipErrorInvalidValue;
       return launch_reduce_mx(a, comp, nranks, groups, waves, s);
+    case kBF16Pair:
+      if (op != kSum) return hipErrorInvalidValue;
+      return launch_reduce_bf16_pair(a, comp, nranks, groups, waves, s);
     default:
       return hipErrorInvalidValue;
   }

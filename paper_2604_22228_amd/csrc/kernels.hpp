@@ -15,13 +15,14 @@ constexpr int kMaxWavesPerGroup = 8;
 
 // Dtype / op codes, equal to the public enums of pcoll.h.
 enum Dtype : int {
-  kI32 = 0, kF32 = 1, kBF16 = 2, kE4M3 = 3, kE5M2 = 4, kMX = 5
+  kI32 = 0, kF32 = 1, kBF16 = 2, kE4M3 = 3, kE5M2 = 4, kMX = 5,
+  kBF16Pair = 6
 };
 enum Op : int { kSum = 0, kMax = 1 };
 
 // Elements per 16-byte vector and alignment unit of partitions.
 inline int elem_bytes(int dtype) {
-  return dtype == kBF16 ? 2
+  return dtype == kBF16 || dtype == kBF16Pair ? 2
                         : (dtype == kE4M3 || dtype == kE5M2 || dtype == kMX
                                ? 1
                                : 4);

@@ -1,4 +1,5 @@
-// bfloat16 payloads, binary32 accumulation: sum (plain or Sum2) and max.
+// bfloat16 payloads, binary32 accumulation: sum (plain or Sum2) and max,
+// and the sum with a bf16 pair (hi, lo) output.
 #include "reduce_impl.hpp"
 
 namespace pcoll {
@@ -8,5 +9,12 @@ hipError_t launch_reduce_bf16(const ReduceArgs& a, int op, bool comp,
   if (op == kMax) return launch_ranks<VecTile<FMax, 2>>(a, nranks, groups, waves, s);
   if (comp) return launch_ranks<VecTile<FSum<true>, 2>>(a, nranks, groups, waves, s);
   return launch_ranks<VecTile<FSum<false>, 2>>(a, nranks, groups, waves, s);
+}
+
+hipError_t launch_reduce_bf16_pair(const ReduceArgs& a, bool comp, int nranks,
+                                   int groups, int waves, hipStream_t s) {
+  using namespace dev;
+  if (comp) return launch_ranks<VecTile<FSum<true>, 3>>(a, nranks, groups, waves, s);
+  return launch_ranks<VecTile<FSum<false>, 3>>(a, nranks, groups, waves, s);
 }
 }  // namespace pcoll

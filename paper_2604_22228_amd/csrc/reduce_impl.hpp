@@ -49,5 +49,7 @@ hipError_t launch_reduce_e5m2(const ReduceArgs&, bool comp, int nranks,
                               int groups, int waves, hipStream_t);
 hipError_t launch_reduce_mx(const ReduceArgs&, bool comp, int nranks,
                             int groups, int waves, hipStream_t);
+hipError_t launch_reduce_bf16_pair(const ReduceArgs&, bool comp, int nranks,
+                                   int groups, int waves, hipStream_t);
 
 }  // namespace pcoll

@@ -90,7 +90,7 @@ const std::vector<TuneRow>& tune_rows() {
   return rows;
 }
 
-bool valid_dtype(int d) { return d >= PCOLL_INT32 && d <= PCOLL_MXFP8_E4M3; }
+bool valid_dtype(int d) { return d >= PCOLL_INT32 && d <= PCOLL_BF16_PAIR; }
 // 8-bit floats: codes plus block scales (binary32 per 256 elements, or
 // E8M0 bytes per 32 for MX blocks)
 bool is_fp8(int d) {
@@ -300,7 +300,8 @@ pcoll_config_t default_config(const pcoll_req_s* r) {
   c.groups_per_cu = env_int("PCOLL_GROUPS_PER_CU", t.groups_per_cu);
   const bool float_sum = r->op == PCOLL_SUM && r->dtype != PCOLL_INT32;
   // compensated accumulation: on for e4m3 and for 16 ranks or more
-  int comp = float_sum && (is_fp8(r->dtype) || r->nranks >= 16);
+  int comp = float_sum && (is_fp8(r->dtype) || r->dtype == PCOLL_BF16_PAIR ||
+                           r->nranks >= 16);
   comp = env_int("PCOLL_COMP", comp);
   c.comp = float_sum && comp ? 1 : 0;
   c.timeout_ms = env_int("PCOLL_TIMEOUT_MS", 10000);
@@ -330,7 +331,8 @@ int create(const std::vector<uint64_t>& counts, int dtype, int op,
   if (!valid_dtype(dtype) || !valid_op(op)) return PCOLL_ERR_ARG;
   if (nparts < 1 || nranks < 1) return PCOLL_ERR_ARG;
   if (nranks > PCOLL_MAX_RANKS) return PCOLL_ERR_UNSUPPORTED;
-  if (is_fp8(dtype) && op == PCOLL_MAX) return PCOLL_ERR_UNSUPPORTED;
+  if ((is_fp8(dtype) || dtype == PCOLL_BF16_PAIR) && op == PCOLL_MAX)
+    return PCOLL_ERR_UNSUPPORTED;
   const uint64_t np_total = (uint64_t)nparts * counts.size();
   if (np_total > (1u << 24)) return PCOLL_ERR_UNSUPPORTED;
   for (uint64_t c : counts)
@@ -685,7 +687,9 @@ int pcoll_bind(pcoll_req_t r, const void* const* rank_bufs, void* const* outs,
   if (check_req(r)) return PCOLL_ERR_ARG;
   if (!rank_bufs || !outs) return PCOLL_ERR_ARG;
   const bool fp8 = is_fp8(r->dtype);
-  if (fp8 != (rank_scales != nullptr) || fp8 != (out_scales != nullptr))
+  // second outputs: scales of the 8-bit floats, low halves of bf16 pairs
+  const bool out2 = fp8 || r->dtype == PCOLL_BF16_PAIR;
+  if (fp8 != (rank_scales != nullptr) || out2 != (out_scales != nullptr))
     return PCOLL_ERR_ARG;
   const int nb = r->nbuckets, P = r->nranks;
   // null is allowed only for empty buckets (never dereferenced)
@@ -702,6 +706,9 @@ int pcoll_bind(pcoll_req_t r, const void* const* rank_bufs, void* const* outs,
       if (bad(rank_scales[i], i / P, sa)) return PCOLL_ERR_ARG;
     for (int b = 0; b < nb; ++b)
       if (bad(out_scales[b], b, sa)) return PCOLL_ERR_ARG;
+  } else if (out2) {
+    for (int b = 0; b < nb; ++b)
+      if (bad(out_scales[b], b, 16)) return PCOLL_ERR_ARG;
   }
   if (r->active) return PCOLL_ERR_STATE;
   try {
@@ -709,10 +716,10 @@ int pcoll_bind(pcoll_req_t r, const void* const* rank_bufs, void* const* outs,
     key.v.reserve((size_t)nb * (2 * P + 2) + 1);
     for (int i = 0; i < nb * P; ++i) key.v.push_back((uintptr_t)rank_bufs[i]);
     for (int b = 0; b < nb; ++b) key.v.push_back((uintptr_t)outs[b]);
-    if (fp8) {
+    if (fp8)
       for (int i = 0; i < nb * P; ++i) key.v.push_back((uintptr_t)rank_scales[i]);
+    if (out2)
       for (int b = 0; b < nb; ++b) key.v.push_back((uintptr_t)out_scales[b]);
-    }
     key.v.push_back((uintptr_t)stream);
     HIP_TRY(hipSetDevice(r->device));
     Binding* hit = r->cache->get(key);
@@ -729,7 +736,7 @@ int pcoll_bind(pcoll_req_t r, const void* const* rank_bufs, void* const* outs,
           d.in_scale[q] = fp8 ? rank_scales[b * P + q] : nullptr;
         }
         d.out = outs[b];
-        d.out_scale = fp8 ? out_scales[b] : nullptr;
+        d.out_scale = out2 ? out_scales[b] : nullptr;
         d.count = r->counts[(size_t)b];
       }
       Binding nb_{};

@@ -188,11 +188,60 @@ struct VecCombine<Acc, P, 2> {
   }
 };
 
+// bf16 pair output of a binary32 sum y: hi = bf16(y), lo = bf16(y - hi).
+// The difference is exact in binary32 (hi is y rounded to fewer bits in
+// the same binade), so hi + lo carries y to 16 significant bits.
+__device__ __forceinline__ uint32_t bf16_pair(float y, uint32_t& lo) {
+  const uint32_t hi = f_to_bf16(y);
+  lo = f_to_bf16(y - bf16_to_f(hi));
+  return hi;
+}
+
+// Kind 3: bf16 lanes in, the pair (hi, lo) out: run() returns the hi
+// vector and leaves the lo vector in `low`.
+template <class Acc, int P>
+struct VecCombine<Acc, P, 3> {
+  __device__ __forceinline__ static uint4 run(const uint4 (&x)[P],
+                                              uint4& low) {
+    uint32_t o[4], l[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      Acc a, b;
+      uint32_t w = Word32::get(x[0], j);
+      a.init(bf16_to_f(w & 0xffffu));
+      b.init(bf16_to_f(w >> 16));
+#pragma unroll
+      for (int r = 1; r < P; ++r) {
+        w = Word32::get(x[r], j);
+        a.add(bf16_to_f(w & 0xffffu));
+        b.add(bf16_to_f(w >> 16));
+      }
+      uint32_t la, lb;
+      const uint32_t ha = bf16_pair(a.get(), la);
+      const uint32_t hb = bf16_pair(b.get(), lb);
+      o[j] = ha | (hb << 16);
+      l[j] = la | (lb << 16);
+    }
+    low = make_uint4(l[0], l[1], l[2], l[3]);
+    return make_uint4(o[0], o[1], o[2], o[3]);
+  }
+};
+
 // Scalar path for the last (< 16 bytes) elements of a bucket.
 template <class Acc, int P, int Kind>
 __device__ __forceinline__ void combine_scalar(const char* const (&in)[P],
-                                               char* out, uint32_t i) {
-  if (Kind == 2) {
+                                               char* out, char* out2,
+                                               uint32_t i) {
+  if (Kind == 3) {
+    Acc a;
+    a.init(bf16_to_f(reinterpret_cast<const uint16_t*>(in[0])[i]));
+#pragma unroll
+    for (int r = 1; r < P; ++r)
+      a.add(bf16_to_f(reinterpret_cast<const uint16_t*>(in[r])[i]));
+    uint32_t lo;
+    reinterpret_cast<uint16_t*>(out)[i] = (uint16_t)bf16_pair(a.get(), lo);
+    reinterpret_cast<uint16_t*>(out2)[i] = (uint16_t)lo;
+  } else if (Kind == 2) {
     Acc a;
     a.init(bf16_to_f(reinterpret_cast<const uint16_t*>(in[0])[i]));
 #pragma unroll
@@ -272,7 +321,7 @@ __device__ __forceinline__ bool owns_row(uint32_t q, uint32_t lt, uint32_t nt,
 
 template <class Acc, int Kind>
 struct VecTile {
-  static constexpr int kElemBytes = Kind == 2 ? 2 : 4;
+  static constexpr int kElemBytes = Kind >= 2 ? 2 : 4;
   static constexpr int kPerVec = 16 / kElemBytes;
   static constexpr uint32_t kRowElems = 64 * kPerVec;
 
@@ -293,6 +342,20 @@ struct VecTile {
           static_cast<const char*>(bd->in[r]) + poff * kElemBytes);
     uint4* out = reinterpret_cast<uint4*>(static_cast<char*>(bd->out) +
                                           poff * kElemBytes);
+    // Kind 3: the low halves of the pairs go to the second output
+    uint4* out2 = Kind == 3 ? reinterpret_cast<uint4*>(
+                                  static_cast<char*>(bd->out_scale) +
+                                  poff * kElemBytes)
+                            : nullptr;
+    auto emit = [&](uint32_t v, const uint4(&xx)[P]) {
+      if constexpr (Kind == 3) {
+        uint4 low;
+        st_stream(out + v, VecCombine<Acc, P, 3>::run(xx, low));
+        st_stream(out2 + v, low);
+      } else {
+        st_stream(out + v, VecCombine<Acc, P, Kind>::run(xx));
+      }
+    };
     const uint32_t nv = (uint32_t)(plen / kPerVec);  // whole vectors
     const uint32_t full = nv / 64;                    // whole rows
     const uint32_t all = (uint32_t)((plen + kRowElems - 1) / kRowElems);
@@ -308,16 +371,14 @@ struct VecTile {
         for (int r = 0; r < P; ++r)
           x[u][r] = ld_stream(in[r] + rows.row(k + u * nwaves) * 64u + lane);
 #pragma unroll
-      for (int u = 0; u < U; ++u)
-        st_stream(out + rows.row(k + u * nwaves) * 64u + lane,
-                  VecCombine<Acc, P, Kind>::run(x[u]));
+      for (int u = 0; u < U; ++u) emit(rows.row(k + u * nwaves) * 64u + lane, x[u]);
     }
     for (; k < rows.limit; k += nwaves) {
       uint4 x[P];
       const uint32_t v = rows.row(k) * 64u + lane;
 #pragma unroll
       for (int r = 0; r < P; ++r) x[r] = ld_stream(in[r] + v);
-      st_stream(out + v, VecCombine<Acc, P, Kind>::run(x));
+      emit(v, x);
     }
     // the partition's ragged end: a partial row and the last < 16 bytes,
     // done by the tile that owns row `full`
@@ -328,7 +389,7 @@ struct VecTile {
       uint4 x[P];
 #pragma unroll
       for (int r = 0; r < P; ++r) x[r] = ld_stream(in[r] + v);
-      st_stream(out + v, VecCombine<Acc, P, Kind>::run(x));
+      emit(v, x);
     }
     const uint32_t tail = (uint32_t)(plen - (uint64_t)nv * kPerVec);
     if (lane < tail) {
@@ -336,6 +397,7 @@ struct VecTile {
 #pragma unroll
       for (int r = 0; r < P; ++r) inb[r] = reinterpret_cast<const char*>(in[r]);
       combine_scalar<Acc, P, Kind>(inb, reinterpret_cast<char*>(out),
+                                   reinterpret_cast<char*>(out2),
                                    nv * kPerVec + lane);
     }
   }

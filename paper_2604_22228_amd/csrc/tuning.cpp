@@ -15,6 +15,7 @@ int parse_dtype(const std::string& s) {
   if (s == "e4m3") return 3;
   if (s == "e5m2") return 4;
   if (s == "mxfp8") return 5;
+  if (s == "bf16pair") return 6;
   return -2;
 }
 

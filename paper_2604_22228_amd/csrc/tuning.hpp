@@ -8,7 +8,8 @@
 //   # dtype op ranks graph log2_lo log2_hi tile groups_per_cu interleave waves batch
 //   f32     sum 8   0     24      28      4096   1             1          4     16
 //
-// dtype in {i32, f32, bf16, e4m3, e5m2, mxfp8, *}, op in {sum, max, *}, ranks a number
+// dtype in {i32, f32, bf16, e4m3, e5m2, mxfp8,
+// bf16pair, *}, op in {sum, max, *}, ranks a number
 // or *, graph 0 / 1 / *, and [log2_lo, log2_hi] the range of
 // floor(log2(bytes per rank of the whole request)); the trailing interleave
 // (tile layout, default 0; 1 = bands of the launch's workgroups, n >= 2 =

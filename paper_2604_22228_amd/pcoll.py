@@ -17,6 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpcoll.so")
 
 INT32, FLOAT32, BFLOAT16, FP8_E4M3, FP8_E5M2, MXFP8_E4M3 = 0, 1, 2, 3, 4, 5
+BF16_PAIR = 6  # bf16 in, (hi, lo) bf16 pair out
 SUM, MAX = 0, 1
 
 SUCCESS = 0
@@ -25,7 +26,7 @@ ERR_TIMEOUT, ERR_NOMEM, ERR_ABORTED = -5, -6, -7
 MAX_RANKS = 16
 
 ELEM_BYTES = {INT32: 4, FLOAT32: 4, BFLOAT16: 2, FP8_E4M3: 1, FP8_E5M2: 1,
-              MXFP8_E4M3: 1}
+              MXFP8_E4M3: 1, BF16_PAIR: 2}
 
 
 class PcollError(RuntimeError):

@@ -63,7 +63,8 @@ def test_version_and_strerror():
                                          (pc.BFLOAT16, 8),
                                          (pc.FP8_E4M3, 256),
                                          (pc.FP8_E5M2, 256),
-                                         (pc.MXFP8_E4M3, 32)])
+                                         (pc.MXFP8_E4M3, 32),
+                                         (pc.BF16_PAIR, 8)])
 def test_plan_matches_oracle(dtype, align):
     orc = get_oracle()
     for count in list(range(0, 70)) + [255, 256, 1000, 262144, 262144 + 37,
@@ -92,7 +93,8 @@ def test_plan_rejects_bad_arguments():
     ((100, pc.FP8_E4M3, pc.MAX, 4, 4), pc.ERR_UNSUPPORTED),
     ((100, pc.FP8_E5M2, pc.MAX, 4, 4), pc.ERR_UNSUPPORTED),
     ((100, pc.MXFP8_E4M3, pc.MAX, 4, 4), pc.ERR_UNSUPPORTED),
-    ((100, 6, pc.SUM, 4, 4), pc.ERR_ARG),           # no dtype 6
+    ((100, pc.BF16_PAIR, pc.MAX, 4, 4), pc.ERR_UNSUPPORTED),
+    ((100, 7, pc.SUM, 4, 4), pc.ERR_ARG),           # no dtype 7
     # a partition beyond 2^31 elements (the kernels' 32-bit row indices)
     ((1 << 33, pc.FLOAT32, pc.SUM, 1, 4), pc.ERR_UNSUPPORTED),
     ((1 << 41, pc.INT32, pc.SUM, 4096, 4), pc.ERR_UNSUPPORTED),
