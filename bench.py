@@ -114,8 +114,15 @@ def cpu_baseline(orc, xs_dev, P, seconds):
         if el >= seconds:
             break
     algo = (P * m * 4 + m * 4) * reps
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f
+                          if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": round(algo / el / 1e9, 3), "unit": "GB/s",
-            "cores": orc.omp_threads(), "kind": "oracle",
+            "cores": orc.omp_threads(), "cpu_model": model, "kind": "oracle",
             "sample": f"first 2^24 elements of each of the {P} ranks, FP64 "
                       f"rank-order sum over host cores, {reps} repetitions "
                       f"in {el:.1f} s"}
@@ -634,8 +641,11 @@ def main():
                         f"random order",
             "ranks": P, "elements_per_rank": n, "partitions": nparts,
             "tile_elems": cfg.tile_elems, "groups": st.groups,
-            "group_waves": cfg.group_waves,
+            "group_waves": cfg.group_waves, "interleave": cfg.interleave,
             "pct_hbm_peak": round(100 * value / HBM_PEAK_GBPS, 2),
+            # OMB-style per-rank message rate: one rank's bytes / time
+            "per_rank_message_GBps": round(n * 4 / (ms_per_step * 1e-3) / 1e9,
+                                           2),
             "time_to_reduce_ms": ttr,
             "cache": "cold by construction: 2.4 GB per step, 9x the "
                      "256 MB MALL",
@@ -659,6 +669,8 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_extras:
         line["extras"] = extras(pc, torch, synth, 2, 5)
+        copy = line["extras"]["copy_probe"]["GBps"]
+        line["config"]["pct_of_copy_probe"] = round(100 * value / copy, 2)
     print(json.dumps(line), flush=True)
 
 

@@ -127,6 +127,13 @@ def test_mx_reduce(orc, stream, comp):
     assert e.max() <= 6e-2
 
 
+@pytest.mark.parametrize("P", [1, 2, 5, 16])
+def test_mx_rank_counts(orc, stream, P):
+    """MX sums (Sum2) at other rank counts than the workload's 8."""
+    say(f"case mx P={P}")
+    _reduce(orc, stream, P, 32 * 3001 + 29, 9, True, 70 + P)
+
+
 @pytest.mark.parametrize("band", [0, 1, 3])
 def test_mx_tile_layouts(orc, stream, band):
     """Small tiles (many per partition), ragged rows and partitions, every

@@ -301,8 +301,8 @@ def test_fp8_identity_covers_every_code(orc, stream, comp):
 
 
 @pytest.mark.parametrize("comp", [True, False])
-def test_fp8_reduce(orc, stream, comp, layout=None):
-    P, n, nparts = 8, 256 * 997 + 131, 32
+def test_fp8_reduce(orc, stream, comp, layout=None, P=8):
+    n, nparts = 256 * 997 + 131, 32
     say(f"case fp8 comp={comp} P={P} n={n} layout={layout}")
     xs = synth.normal_with_outliers_f32(P, n, synth.seed_for(5), 1e-2)
     packs = [pack_fp8_gpu(x.to(DEV)) for x in xs]
@@ -341,6 +341,12 @@ def test_fp8_reduce(orc, stream, comp, layout=None):
 def test_fp8_tile_layouts(orc, stream, band):
     """e4m3 with one-row tiles (8 per partition) in each tile layout."""
     test_fp8_reduce(orc, stream, True, layout=band)
+
+
+@pytest.mark.parametrize("P", [1, 2, 5, 16])
+def test_fp8_rank_counts(orc, stream, P):
+    """e4m3 sums (Sum2) at other rank counts than the workload's 8."""
+    test_fp8_reduce(orc, stream, True, P=P)
 
 
 # ------------------------------------------------------- batched and graphs
