@@ -51,7 +51,8 @@ struct QEntry {
 };
 
 // Host-coherent pinned memory shared with the host thread.  Followed in the
-// same allocation by hlist[nparts] and arrived[nparts] (uint32 each).
+// same allocation by the ready list hlist[nparts] (uint64 tagged entries)
+// and the arrived stamps arrived[nparts] (uint32).
 struct HostShared {
   uint32_t epoch;         // host: stamp of the next / running epoch, stored
                           // before the launch

@@ -358,9 +358,12 @@ def pcoll_last_error_detail():
 class Request:
     """A persistent partitioned-reduction request bound to torch tensors.
 
-    buckets: list of per-bucket lists of P rank tensors (one bucket for the
-    plain form); outs: one output tensor per bucket; for the 8-bit dtypes also the
-    per-256 scale tensors.  The tensors are kept referenced while bound."""
+    bind(): rank_bufs, a list of per-bucket lists of P rank tensors (one
+    bucket for the plain form); outs, one output tensor per bucket; for the
+    8-bit dtypes also rank_scales (per bucket, per rank) and out_scales (per
+    bucket): binary32 per 256 elements, or E8M0 bytes per 32 for MX blocks;
+    for BF16_PAIR out_scales holds the lo output of each bucket.  The
+    tensors are kept referenced while bound."""
 
     def __init__(self, counts, dtype, op, nparts, nranks, batched=None):
         self.counts = list(counts)
