@@ -31,3 +31,14 @@ def test_autotune_table_round_trip(tmp_path):
     assert out.read_text() == open(src).read()
     assert autotune.grid_for(3)[0] == autotune.TILES_8BIT
     assert autotune.grid_for(1)[0] == autotune.TILES
+
+
+def test_shipped_table_covers_every_tuned_workload():
+    """Every (dtype, op, ranks) the autotuner tunes has a row of its own in
+    the shipped table, so no workload falls back to the catch-all row."""
+    from paper_2604_22228_amd import autotune
+    src = os.path.join(ROOT, "paper_2604_22228_amd", "tuned_mi355x.txt")
+    have = {(r[0], r[1], r[2]) for r in autotune.read_table(src)}
+    for dtype, op, ranks, _graph, _counts, _nparts in autotune.default_keys():
+        key = (autotune.DTYPE_NAMES[dtype], autotune.OP_NAMES[op], ranks)
+        assert key in have, key
