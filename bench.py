@@ -103,7 +103,9 @@ def probe_copy(pc, torch, steps):
 def cpu_baseline(orc, xs_dev, P, seconds):
     """The oracle (FP64 rank-order sum, element-parallel over the host
     cores) on a bounded sample: the first 2^24 elements (64 MiB) of every
-    rank, repeated until about `seconds` of CPU work."""
+    rank, repeated until about `seconds` of CPU work; beside it the
+    single-threaded fixed-order oracle on the first 2^22 elements for a
+    quarter of that time (`single_thread_value`, same unit)."""
     m = 1 << 24
     sample = [x[:m].cpu().numpy() for x in xs_dev]
     reps, t0 = 0, time.perf_counter()
@@ -114,6 +116,16 @@ def cpu_baseline(orc, xs_dev, P, seconds):
         if el >= seconds:
             break
     algo = (P * m * 4 + m * 4) * reps
+    # the single-threaded fixed-order oracle on a quarter of the sample
+    q = [x[:m // 4] for x in sample]
+    reps1, t1 = 0, time.perf_counter()
+    while True:
+        orc.sum_f32_f64(q, threads=False)
+        reps1 += 1
+        el1 = time.perf_counter() - t1
+        if el1 >= seconds / 4:
+            break
+    single = (P * m + m) * reps1 / el1 / 1e9  # (P + 1) * 4 * m / 4 bytes
     model = ""
     try:
         with open("/proc/cpuinfo") as f:
@@ -123,9 +135,11 @@ def cpu_baseline(orc, xs_dev, P, seconds):
         pass
     return {"value": round(algo / el / 1e9, 3), "unit": "GB/s",
             "cores": orc.omp_threads(), "cpu_model": model, "kind": "oracle",
+            "single_thread_value": round(single, 3),
             "sample": f"first 2^24 elements of each of the {P} ranks, FP64 "
                       f"rank-order sum over host cores, {reps} repetitions "
-                      f"in {el:.1f} s"}
+                      f"in {el:.1f} s; single thread: the first 2^22 "
+                      f"elements, {reps1} repetitions in {el1:.1f} s"}
 
 
 def ready_array(order):
