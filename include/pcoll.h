@@ -130,7 +130,9 @@ int pcoll_init_batch(int nbuckets, const size_t *counts, int dtype, int op,
  *              and out_scales holds the nbuckets lo arrays (bf16, count
  *              elements each, 16-byte aligned).
  * Not allowed while an epoch is active.  A binding seen before (same
- * pointers and stream) reuses its cached descriptor table and graph. */
+ * pointers and stream) reuses its cached descriptor table and graph; each
+ * request keeps the PCOLL_GRAPH_CACHE (environment, default 8) most
+ * recently used bindings and frees the least recently used beyond that. */
 int pcoll_bind(pcoll_req_t req, const void *const *rank_bufs,
                void *const *outs, const void *const *rank_scales,
                void *const *out_scales, void *stream);
