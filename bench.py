@@ -245,7 +245,8 @@ def rank_readiness(pc, torch, synth, reps=5):
     SIMD: the products' matrix-core waves must start beside the resident
     reduce kernel, and the tuned 8-wave groups of this size leave them no
     room) on every compute unit and on 64 of them (a persistent kernel that
-    waits holds registers the producers could use).  bulk: every product first, then start, ready
+    waits holds registers the producers could use).  bulk: every product
+    first, then start, ready
     everything, wait.  Host ms from the first product to the return of wait
     (median); `identical`: every run gives the same output bits."""
     import statistics
@@ -380,7 +381,8 @@ def graph_lifecycle(pc, torch, reps=20):
     return rows
 
 
-EIGHT_BIT = {"e4m3": ("FP8_E4M3", "pcoll_pack_fp8", 256, "fp8_batched_p8_1GiB"),
+EIGHT_BIT = {"e4m3": ("FP8_E4M3", "pcoll_pack_fp8", 256,
+                      "fp8_batched_p8_1GiB"),
              "e5m2": ("FP8_E5M2", "pcoll_pack_e5m2", 256,
                       "e5m2_batched_p8_1GiB"),
              "mxfp8": ("MXFP8_E4M3", "pcoll_pack_mxfp8", 32,
@@ -430,133 +432,162 @@ def eight_bit(pc, torch, synth, fmt, stream, warmup, reps):
 
 def extras(pc, torch, synth, warmup, reps):
     """The other workloads, timed (correctness and error are the tests'
-    job: the full-size GPU tests check them against the oracle)."""
+    job: the full-size GPU tests check them against the oracle).  A
+    workload that fails leaves {"error": ...} in its place, so that the
+    line is still printed."""
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream(dev)
     cur = torch.cuda.current_stream(dev)
-    out = {"copy_probe": probe_copy(pc, torch, 10)}
-    out["size_sweep"] = size_sweep(pc, torch, synth, stream)
-    out["rank_readiness"] = rank_readiness(pc, torch, synth)
-    out["graph_lifecycle"] = graph_lifecycle(pc, torch)
+    out = {}
 
-    # workload 1: 4 ranks, FP32, 262144 elements, 8 partitions in order
-    xs = synth.uniform_f32(4, 262144, synth.seed_for(1), device=dev)
-    y = torch.empty(262144, device=dev)
-    req = pc.Request([262144], pc.FLOAT32, pc.SUM, 8, 4)
-    req.bind([xs], [y], stream=stream)
-    h, d = time_requests(torch, [req], [list(range(8))], stream, warmup,
-                         max(reps, 50))
-    out["plain_fp32_p4_1MiB"] = {"host_us": round(h * 1e3, 1),
-                                 "kernel_us": round(d * 1e3, 1),
-                                 "GBps": round(5 * 262144 * 4 / d / 1e6, 1)}
-    req.free()
-    del xs, y
+    def guard(key, fn):
+        try:
+            fn()
+        except Exception as e:  # noqa: BLE001 - reported, not hidden
+            out[key] = {"error": f"{type(e).__name__}: {e}"}
+            torch.cuda.synchronize()
+            torch.cuda.empty_cache()
 
-    # workload 3: 64 bf16 gradient buckets, batched graph vs separate fp32
-    counts = synth.batched_bf16_counts()
-    P, nparts = 8, 32
-    f32 = [synth.normal_f32(P, c, synth.seed_for(3) * 1000 + b, std=1e-3,
-                            device=dev) for b, c in enumerate(counts)]
-    bf = []
-    for bucket, c in zip(f32, counts):
-        row = []
-        for t in bucket:
-            o = torch.empty(c, dtype=torch.int16, device=dev)
-            pc.pcoll_pack_bf16(t, o, c, cur)
-            row.append(o)
-        bf.append(row)
-    torch.cuda.synchronize()
-    n_el = sum(counts)
-    res = {"buckets": len(counts), "elements_per_rank": n_el}
-    # (a) batched bf16, one persistent launch per epoch: direct (the
-    # default) and replayed from a captured graph
-    yb = [torch.empty(c, dtype=torch.int16, device=dev) for c in counts]
-    order = ready_array(synth.permutation(len(counts) * nparts, 3))
-    for graph, key in ((0, "batched_bf16"), (1, "batched_bf16_graph")):
-        rb = pc.Request(counts, pc.BFLOAT16, pc.SUM, nparts, P,
-                        batched=True)
-        rb.set_config(graph=graph)
-        rb.bind(bf, yb, stream=stream)
-        h, d = time_requests(torch, [rb], [order], stream, warmup, reps)
-        st = rb.stats()
-        res[key] = {"host_ms": round(h, 4), "kernel_ms": round(d, 4),
-                    "GBps": round(n_el * 2 * (P + 1) / d / 1e6, 1),
-                    "graph": rb.config().graph}
-        if graph:
-            res[key].update({"graph_captures": st.graph_captures,
-                             "capture_ms": round(st.last_capture_ms, 3),
-                             "instantiate_ms": round(st.last_instantiate_ms,
-                                                     3)})
-        rb.free()
-    # (a') the same bf16 buckets with the compensated pair output (hi, lo)
-    ylo = [torch.empty(c, dtype=torch.int16, device=dev) for c in counts]
-    rp = pc.Request(counts, pc.BF16_PAIR, pc.SUM, nparts, P, batched=True)
-    rp.bind(bf, yb, out_scales=ylo, stream=stream)
-    h, d = time_requests(torch, [rp], [order], stream, warmup, reps)
-    res["batched_bf16_pair"] = {"host_ms": round(h, 4),
-                                "kernel_ms": round(d, 4),
-                                "GBps": round(n_el * (2 * P + 4) / d / 1e6, 1),
-                                "comp": rp.config().comp}
-    rp.free()
-    del ylo
-    # (b) plain fp32: one request per bucket, no graph
-    yf = [torch.empty(c, device=dev) for c in counts]
-    reqs, orders = [], []
-    for b, c in enumerate(counts):
-        r = pc.Request([c], pc.FLOAT32, pc.SUM, nparts, P, batched=False)
-        r.set_config(graph=0)
-        r.bind([f32[b]], [yf[b]], stream=stream)
-        reqs.append(r)
-        orders.append(ready_array(synth.permutation(nparts, b)))
-    h, d = time_requests(torch, reqs, orders, stream, warmup, reps)
-    res["plain_fp32_separate"] = {
-        "host_ms": round(h, 4), "kernel_ms": round(d, 4),
-        "GBps": round(n_el * 4 * (P + 1) / d / 1e6, 1)}
-    # the bf16 result against the fp32 path's result (not the oracle)
-    num = den = 0.0
-    for b in range(len(counts)):
-        v = (yb[b].view(torch.bfloat16).float() - yf[b]).abs()
-        num = max(num, float(v.max()))
-        den = max(den, float(yf[b].abs().max()))
-    res["bf16_vs_fp32_path_max_abs_rel_to_max"] = num / den if den else 0.0
-    for r in reqs:
-        r.free()
-    # (c) batched fp32 (one launch): separates batching from precision
-    rf = pc.Request(counts, pc.FLOAT32, pc.SUM, nparts, P, batched=True)
-    rf.bind(f32, yf, stream=stream)
-    h, d = time_requests(torch, [rf], [order], stream, warmup, reps)
-    res["batched_fp32"] = {"host_ms": round(h, 4), "kernel_ms": round(d, 4),
-                           "GBps": round(n_el * 4 * (P + 1) / d / 1e6, 1)}
-    rf.free()
-    res["bf16_batched_speedup_vs_plain_fp32"] = round(
-        res["plain_fp32_separate"]["host_ms"] /
-        res["batched_bf16"]["host_ms"], 3)
-    out["batched_bf16_vs_plain_fp32"] = res
-    del f32, bf, yb, yf
-    torch.cuda.empty_cache()
+    def put(key, fn, *a):
+        def run():
+            out[key] = fn(*a)
+        guard(key, run)
 
-    # workload 4: int32, 16 ranks, 2^24 elements, 256 partitions
-    n4 = 1 << 24
-    xi = synth.uniform_i32(16, n4, synth.seed_for(4), -(1 << 20), 1 << 20,
-                           device=dev)
-    yi = torch.empty(n4, dtype=torch.int32, device=dev)
-    o4 = ready_array(synth.permutation(256, synth.seed_for(4)))
-    for op, name in ((pc.SUM, "int32_sum_p16_64MiB"),
-                     (pc.MAX, "int32_max_p16_64MiB")):
-        r = pc.Request([n4], pc.INT32, op, 256, 16)
-        r.bind([xi], [yi], stream=stream)
-        h, d = time_requests(torch, [r], [o4], stream, warmup, reps)
-        out[name] = {"host_ms": round(h, 4), "kernel_ms": round(d, 4),
-                     "GBps": round(17 * n4 * 4 / d / 1e6, 1)}
-        r.free()
-    del xi, yi
-    torch.cuda.empty_cache()
+    put("copy_probe", probe_copy, pc, torch, 10)
+    put("size_sweep", size_sweep, pc, torch, synth, stream)
+    put("rank_readiness", rank_readiness, pc, torch, synth)
+    put("graph_lifecycle", graph_lifecycle, pc, torch)
+
+    def w1():
+        # workload 1: 4 ranks, FP32, 262144 elements, 8 partitions in order
+        xs = synth.uniform_f32(4, 262144, synth.seed_for(1), device=dev)
+        y = torch.empty(262144, device=dev)
+        req = pc.Request([262144], pc.FLOAT32, pc.SUM, 8, 4)
+        req.bind([xs], [y], stream=stream)
+        h, d = time_requests(torch, [req], [list(range(8))], stream, warmup,
+                             max(reps, 50))
+        out["plain_fp32_p4_1MiB"] = {
+            "host_us": round(h * 1e3, 1), "kernel_us": round(d * 1e3, 1),
+            "GBps": round(5 * 262144 * 4 / d / 1e6, 1)}
+        req.free()
+        del xs, y
+
+    guard("plain_fp32_p4_1MiB", w1)
+
+    def w3():
+        # workload 3: 64 bf16 gradient buckets, batched graph vs separate fp32
+        counts = synth.batched_bf16_counts()
+        P, nparts = 8, 32
+        f32 = [synth.normal_f32(P, c, synth.seed_for(3) * 1000 + b, std=1e-3,
+                                device=dev) for b, c in enumerate(counts)]
+        bf = []
+        for bucket, c in zip(f32, counts):
+            row = []
+            for t in bucket:
+                o = torch.empty(c, dtype=torch.int16, device=dev)
+                pc.pcoll_pack_bf16(t, o, c, cur)
+                row.append(o)
+            bf.append(row)
+        torch.cuda.synchronize()
+        n_el = sum(counts)
+        res = {"buckets": len(counts), "elements_per_rank": n_el}
+        # (a) batched bf16, one persistent launch per epoch: direct (the
+        # default) and replayed from a captured graph
+        yb = [torch.empty(c, dtype=torch.int16, device=dev) for c in counts]
+        order = ready_array(synth.permutation(len(counts) * nparts, 3))
+        for graph, key in ((0, "batched_bf16"), (1, "batched_bf16_graph")):
+            rb = pc.Request(counts, pc.BFLOAT16, pc.SUM, nparts, P,
+                            batched=True)
+            rb.set_config(graph=graph)
+            rb.bind(bf, yb, stream=stream)
+            h, d = time_requests(torch, [rb], [order], stream, warmup, reps)
+            st = rb.stats()
+            res[key] = {"host_ms": round(h, 4), "kernel_ms": round(d, 4),
+                        "GBps": round(n_el * 2 * (P + 1) / d / 1e6, 1),
+                        "graph": rb.config().graph}
+            if graph:
+                res[key].update({
+                    "graph_captures": st.graph_captures,
+                    "capture_ms": round(st.last_capture_ms, 3),
+                    "instantiate_ms": round(st.last_instantiate_ms, 3)})
+            rb.free()
+        # (a') the same bf16 buckets with the compensated pair output (hi, lo)
+        ylo = [torch.empty(c, dtype=torch.int16, device=dev) for c in counts]
+        rp = pc.Request(counts, pc.BF16_PAIR, pc.SUM, nparts, P, batched=True)
+        rp.bind(bf, yb, out_scales=ylo, stream=stream)
+        h, d = time_requests(torch, [rp], [order], stream, warmup, reps)
+        res["batched_bf16_pair"] = {
+            "host_ms": round(h, 4), "kernel_ms": round(d, 4),
+            "GBps": round(n_el * (2 * P + 4) / d / 1e6, 1),
+            "comp": rp.config().comp}
+        rp.free()
+        del ylo
+        # (b) plain fp32: one request per bucket, no graph
+        yf = [torch.empty(c, device=dev) for c in counts]
+        reqs, orders = [], []
+        for b, c in enumerate(counts):
+            r = pc.Request([c], pc.FLOAT32, pc.SUM, nparts, P, batched=False)
+            r.set_config(graph=0)
+            r.bind([f32[b]], [yf[b]], stream=stream)
+            reqs.append(r)
+            orders.append(ready_array(synth.permutation(nparts, b)))
+        h, d = time_requests(torch, reqs, orders, stream, warmup, reps)
+        res["plain_fp32_separate"] = {
+            "host_ms": round(h, 4), "kernel_ms": round(d, 4),
+            "GBps": round(n_el * 4 * (P + 1) / d / 1e6, 1)}
+        # the bf16 result against the fp32 path's result (not the oracle)
+        num = den = 0.0
+        for b in range(len(counts)):
+            v = (yb[b].view(torch.bfloat16).float() - yf[b]).abs()
+            num = max(num, float(v.max()))
+            den = max(den, float(yf[b].abs().max()))
+        res["bf16_vs_fp32_path_max_abs_rel_to_max"] = num / den if den else 0.0
+        for r in reqs:
+            r.free()
+        # (c) batched fp32 (one launch): separates batching from precision
+        rf = pc.Request(counts, pc.FLOAT32, pc.SUM, nparts, P, batched=True)
+        rf.bind(f32, yf, stream=stream)
+        h, d = time_requests(torch, [rf], [order], stream, warmup, reps)
+        res["batched_fp32"] = {"host_ms": round(h, 4),
+                               "kernel_ms": round(d, 4),
+                               "GBps": round(n_el * 4 * (P + 1) / d / 1e6, 1)}
+        rf.free()
+        res["bf16_batched_speedup_vs_plain_fp32"] = round(
+            res["plain_fp32_separate"]["host_ms"] /
+            res["batched_bf16"]["host_ms"], 3)
+        out["batched_bf16_vs_plain_fp32"] = res
+        del f32, bf, yb, yf
+        torch.cuda.empty_cache()
+
+    guard("batched_bf16_vs_plain_fp32", w3)
+
+    def w4():
+        # workload 4: int32, 16 ranks, 2^24 elements, 256 partitions
+        n4 = 1 << 24
+        xi = synth.uniform_i32(16, n4, synth.seed_for(4), -(1 << 20), 1 << 20,
+                               device=dev)
+        yi = torch.empty(n4, dtype=torch.int32, device=dev)
+        o4 = ready_array(synth.permutation(256, synth.seed_for(4)))
+        for op, name in ((pc.SUM, "int32_sum_p16_64MiB"),
+                         (pc.MAX, "int32_max_p16_64MiB")):
+            r = pc.Request([n4], pc.INT32, op, 256, 16)
+            r.bind([xi], [yi], stream=stream)
+            h, d = time_requests(torch, [r], [o4], stream, warmup, reps)
+            out[name] = {"host_ms": round(h, 4), "kernel_ms": round(d, 4),
+                         "GBps": round(17 * n4 * 4 / d / 1e6, 1)}
+            r.free()
+        del xi, yi
+        torch.cuda.empty_cache()
+
+    guard("int32_sum_p16_64MiB", w4)
 
     # workload 5: 8-bit floats (e4m3; e5m2 and MX blocks on the same
     # values), 8 ranks, 128 buckets totalling 2^30 elements
     for fmt in ("e4m3", "e5m2", "mxfp8"):
-        key, res = eight_bit(pc, torch, synth, fmt, stream, warmup, reps)
-        out[key] = res
+        def w5(fmt=fmt):
+            key, res = eight_bit(pc, torch, synth, fmt, stream, warmup, reps)
+            out[key] = res
+        guard(EIGHT_BIT[fmt][3], w5)
     return out
 
 
