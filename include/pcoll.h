@@ -187,9 +187,10 @@ int pcoll_pready_list(pcoll_req_t req, int n, const int *parts);
  * reduce kernel, whose workgroups of `group_waves` waves (groups_per_cu of
  * them per unit) stay until the epoch ends.  A producer wave that needs
  * more registers or LDS than a unit has left cannot start, so readiness
- * never comes; with matrix-core (MFMA) producers, which can take a SIMD's
- * whole register file, leave SIMDs room with pcoll_set_config: fewer
- * groups, or group_waves = 4 (one wave per SIMD). */
+ * never comes.  With matrix-core (MFMA) producers, whose waves can take
+ * most of a SIMD's register file, leave room with pcoll_set_config:
+ * group_waves = 4 (one resident wave per SIMD) and unroll = 2 (about 115
+ * instead of 160-190 VGPRs per wave at 8 ranks), or fewer groups. */
 int pcoll_pready_on_stream(pcoll_req_t req, const int *parts_dev, int n,
                            void *stream);
 
@@ -295,6 +296,12 @@ typedef struct {
                         epoch gets tiles of about R / (f x workgroups) rows,
                         clamped to [min_tile_elems, tile_elems]; 0 = every
                         tile has tile_elems elements */
+  int unroll;        /* rows (64 lanes x 16 bytes) each lane keeps loading
+                        at once in the int32 / fp32 / bf16 kernels at 3..8
+                        ranks: 4 (the default) or 2, which takes about 40 %
+                        fewer registers per wave and leaves room for
+                        kernels that run beside the reduction (see
+                        pcoll_pready_on_stream) */
 } pcoll_config_t;
 
 /* Reads the request's configuration.  The defaults come from the tuned
@@ -302,7 +309,7 @@ typedef struct {
  * then from environment overrides: PCOLL_TILE, PCOLL_MIN_TILE, PCOLL_GROUPS,
  * PCOLL_GROUPS_PER_CU, PCOLL_COMP, PCOLL_GRAPH, PCOLL_TIMEOUT_MS,
  * PCOLL_DEBUG, PCOLL_INTERLEAVE, PCOLL_GUIDE, PCOLL_GROUP_WAVES,
- * PCOLL_PUBLISH_BATCH. */
+ * PCOLL_PUBLISH_BATCH, PCOLL_UNROLL. */
 int pcoll_get_config(pcoll_req_t req, pcoll_config_t *cfg);
 
 /* Replaces the configuration (not while an epoch is active).  Fields out of

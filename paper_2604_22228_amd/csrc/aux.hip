@@ -9,17 +9,18 @@
 namespace pcoll {
 
 hipError_t launch_reduce(const ReduceArgs& a, int dtype, int op, bool comp,
-                         int nranks, int groups, int waves, hipStream_t s) {
+                         bool deep, int nranks, int groups, int waves,
+                         hipStream_t s) {
   if (nranks < 1 || nranks > kMaxRanks || groups < 1 || waves < 1 ||
       waves > kMaxWavesPerGroup)
     return hipErrorInvalidValue;
   switch (dtype) {
     case kF32:
-      return launch_reduce_f32(a, op, comp, nranks, groups, waves, s);
+      return launch_reduce_f32(a, op, comp, deep, nranks, groups, waves, s);
     case kI32:
-      return launch_reduce_i32(a, op, nranks, groups, waves, s);
+      return launch_reduce_i32(a, op, deep, nranks, groups, waves, s);
     case kBF16:
-      return launch_reduce_bf16(a, op, comp, nranks, groups, waves, s);
+      return launch_reduce_bf16(a, op, comp, deep, nranks, groups, waves, s);
     case kE4M3:
       if (op != kSum) return hipErrorInvalidValue;
       return launch_reduce_e4m3(a, comp, nranks, groups, waves, s);
@@ -31,7 +32,8 @@ hipError_t launch_reduce(const ReduceArgs& a, int dtype, int op, bool comp,
       return launch_reduce_mx(a, comp, nranks, groups, waves, s);
     case kBF16Pair:
       if (op != kSum) return hipErrorInvalidValue;
-      return launch_reduce_bf16_pair(a, comp, nranks, groups, waves, s);
+      return launch_reduce_bf16_pair(a, comp, deep, nranks, groups, waves,
+                                     s);
     default:
       return hipErrorInvalidValue;
   }

@@ -29,10 +29,12 @@ inline int elem_bytes(int dtype) {
 }
 
 // The persistent partitioned-reduce kernel: `groups` workgroups of `waves`
-// wavefronts.  Returns hipErrorInvalidValue for an unsupported (dtype, op,
-// comp, nranks) combination.
+// wavefronts; deep: 4 rows per lane in flight in the 16-byte-vector
+// kernels at 3..8 ranks (else 2).  Returns hipErrorInvalidValue for an
+// unsupported (dtype, op, comp, nranks) combination.
 hipError_t launch_reduce(const ReduceArgs& a, int dtype, int op, bool comp,
-                         int nranks, int groups, int waves, hipStream_t s);
+                         bool deep, int nranks, int groups, int waves,
+                         hipStream_t s);
 // Device-side readiness: appends `a.n` partition ids to the device ready
 // ring.
 hipError_t launch_pready(const PreadyArgs& a, hipStream_t s);

@@ -37,11 +37,13 @@ hipError_t launch_ranks(const ReduceArgs& a, int nranks, int groups,
 }
 
 // Per-family launchers, defined in reduce_<family>.hip.
-hipError_t launch_reduce_f32(const ReduceArgs&, int op, bool comp, int nranks,
+// deep: the 16-byte-vector kernels keep 4 rows per lane in flight at 3..8
+// ranks (else 2).
+hipError_t launch_reduce_f32(const ReduceArgs&, int op, bool comp, bool deep,
+                             int nranks, int groups, int waves, hipStream_t);
+hipError_t launch_reduce_i32(const ReduceArgs&, int op, bool deep, int nranks,
                              int groups, int waves, hipStream_t);
-hipError_t launch_reduce_i32(const ReduceArgs&, int op, int nranks, int groups,
-                             int waves, hipStream_t);
-hipError_t launch_reduce_bf16(const ReduceArgs&, int op, bool comp,
+hipError_t launch_reduce_bf16(const ReduceArgs&, int op, bool comp, bool deep,
                               int nranks, int groups, int waves, hipStream_t);
 hipError_t launch_reduce_e4m3(const ReduceArgs&, bool comp, int nranks,
                               int groups, int waves, hipStream_t);
@@ -49,7 +51,8 @@ hipError_t launch_reduce_e5m2(const ReduceArgs&, bool comp, int nranks,
                               int groups, int waves, hipStream_t);
 hipError_t launch_reduce_mx(const ReduceArgs&, bool comp, int nranks,
                             int groups, int waves, hipStream_t);
-hipError_t launch_reduce_bf16_pair(const ReduceArgs&, bool comp, int nranks,
-                                   int groups, int waves, hipStream_t);
+hipError_t launch_reduce_bf16_pair(const ReduceArgs&, bool comp, bool deep,
+                                   int nranks, int groups, int waves,
+                                   hipStream_t);
 
 }  // namespace pcoll

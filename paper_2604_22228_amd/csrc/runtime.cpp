@@ -211,7 +211,8 @@ uint64_t launch_signature(const pcoll_req_s* r) {
                         (uint64_t)r->cfg.timeout_ms, r->total_rows,
                         (uint64_t)r->cfg.interleave, (uint64_t)r->cfg.guide,
                         (uint64_t)r->cfg.group_waves,
-                        (uint64_t)r->cfg.publish_batch};
+                        (uint64_t)r->cfg.publish_batch,
+                        (uint64_t)r->cfg.unroll};
   for (uint64_t x : v) {
     h ^= x;
     h *= 1099511628211ull;
@@ -237,6 +238,7 @@ int validate_config(const pcoll_req_s* r, const pcoll_config_t& c) {
   if (c.debug != 0 && c.debug != 1) return PCOLL_ERR_ARG;
   if (c.interleave < 0 || c.interleave > (1 << 20)) return PCOLL_ERR_ARG;
   if (c.guide < 0 || c.guide > 64) return PCOLL_ERR_ARG;
+  if (c.unroll != 2 && c.unroll != 4) return PCOLL_ERR_ARG;
   if (c.group_waves < 1 || c.group_waves > kMaxWavesPerGroup)
     return PCOLL_ERR_ARG;
   if (c.publish_batch < 1 || c.publish_batch > kMaxPublishBatch)
@@ -294,6 +296,7 @@ pcoll_config_t default_config(const pcoll_req_s* r) {
   if (c.min_tile_elems > c.tile_elems) c.min_tile_elems = c.tile_elems;
   c.interleave = env_int("PCOLL_INTERLEAVE", t.interleave);
   c.guide = env_int("PCOLL_GUIDE", 0);
+  c.unroll = env_int("PCOLL_UNROLL", 4);
   c.group_waves = env_int("PCOLL_GROUP_WAVES", t.group_waves);
   c.publish_batch = env_int("PCOLL_PUBLISH_BATCH", t.publish_batch);
   c.groups = env_int("PCOLL_GROUPS", 0);
@@ -482,8 +485,9 @@ ReduceArgs make_args(const pcoll_req_s* r) {
 int launch_direct(pcoll_req_t r, hipStream_t s, uint32_t epoch) {
   ReduceArgs a = make_args(r);
   a.epoch = epoch;
-  HIP_TRY(launch_reduce(a, r->dtype, r->op, r->cfg.comp != 0, r->nranks,
-                        r->groups, r->cfg.group_waves, s));
+  HIP_TRY(launch_reduce(a, r->dtype, r->op, r->cfg.comp != 0,
+                        r->cfg.unroll != 2, r->nranks, r->groups,
+                        r->cfg.group_waves, s));
   return PCOLL_SUCCESS;
 }
 

@@ -265,10 +265,13 @@ __device__ __forceinline__ void combine_scalar(const char* const (&in)[P],
   }
 }
 
-// Unroll depth: enough loads in flight, bounded register use.
-template <int P>
+// Rows each lane loads at once: enough loads in flight, bounded register
+// use.  DEEP (the default) keeps 4 rows in flight up to 8 ranks; the
+// shallow form keeps 2 from 3 ranks on, which needs fewer registers and
+// leaves more room for kernels that run beside the reduction.
+template <int P, bool DEEP>
 struct Unroll {
-  static constexpr int value = P <= 2 ? 4 : (P <= 8 ? 2 : 1);
+  static constexpr int value = P <= 2 ? 4 : (P <= 8 ? (DEEP ? 4 : 2) : 1);
 };
 
 // Rows of a tile.  A partition is cut into rows of 64 lanes x 16 bytes
@@ -319,7 +322,7 @@ __device__ __forceinline__ bool owns_row(uint32_t q, uint32_t lt, uint32_t nt,
   return b * band + (uint32_t)(q - b * span) % nb == lt;
 }
 
-template <class Acc, int Kind>
+template <class Acc, int Kind, bool DEEP = true>
 struct VecTile {
   static constexpr int kElemBytes = Kind >= 2 ? 2 : 4;
   static constexpr int kPerVec = 16 / kElemBytes;
@@ -361,7 +364,7 @@ struct VecTile {
     const uint32_t all = (uint32_t)((plen + kRowElems - 1) / kRowElems);
     const uint32_t rpt = (all + nt - 1) / nt;
     const RowSet rows(lt, nt, rpt, inter, full);
-    constexpr int U = Unroll<P>::value;
+    constexpr int U = Unroll<P, DEEP>::value;
     uint32_t k = wave;
     for (; k + (U - 1) * nwaves < rows.limit; k += U * nwaves) {
       uint4 x[U][P];

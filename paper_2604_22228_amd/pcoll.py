@@ -42,7 +42,7 @@ class Config(C.Structure):
                 ("graph", C.c_int), ("timeout_ms", C.c_int),
                 ("debug", C.c_int), ("interleave", C.c_int),
                 ("group_waves", C.c_int), ("publish_batch", C.c_int),
-                ("guide", C.c_int)]
+                ("guide", C.c_int), ("unroll", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -632,3 +632,46 @@ def test_rebind_hits_cache(orc, stream):
     st = req.stats()
     assert st.cache_misses == 2 and st.cache_hits == 2
     req.free()
+
+
+@pytest.mark.parametrize("unroll", [2, 4])
+@pytest.mark.parametrize("dtype,P", [(pc.FLOAT32, 8), (pc.BFLOAT16, 5),
+                                     (pc.INT32, 3)])
+def test_unroll_depths(orc, stream, unroll, dtype, P):
+    """Both row depths of the 16-byte-vector kernels, bitwise, with ragged
+    partitions and several rows per wave."""
+    n, nparts = 65536 * 3 + 1031, 5
+    say(f"case unroll={unroll} dtype={dtype} P={P}")
+    if dtype == pc.INT32:
+        xs = synth.uniform_i32(P, n, 77, -(1 << 20), 1 << 20)
+        want = orc.sum_i32([x.numpy() for x in xs])
+        out = torch.empty(n, dtype=torch.int32, device=DEV)
+    elif dtype == pc.FLOAT32:
+        xs = synth.normal_f32(P, n, 78)
+        want = orc.sum_f32_f32([x.numpy() for x in xs], comp=False)
+        out = torch.empty(n, device=DEV)
+    else:
+        xs = [t.to(torch.bfloat16).view(torch.int16)
+              for t in synth.normal_f32(P, n, 79)]
+        want, _ = orc.sum_bf16_f32([x.numpy().view(np.uint16) for x in xs],
+                                   comp=False)
+        out = torch.empty(n, dtype=torch.int16, device=DEV)
+    req = new_request([n], dtype, pc.SUM, nparts, P, comp=0, unroll=unroll,
+                      tile_elems=16384, interleave=16)
+    assert req.config().unroll == unroll
+    req.bind([[x.to(DEV) for x in xs]], [out], stream=stream)
+    run_epoch(req, synth.permutation(nparts, unroll), stream)
+    got = out.cpu().numpy()
+    req.free()
+    assert np.array_equal(got.view(np.uint32 if got.itemsize == 4
+                                   else np.uint16),
+                          np.asarray(want).view(np.uint32 if got.itemsize == 4
+                                                else np.uint16))
+
+
+def test_unroll_rejects_other_depths(stream):
+    req = pc.Request([1024], pc.FLOAT32, pc.SUM, 1, 2)
+    with pytest.raises(pc.PcollError):
+        req.set_config(unroll=3)
+    assert req.config().unroll == 4
+    req.free()
