@@ -343,10 +343,11 @@ enum WaitResult { kBail, kStop, kReady };
 // Waits until tile t is queued (kReady, with the queue state in qs_out).
 // Before it first has to wait it calls publish_pending().
 // kStop: every partition is queued and t is beyond the last tile.  kBail:
-// give up (deadline, host abort, or another worker's error).  Only the few
+// give up (deadline, host abort, or another worker's error).  The few
 // workers at the front of the claim order (t within 8 tiles of the queued
 // total) poll the ready lists and the host's abort word; the rest re-read
-// the device-side queue state at a slower pace.
+// the device-side queue state at a slower pace, and after a long wait they
+// also poll the lists now and then (see below).
 template <class Publish>
 __device__ __forceinline__ WaitResult wait_queued(const ReduceArgs& a,
                                                   uint32_t t, uint32_t epoch,
@@ -370,11 +371,18 @@ __device__ __forceinline__ WaitResult wait_queued(const ReduceArgs& a,
     if ((uint32_t)(qs >> 32) >= a.nparts_total) return kStop;
     // about to wait: finished tiles must not sit behind the wait
     publish_pending();
-    const bool front = t - qt < 8u;
+    // The workers near the queue's end ingest.  So does, every 16th poll,
+    // any worker that has waited 64 polls: a launch can have more
+    // workgroups than fit on the device at once, and the tiles at the
+    // queue's end may belong to workgroups that start only when resident
+    // ones leave, so ingesting must not depend on them.
+    const bool near = t - qt < 8u;
+    const bool stuck = spins >= 64u;
+    const bool front = near || (stuck && (spins & 15u) == 0u);
     if (front && try_ingest(a, epoch, spins >= 16u)) continue;
     if (uni(ld_rlx(&a.ctr->error)) != 0u) return kBail;
     if ((spins & 7u) == 7u) {
-      if (front && uni(ld_rlx_sys(&a.host->abort)) == epoch) {
+      if ((near || stuck) && uni(ld_rlx_sys(&a.host->abort)) == epoch) {
         set_error(a, kStatusAborted, epoch);
         return kBail;
       }
@@ -383,7 +391,7 @@ __device__ __forceinline__ WaitResult wait_queued(const ReduceArgs& a,
         return kBail;
       }
     }
-    if (front)
+    if (near)
       __builtin_amdgcn_s_sleep(2);
     else
       __builtin_amdgcn_s_sleep(8);

@@ -675,3 +675,34 @@ def test_unroll_rejects_other_depths(stream):
         req.set_config(unroll=3)
     assert req.config().unroll == 4
     req.free()
+
+
+def test_more_workgroups_than_resident_with_slow_readiness(orc, stream):
+    """A launch with more workgroups than the device holds at once (bf16 at
+    8 ranks, 2 groups of 8 waves per compute unit) and readiness trickling
+    in, so that ingestion is partial: the tiles at the queue's end can
+    belong to workgroups that have not started, and the waiting resident
+    ones must ingest instead.  Bitwise against the oracle."""
+    import time
+    P, nparts = 8, 64
+    n = nparts * 16 * 1024  # 16 one-row-pair tiles per partition
+    say(f"case oversubscribed grid, slow readiness n={n}")
+    xs = [t.to(torch.bfloat16).view(torch.int16)
+          for t in synth.normal_f32(P, n, 81)]
+    want, _ = orc.sum_bf16_f32([x.numpy().view(np.uint16) for x in xs],
+                               comp=False)
+    out = torch.empty(n, dtype=torch.int16, device=DEV)
+    req = new_request([n], pc.BFLOAT16, pc.SUM, nparts, P, comp=0,
+                      tile_elems=1024, min_tile_elems=1024,
+                      groups_per_cu=2, group_waves=8, interleave=0)
+    req.bind([[x.to(DEV) for x in xs]], [out], stream=stream)
+    for epoch in range(2):
+        req.start()
+        for p in synth.permutation(nparts, 90 + epoch):
+            req.pready(int(p))
+            time.sleep(2e-4)
+        req.wait()
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy().view(np.uint16), want)
+    assert req.stats().groups > 256
+    req.free()
