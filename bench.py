@@ -297,7 +297,8 @@ def rank_readiness(pc, torch, synth, reps=5):
     for name, fn, groups in (("overlapped_ms", overlapped, 0),
                              ("overlapped_64_groups_ms", overlapped, 64),
                              ("bulk_ms", bulk, 0)):
-        req.set_config(groups=groups, group_waves=4, unroll=2)
+        req.set_config(groups=groups, groups_per_cu=1, group_waves=4,
+                       unroll=2)
         ts = []
         for it in range(2 + reps):
             torch.cuda.synchronize()
@@ -317,6 +318,7 @@ def rank_readiness(pc, torch, synth, reps=5):
                        "an 8.6 GFLOP FP32 product per rank and partition")
     res["reduce_group_waves"] = 4
     res["reduce_unroll"] = 2
+    res["reduce_groups_per_cu"] = 1
     return res
 
 

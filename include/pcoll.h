@@ -188,9 +188,11 @@ int pcoll_pready_list(pcoll_req_t req, int n, const int *parts);
  * them per unit) stay until the epoch ends.  A producer wave that needs
  * more registers or LDS than a unit has left cannot start, so readiness
  * never comes.  With matrix-core (MFMA) producers, whose waves can take
- * most of a SIMD's register file, leave room with pcoll_set_config:
- * group_waves = 4 (one resident wave per SIMD) and unroll = 2 (about 115
- * instead of 160-190 VGPRs per wave at 8 ranks), or fewer groups. */
+ * most of a SIMD's register file, leave room with pcoll_set_config: one
+ * resident wave per SIMD (groups_per_cu = 1 and group_waves = 4, or fewer
+ * groups) and unroll = 2 (about 115 instead of 160-190 VGPRs per wave at 8
+ * ranks).  The tuned defaults are chosen for host-readied requests and may
+ * put more waves on each unit. */
 int pcoll_pready_on_stream(pcoll_req_t req, const int *parts_dev, int n,
                            void *stream);
 
