@@ -1,2 +1,2 @@
 """CPU oracle for the partitioned reduction (test infrastructure only)."""
-from .oracle import Oracle, arrival_constraints, get  # noqa: F401
+from .oracle import Oracle, get  # noqa: F401

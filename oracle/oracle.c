@@ -12,7 +12,12 @@
  * its arithmetic; the definitions below are the plain mathematical ones:
  *
  *   - int32 sum: two's-complement wrap, computed in uint32 (no C overflow UB).
- *   - int32 / float max: the largest input (exact; the result is an input).
+ *   - int32 max: the largest input (exact; the result is an input).
+ *   - float max: the maximum operation of IEEE 754-2019 (clause 9.6): NaN if
+ *     any input is NaN, otherwise the largest input, with +0 counted larger
+ *     than -0.  It is commutative and associative, so the result does not
+ *     depend on rank order.  A NaN result of a bf16 output is encoded as the
+ *     quiet NaN 0x7FC0 (see orc_bf16_encode).
  *   - float sum, FP64 reference: every input decoded exactly to double, then
  *     summed left to right in rank order 0..P-1 in double.
  *   - float sum, FP32 mirror: the same left-to-right order in binary32
@@ -20,6 +25,11 @@
  *     2005, Algorithm 4.4) built on Knuth's TwoSum (TAOCP vol. 2, 4.2.2), in
  *     binary32 (compensated).  These fix the integer decisions of the encoded
  *     outputs (bf16 / e4m3 codes) in the precision the kernel takes them in.
+ *     Non-finite values follow IEEE arithmetic (an infinity absorbs finite
+ *     terms, opposite infinities give NaN, NaN propagates).  Sum2's
+ *     correction has no meaning once the running sum is not finite, so the
+ *     compensated sum then returns the running sum itself: plain and
+ *     compensated sums agree whenever the result is not finite.
  *
  * The partition plan follows the chunk rule of Algorithm 1 (Section 4.3):
  * every chunk is ceil(size / max_chunks) long, offsets are fixed in advance by
@@ -153,7 +163,8 @@ static float acc_f32(int P, const float *v, int comp) {
     two_sum_f32(p, v[r], &p, &q);
     sigma = sigma + q;
   }
-  return p + sigma;
+  /* a running sum that is not finite stays so; its errors are NaN */
+  return isfinite(p) ? p + sigma : p;
 }
 
 void orc_sum_f32_f32(int P, int64_t n, const float *const *x, int comp,
@@ -165,12 +176,19 @@ void orc_sum_f32_f32(int P, int64_t n, const float *const *x, int comp,
   }
 }
 
+/* maximum(a, b) of IEEE 754-2019 (clause 9.6): NaN if either operand is
+ * NaN; otherwise the larger, +0 being larger than -0. */
+static double maximum_ieee(double a, double b) {
+  if (isnan(a) || isnan(b)) return NAN;
+  if (a == b) return signbit(a) ? b : a; /* equal values: +0 over -0 */
+  return a > b ? a : b;
+}
+
 void orc_max_f32(int P, int64_t n, const float *const *x, float *y) {
   for (int64_t i = 0; i < n; ++i) {
-    float m = x[0][i];
-    for (int r = 1; r < P; ++r)
-      if (x[r][i] > m) m = x[r][i];
-    y[i] = m;
+    double m = (double)x[0][i];
+    for (int r = 1; r < P; ++r) m = maximum_ieee(m, (double)x[r][i]);
+    y[i] = (float)m; /* exact: m is one of the inputs, or NaN */
   }
 }
 
@@ -202,6 +220,7 @@ static double round_to_quantum_rne(double a, double quantum) {
 }
 
 uint16_t orc_bf16_encode(double v) {
+  /* every NaN becomes the quiet NaN with sign 0 and an empty payload */
   if (isnan(v)) return 0x7fc0;
   int s = signbit(v) ? 1 : 0;
   double a = fabs(v);
@@ -248,8 +267,9 @@ void orc_sum_bf16_f32(int P, int64_t n, const uint16_t *const *x, int comp,
   }
 }
 
-/* bf16 pair output of the same sum: hi = bf16(y32), lo = bf16(y32 - hi),
- * y32 the binary32 sum above (left to right or Sum2).  The difference is
+/* bf16 pair output of the same sum: hi = bf16(y32), lo = bf16(y32 - hi)
+ * (lo = +0 when hi is not finite), y32 the binary32 sum above (left to
+ * right or Sum2).  The difference is
  * exact in double (and in binary32: hi is y32 rounded to fewer bits in the
  * same binade), so hi + lo carries y32 to 16 significant bits. */
 void orc_sum_bf16_hilo(int P, int64_t n, const uint16_t *const *x, int comp,
@@ -259,6 +279,12 @@ void orc_sum_bf16_hilo(int P, int64_t n, const uint16_t *const *x, int comp,
     for (int r = 0; r < P; ++r) v[r] = (float)orc_bf16_decode(x[r][i]);
     float acc = acc_f32(P, v, comp);
     hi[i] = orc_bf16_encode((double)acc);
+    /* hi infinite (the sum is beyond bf16's range) or NaN: lo = +0, so that
+     * hi + lo is hi rather than a NaN from y - hi */
+    if (!isfinite(orc_bf16_decode(hi[i]))) {
+      lo[i] = 0;
+      continue;
+    }
     lo[i] = orc_bf16_encode((double)acc - orc_bf16_decode(hi[i]));
   }
 }
@@ -266,10 +292,7 @@ void orc_sum_bf16_hilo(int P, int64_t n, const uint16_t *const *x, int comp,
 void orc_max_bf16(int P, int64_t n, const uint16_t *const *x, uint16_t *y) {
   for (int64_t i = 0; i < n; ++i) {
     double m = orc_bf16_decode(x[0][i]);
-    for (int r = 1; r < P; ++r) {
-      double d = orc_bf16_decode(x[r][i]);
-      if (d > m) m = d;
-    }
+    for (int r = 1; r < P; ++r) m = maximum_ieee(m, orc_bf16_decode(x[r][i]));
     y[i] = orc_bf16_encode(m);
   }
 }

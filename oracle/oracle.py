@@ -4,9 +4,6 @@ Only the tests, the smoke check and the benchmark's CPU-baseline leg import
 this module.  It loads liboracle.so (plain C, built by gcc from oracle.c; see
 that file for every definition and its citation) through ctypes and marshals
 numpy arrays.  It imports nothing from the GPU package.
-
-The arrival-order model at the bottom restates the completion rules of
-Section 4.5 (Ordering Guarantee, Final Synchronization) for a single request.
 """
 import ctypes as C
 import os
@@ -293,19 +290,6 @@ class Oracle:
                                 self._ptr(y32))
         return yq, ysb, y32
 
-
-# ---- arrival model (Section 4.5: disjoint regions, completion rule) ------
-def arrival_constraints(order):
-    """For a pready sequence `order`, the set of partitions that may report
-    arrived after each step: only partitions already readied (a partition's
-    region is reduced only after it is marked ready), and after the final
-    wait every partition.  Returns a list of frozensets, one per step."""
-    seen = set()
-    out = []
-    for p in order:
-        seen.add(int(p))
-        out.append(frozenset(seen))
-    return out
 
 
 _DEFAULT = None

@@ -39,7 +39,7 @@ MUTANTS = {
     "twosum_sign_flip": (
         "*e = (a - av) + (b - bv);", "*e = (a - av) - (b - bv);"),
     "sum2_drops_correction": (
-        "return p + sigma;", "return p;"),
+        "return isfinite(p) ? p + sigma : p;", "return p;"),
     "bf16_decode_bias": (
         "v = ldexp((double)(128 + f), e - 127 - 7);",
         "v = ldexp((double)(128 + f), e - 128 - 7);"),
@@ -88,6 +88,26 @@ MUTANTS = {
     "bf16_hilo_low_part_sign": (
         "lo[i] = orc_bf16_encode((double)acc - orc_bf16_decode(hi[i]));",
         "lo[i] = orc_bf16_encode(orc_bf16_decode(hi[i]) - (double)acc);"),
+    "max_without_nan_check": (
+        "if (isnan(a) || isnan(b)) return NAN;", "/* no NaN check */"),
+    "max_keeps_running_value_unless_greater": (
+        "if (isnan(a) || isnan(b)) return NAN;\n"
+        "  if (a == b) return signbit(a) ? b : a; /* equal values: +0 over -0 */"
+        "\n  return a > b ? a : b;",
+        "return b > a ? b : a;"),
+    "max_signed_zero_keeps_first": (
+        "if (a == b) return signbit(a) ? b : a;", "if (a == b) return a;"),
+    "max_first_rank_only_compared": (
+        "for (int r = 1; r < P; ++r) m = maximum_ieee(m, (double)x[r][i]);",
+        "for (int r = 1; r < P - 1; ++r) m = maximum_ieee(m, (double)x[r][i]);"),
+    "sum2_corrects_non_finite_sums": (
+        "return isfinite(p) ? p + sigma : p;", "return p + sigma;"),
+    "bf16_encode_nan_keeps_sign": (
+        "if (isnan(v)) return 0x7fc0;",
+        "if (isnan(v)) return signbit(v) ? 0xffc0 : 0x7fc0;"),
+    "bf16_hilo_low_part_of_infinity": (
+        "if (!isfinite(orc_bf16_decode(hi[i]))) {",
+        "if (isnan(orc_bf16_decode(hi[i]))) {"),
     "plan_floor_instead_of_ceil": (
         "int64_t psize = (count + nparts - 1) / nparts;",
         "int64_t psize = count / nparts + (count > 0);"),

@@ -266,6 +266,153 @@ def test_max_f32(orc):
 
 
 # --------------------------------------------------------------------------
+# non-finite inputs: IEEE 754-2019 maximum, NaN encodings, sums
+# --------------------------------------------------------------------------
+SPECIALS = np.array([np.nan, np.inf, -np.inf, 0.0, -0.0, 1.0, -1.0,
+                     2.0 ** -149, -3.5], np.float32)
+
+
+def _combos(P):
+    """Every P-tuple of SPECIALS, as P rank arrays (one element per tuple)."""
+    grid = np.array(list(itertools.product(range(len(SPECIALS)), repeat=P)))
+    return [SPECIALS[grid[:, r]] for r in range(P)]
+
+
+def _max_properties(y, st):
+    """IEEE 754-2019 maximum, checked as properties of the result: NaN
+    exactly where some input is NaN (numpy's isnan); elsewhere bitwise one of
+    the inputs and, as a value, numpy's max; a zero result is +0 exactly when
+    some input is +0."""
+    nan_in = np.isnan(st).any(axis=0)
+    assert np.array_equal(np.isnan(y), nan_in)
+    ok = ~nan_in
+    yb, sb = y.view(np.uint32)[ok], st.view(np.uint32)[:, ok]
+    assert (sb == yb[None]).any(axis=0).all()
+    assert np.array_equal(y[ok], st[:, ok].max(axis=0))
+    zero = ok & (y == 0)
+    plus_zero_in = ((st == 0) & ~np.signbit(st)).any(axis=0)
+    assert np.array_equal(~np.signbit(y[zero]), plus_zero_in[zero])
+
+
+def test_max_f32_ieee_maximum(orc):
+    for P in (1, 2, 3, 4):
+        xs = _combos(P)
+        y = orc.max_f32(xs)
+        _max_properties(y, np.stack(xs))
+        # the same bits for every rank order (NaN results included)
+        for perm in itertools.permutations(range(P)):
+            yp = orc.max_f32([xs[i] for i in perm])
+            assert np.array_equal(yp.view(np.uint32), y.view(np.uint32))
+
+
+def test_max_f32_nan_from_any_rank(orc):
+    """A NaN at rank r makes the result NaN, whatever r and the others."""
+    for P in (2, 3, 8, 16):
+        for r in range(P):
+            xs = [np.float32([5.0, -0.0, np.inf]) for _ in range(P)]
+            xs[r] = np.float32([np.nan] * 3)
+            assert np.isnan(orc.max_f32(xs)).all(), (P, r)
+
+
+def _bf16_of(x):
+    return torch.from_numpy(np.asarray(x, np.float32)).to(torch.bfloat16) \
+        .view(torch.int16).numpy().view(np.uint16)
+
+
+def _bf16_dec(h):
+    return torch.from_numpy(np.ascontiguousarray(h).view(np.int16)) \
+        .view(torch.bfloat16).to(torch.float32).numpy()
+
+
+def test_bf16_max_ieee_maximum(orc):
+    # NaN inputs with other payloads and signs than the canonical one
+    nan_codes = np.uint16([0x7FC1, 0xFFC0, 0x7F81])
+    for P in (1, 2, 3):
+        xs = [_bf16_of(x) for x in _combos(P)]
+        for r in range(P):
+            xs[r][np.isnan(_bf16_dec(xs[r]))] = nan_codes[r % 3]
+        y = orc.max_bf16(xs)
+        st = np.stack([_bf16_dec(x) for x in xs])
+        _max_properties(_bf16_dec(y), st)
+        # NaN results are the canonical quiet NaN
+        assert (y[np.isnan(_bf16_dec(y))] == 0x7FC0).all()
+        for perm in itertools.permutations(range(P)):
+            assert np.array_equal(orc.max_bf16([xs[i] for i in perm]), y)
+
+
+def test_bf16_nan_encoding_is_canonical(orc):
+    """Every NaN, of either sign and any payload, encodes to 0x7FC0; every
+    NaN code decodes to NaN."""
+    assert orc.bf16_encode(float("nan")) == 0x7FC0
+    assert orc.bf16_encode(-float("nan")) == 0x7FC0
+    nan_codes = [c for c in range(1 << 16)
+                 if (c & 0x7F80) == 0x7F80 and (c & 0x7F)]
+    assert len(nan_codes) == 2 * 127
+    for c in nan_codes:
+        v = orc.bf16_decode(c)
+        assert math.isnan(v)
+        assert orc.bf16_encode(v) == 0x7FC0
+
+
+def _seq_sum(vals, dtype):
+    """IEEE left-to-right sum in numpy scalars of `dtype`."""
+    with np.errstate(all="ignore"):
+        acc = dtype(vals[0])
+        for v in vals[1:]:
+            acc = dtype(acc + dtype(v))
+    return acc
+
+
+def test_sums_with_non_finite_inputs(orc):
+    """Plain binary32 and FP64 sums follow IEEE arithmetic (numpy scalar
+    adds in the same order); the compensated sum gives the same result
+    whenever that result is not finite (infinity absorbs, opposite
+    infinities and NaN give NaN, overflow gives infinity); finite results
+    keep Sum2's value."""
+    big = np.float32(3.0e38)
+    cases = [[np.inf, 1.0, 2.0], [1.0, np.inf, -1.0], [np.inf, -np.inf],
+             [-np.inf, 5.0, -np.inf], [np.nan, 1.0], [1.0, 2.0, np.nan],
+             [big, big], [big, big, -big], [-big, -big, 1.0],
+             [1.0, 2.0 ** -30, -1.0]]
+    for P in (2, 3):
+        for t in itertools.product(SPECIALS, repeat=P):
+            cases.append(list(t))
+    for c in cases:
+        xs = [np.float32([v]) for v in c]
+        want32 = _seq_sum(c, np.float32)
+        want64 = _seq_sum([np.float64(np.float32(v)) for v in c], np.float64)
+        y = orc.sum_f32_f32(xs, comp=False)[0]
+        yc = orc.sum_f32_f32(xs, comp=True)[0]
+        y64 = orc.sum_f32_f64(xs)[0]
+        for got, want in ((y, want32), (y64, want64)):
+            assert (np.isnan(got) and np.isnan(want)) or got == want, c
+        if not np.isfinite(want32):
+            assert (np.isnan(yc) and np.isnan(want32)) or yc == want32, c
+        else:
+            assert np.isfinite(yc), c
+
+
+def test_bf16_sums_with_non_finite_inputs(orc):
+    """bf16 codes of non-finite sums: infinities keep their sign, NaN is
+    0x7FC0; the pair output of a sum that is not finite in bf16 is
+    (hi, +0)."""
+    top = 0x7F7F  # largest finite bf16, about 3.3895e38
+    cases = [([0x7F80, 0x3F80], 0x7F80), ([0xFF80, 0x3F80], 0xFF80),
+             ([0x7F80, 0xFF80], 0x7FC0), ([0x7FC1, 0x3F80], 0x7FC0),
+             ([0x3F80, 0xFFC3], 0x7FC0),
+             # finite in binary32, beyond bf16's range: rounds to +inf
+             ([top, 0x7B40], 0x7F80)]
+    for codes, want in cases:
+        xs = [np.uint16([c]) for c in codes]
+        for comp in (False, True):
+            yq = orc.sum_bf16_f32(xs, comp=comp)
+            yq = yq[0] if isinstance(yq, tuple) else yq
+            assert int(yq[0]) == want, (codes, comp)
+            hi, lo = orc.sum_bf16_hilo(xs, comp=comp)
+            assert int(hi[0]) == want and int(lo[0]) == 0, (codes, comp)
+
+
+# --------------------------------------------------------------------------
 # bfloat16 codec and sums
 # --------------------------------------------------------------------------
 def test_bf16_golden_values(orc):
