@@ -22,7 +22,12 @@ namespace pcoll {
 namespace dev {
 
 // ------------------------------------------------------------ accumulators
-template <bool COMP>
+// Float sum in binary32, plain or Sum2.  Non-finite values follow IEEE
+// arithmetic; once the running sum is not finite the TwoSum errors are
+// NaN, so the compensated result is the running sum itself (plain and
+// compensated sums then agree).  FINITE: the inputs and sums are known to
+// be finite (the 8-bit payloads), which spares that test.
+template <bool COMP, bool FINITE = false>
 struct FSum {
   float s, c;
   __device__ __forceinline__ void init(float v) { s = v; c = 0.0f; }
@@ -35,13 +40,22 @@ struct FSum {
       s = s + v;
     }
   }
-  __device__ __forceinline__ float get() const { return COMP ? s + c : s; }
+  __device__ __forceinline__ float get() const {
+    if (!COMP) return s;
+    if (FINITE) return s + c;
+    return __builtin_isfinite(s) ? s + c : s;
+  }
 };
 
+// Float max: the maximum operation of IEEE 754-2019 (NaN if any input is
+// NaN, +0 above -0), one v_maximum3_f32 on gfx950.  It is commutative and
+// associative, so the rank order does not change the result.
 struct FMax {
   float m;
   __device__ __forceinline__ void init(float v) { m = v; }
-  __device__ __forceinline__ void add(float v) { m = v > m ? v : m; }
+  __device__ __forceinline__ void add(float v) {
+    m = __builtin_elementwise_maximum(m, v);
+  }
   __device__ __forceinline__ float get() const { return m; }
 };
 
@@ -78,11 +92,12 @@ __device__ __forceinline__ float as_f(uint32_t u) { return __uint_as_float(u); }
 __device__ __forceinline__ float bf16_to_f(uint32_t h) {
   return __uint_as_float(h << 16);
 }
-// float -> bfloat16, round to nearest even (ties to the even code); NaN
-// stays NaN (quiet bit set); overflow rounds to infinity.
+// float -> bfloat16, round to nearest even (ties to the even code); every
+// NaN becomes the quiet NaN 0x7FC0 (sign and payload dropped); overflow
+// rounds to infinity.
 __device__ __forceinline__ uint32_t f_to_bf16(float f) {
   uint32_t u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;
+  if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0u;
   u += 0x7fffu + ((u >> 16) & 1u);
   return u >> 16;
 }
@@ -190,10 +205,12 @@ struct VecCombine<Acc, P, 2> {
 
 // bf16 pair output of a binary32 sum y: hi = bf16(y), lo = bf16(y - hi).
 // The difference is exact in binary32 (hi is y rounded to fewer bits in
-// the same binade), so hi + lo carries y to 16 significant bits.
+// the same binade), so hi + lo carries y to 16 significant bits.  When hi
+// is not finite (y is NaN, infinite or beyond bf16's range), lo = +0, so
+// that hi + lo is hi.
 __device__ __forceinline__ uint32_t bf16_pair(float y, uint32_t& lo) {
   const uint32_t hi = f_to_bf16(y);
-  lo = f_to_bf16(y - bf16_to_f(hi));
+  lo = (hi & 0x7f80u) == 0x7f80u ? 0u : f_to_bf16(y - bf16_to_f(hi));
   return hi;
 }
 
@@ -464,7 +481,7 @@ struct Fp8Tile {
     // every rank's codes and scale are requested before the first is used,
     // so that one memory latency covers the row
     if (FULL) __builtin_amdgcn_sched_barrier(0);
-    FSum<COMP> acc[16];
+    FSum<COMP, true> acc[16];
     {
       float d[16];
       dec16<Fmt>(raw[0], s_in[0], d);
@@ -637,7 +654,7 @@ struct MxTile {
       }
     }
     if (FULL) __builtin_amdgcn_sched_barrier(0);
-    FSum<COMP> acc[16];
+    FSum<COMP, true> acc[16];
     {
       float d[16];
       mx_dec16(raw[0], e8m0_operand(b_in[0]), d);

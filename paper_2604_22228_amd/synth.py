@@ -87,6 +87,61 @@ def random_bits(nranks, n, seed, dtype, device="cpu"):
                           dtype=torch.int16) for _ in range(nranks)]
 
 
+# Raw bit patterns of special values: quiet and signalling NaNs of both
+# signs with and without payload, infinities, signed zeros, the largest
+# finite magnitudes (whose sums overflow) and the smallest subnormals.
+F32_SPECIAL_BITS = (0x7FC00000, 0xFFC00001, 0x7F800001, 0xFFA00000,
+                    0x7F800000, 0xFF800000, 0x00000000, 0x80000000,
+                    0x7F7FFFFF, 0xFF7FFFFF, 0x00000001, 0x80000001)
+BF16_SPECIAL_CODES = (0x7FC0, 0xFFC1, 0x7F81, 0xFFA0, 0x7F80, 0xFF80,
+                      0x0000, 0x8000, 0x7F7F, 0xFF7F, 0x0001, 0x8001)
+
+
+def bf16_codes(nranks, n, seed, exp_lo=112, exp_hi=135, device="cpu"):
+    """Random bfloat16 codes (int16 views): random sign and 7 fraction
+    bits, biased exponent uniform on [exp_lo, exp_hi] (finite normals)."""
+    g = _gen(seed, device)
+    out = []
+    for _ in range(nranks):
+        sign = torch.randint(0, 2, (n,), generator=g, device=device,
+                             dtype=torch.int32)
+        ex = torch.randint(exp_lo, exp_hi + 1, (n,), generator=g,
+                           device=device, dtype=torch.int32)
+        fr = torch.randint(0, 128, (n,), generator=g, device=device,
+                           dtype=torch.int32)
+        code = (sign << 15) | (ex << 7) | fr
+        out.append(torch.where(code >= 32768, code - 65536, code)
+                   .to(torch.int16))
+    return out
+
+
+def plant_specials(codes, seed, specials, density=0.05, zero_cols=0.02):
+    """Copies of the raw-bit tensors `codes` (int32 or int16 views, one per
+    rank) in which each element is independently replaced, with
+    probability `density`, by a pattern drawn from `specials`, and a
+    fraction `zero_cols` of the element positions hold +0 or -0 (drawn per
+    rank) in every rank."""
+    g = _gen(seed, codes[0].device)
+    n = codes[0].numel()
+    bits = 32 if codes[0].dtype == torch.int32 else 16
+    pats = torch.tensor([v - (1 << bits) if v >= 1 << (bits - 1) else v
+                         for v in specials], dtype=codes[0].dtype,
+                        device=codes[0].device)
+    zcol = torch.rand(n, generator=g, device=codes[0].device) < zero_cols
+    neg0 = torch.tensor(-(1 << (bits - 1)), dtype=codes[0].dtype,
+                        device=codes[0].device)
+    out = []
+    for c in codes:
+        hit = torch.rand(n, generator=g, device=c.device) < density
+        pick = torch.randint(0, len(specials), (n,), generator=g,
+                             device=c.device)
+        v = torch.where(hit, pats[pick], c)
+        zsign = torch.rand(n, generator=g, device=c.device) < 0.5
+        zero = torch.where(zsign, neg0, torch.zeros_like(neg0))
+        out.append(torch.where(zcol, zero, v))
+    return out
+
+
 def permutation(n, seed):
     return np.random.default_rng(int(seed)).permutation(int(n))
 
