@@ -100,6 +100,46 @@ def probe_copy(pc, torch, steps):
             "GBps": 2 * nbytes / (ms * 1e-3) / 1e9}
 
 
+def probe_streams(pc, torch, steps, P=8, log2n=26):
+    """The headline's memory traffic without the reduce's protocol or
+    arithmetic (pcoll_probe_stream): P reads of 2^log2n FP32 elements each
+    and one write of their XOR (the reduce's P:1 read:write mix, the same
+    bytes as one headline launch), and the same P reads alone.  Buffers are
+    9x the MALL, so every launch streams from HBM.  GB/s over the mean
+    launch time (HIP events around `steps` launches)."""
+    n = 1 << log2n
+    nbytes = 4 * n
+    srcs = [torch.full((n,), float(r + 1), device="cuda") for r in range(P)]
+    dst = torch.empty(n, device="cuda")
+    s = torch.cuda.current_stream()
+    res = {}
+    for layout, lname in ((1, "tiles"), (0, "grid_stride")):
+        for name, write in (("read_write", 1), ("read_only", 0)):
+            for _ in range(2):
+                pc.pcoll_probe_stream(srcs, dst, nbytes, write, layout, s)
+            torch.cuda.synchronize()
+            e0, e1 = _events(torch)
+            e0.record(s)
+            for _ in range(steps):
+                pc.pcoll_probe_stream(srcs, dst, nbytes, write, layout, s)
+            e1.record(s)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            total = (P + write) * nbytes
+            res[f"{name}_{lname}"] = {
+                "bytes_per_launch": total, "ms": round(ms, 4),
+                "GBps": round(total / (ms * 1e-3) / 1e9, 1)}
+    res["streams"] = f"{P} reads of {nbytes >> 20} MiB (+ 1 write)"
+    res["layouts"] = ("tiles: the headline reduce's schedule (8192-element "
+                      "tiles in bands of 16, 2 workgroups of 8 waves per "
+                      "compute unit, tiles taken in turn) without its "
+                      "protocol; grid_stride: thread i takes vectors i, "
+                      "i + T, ...")
+    del srcs, dst
+    torch.cuda.empty_cache()
+    return res
+
+
 def cpu_baseline(orc, xs_dev, P, seconds):
     """The oracle (FP64 rank-order sum, element-parallel over the host
     cores) on a bounded sample: the first 2^24 elements (64 MiB) of every
@@ -172,6 +212,7 @@ def time_requests(torch, reqs, orders, stream, warmup, reps):
         for r, o in zip(reqs, orders):
             r.pready_list(o)
         e1.record(stream)
+        stream.query()  # the HIP runtime may hold the record back until then
         for r in reqs:
             r.wait()
         t1 = time.perf_counter()
@@ -214,6 +255,7 @@ def size_sweep(pc, torch, synth, stream):
                 req.start()
                 req.pready_list(order)
                 e1.record(stream)
+                stream.query()  # submits the record now
                 req.wait()
                 if it >= 2:
                     e1.synchronize()
@@ -241,13 +283,13 @@ def rank_readiness(pc, torch, synth, reps=5):
     outside the library), ranks spread over two streams.  overlapped: the
     reduction starts first and each (rank, partition) is marked on the
     device right after its product, so the kernel reduces each partition
-    while later ones are produced; run with 4-wave workgroups and 2 rows in
-    flight per lane (one resident wave per SIMD with fewer registers: the
-    products' matrix-core waves must start beside the resident kernel), on
-    every compute unit and on 64 of them (a persistent kernel that waits
-    holds registers the producers could use).  bulk: every product
-    first, then start, ready
-    everything, wait.  Host ms from the first product to the return of wait
+    while later ones are produced; run in the library's producer mode
+    (`producers` = 1: one resident wave per SIMD with fewer registers, so
+    that the products' matrix-core waves start beside the resident kernel),
+    on every compute unit and on 64 of them (a persistent kernel that waits
+    holds registers the producers could use); the signalling streams are
+    checked to run beside the reduce kernel's stream.  bulk: every product
+    first, then start, ready everything, wait.  Host ms from the first product to the return of wait
     (median); `identical`: every run gives the same output bits."""
     import statistics
     dev = torch.device("cuda:0")
@@ -258,8 +300,9 @@ def rank_readiness(pc, torch, synth, reps=5):
     b_ = torch.randn(k, q, device=dev, generator=gen)
     xs = [torch.empty(n, device=dev) for _ in range(P)]
     out = torch.empty(n, device=dev)
-    sig = [torch.cuda.Stream(dev) for _ in range(2)]
+    from paper_2604_22228_amd.streams import independent_streams
     stream = torch.cuda.Stream(dev)
+    sig = independent_streams(stream, 2)
     req = pc.Request([n], pc.FLOAT32, pc.SUM, nparts, P)
     req.bind([xs], [out], stream=stream)
     parts_dev = torch.arange(nparts, dtype=torch.int32, device=dev)
@@ -297,8 +340,7 @@ def rank_readiness(pc, torch, synth, reps=5):
     for name, fn, groups in (("overlapped_ms", overlapped, 0),
                              ("overlapped_64_groups_ms", overlapped, 64),
                              ("bulk_ms", bulk, 0)):
-        req.set_config(groups=groups, groups_per_cu=1, group_waves=4,
-                       unroll=2)
+        req.set_config(groups=groups, producers=1)
         ts = []
         for it in range(2 + reps):
             torch.cuda.synchronize()
@@ -316,9 +358,8 @@ def rank_readiness(pc, torch, synth, reps=5):
         res["overlapped_ms"], res["overlapped_64_groups_ms"]), 3)
     res["workload"] = ("8 ranks, FP32, 2^26 elements per rank, 8 partitions, "
                        "an 8.6 GFLOP FP32 product per rank and partition")
-    res["reduce_group_waves"] = 4
-    res["reduce_unroll"] = 2
-    res["reduce_groups_per_cu"] = 1
+    res["reduce_config"] = "producers = 1 (one workgroup of 4 waves per "\
+        "compute unit, 2 rows in flight per lane)"
     return res
 
 
@@ -363,6 +404,7 @@ def graph_lifecycle(pc, torch, reps=20):
                     h1 = time.perf_counter()
                     req.pready_list(order)
                     e1.record(stream)
+                    stream.query()  # submits the record now
                     req.wait()
                     e1.synchronize()
                     hs.append((h1 - h0) * 1e6)
@@ -427,9 +469,95 @@ def eight_bit(pc, torch, synth, fmt, stream, warmup, reps):
     res = {"host_ms": round(h, 4), "kernel_ms": round(d, 4),
            "GBps": round(nbytes / d / 1e6, 1), "comp": req.config().comp}
     req.free()
+    res["error"] = eight_bit_errors(pc, torch, synth, fmt, counts, qs, ss, ys,
+                                    yss, stream)
     del qs, ss, ys, yss
     torch.cuda.empty_cache()
     return key, res
+
+
+def _dequant(torch, fmt, codes, scales, c):
+    """Values of 8-bit codes and their block scales, in float32 (exact):
+    torch's float8 decode times the binary32 scale of each 256 elements, or
+    times 2^(b - 127) of each E8M0 byte b of 32 elements."""
+    f8 = torch.float8_e5m2 if fmt == "e5m2" else torch.float8_e4m3fn
+    v = codes[:c].view(f8).float()
+    if fmt == "mxfp8":
+        s = torch.ldexp(torch.ones_like(scales, dtype=torch.float32),
+                        scales.int() - 127)
+        return v * s.repeat_interleave(32)[:c]
+    return v * scales.repeat_interleave(256)[:c]
+
+
+def eight_bit_errors(pc, torch, synth, fmt, counts, qs, ss, ys, yss, stream,
+                     sample=1 << 24):
+    """Error of the 8-bit result, ungated, on a sample of buckets (every
+    8th bucket from the first until 2^24 elements): against the FP64 sum of
+    the dequantized payload in rank order (the reduction's own error,
+    torch float64 on the host) and against the library's plain FP32 path
+    run on the values before quantization (end to end: packing plus
+    reduction).  Max Sigma|x|-normalized error |y - ref| / max(Sigma|x|,
+    tau) (tau = the output block's smallest normal, for the FP64 error) and
+    the normwise ||y - ref|| / ||ref||."""
+    dev = torch.device("cuda:0")
+    pick, tot = [], 0
+    for b in range(0, len(counts), 8):
+        if tot >= sample:
+            break
+        pick.append(b)
+        tot += counts[b]
+    e64 = eend = 0.0
+    n64 = d64 = nend = dend = 0.0
+    for b in pick:
+        c = counts[b]
+        blk = 32 if fmt == "mxfp8" else 256
+        y = _dequant(torch, fmt, ys[b], yss[b], c)
+        xq = [_dequant(torch, fmt, q, s, c) for q, s in zip(qs[b], ss[b])]
+        # FP64 reference of the payload, rank order, on the host
+        y64 = torch.zeros(c, dtype=torch.float64)
+        absq = torch.zeros(c, dtype=torch.float64)
+        for x in xq:
+            xh = x.cpu().double()
+            y64 += xh
+            absq += xh.abs()
+        if fmt == "mxfp8":
+            so = torch.ldexp(torch.ones(yss[b].numel(), dtype=torch.float64),
+                             yss[b].cpu().long() - 127)
+        else:
+            so = yss[b].cpu().double()
+        small = {"e4m3": 2.0 ** -6, "mxfp8": 2.0 ** -6, "e5m2": 2.0 ** -14}
+        tau = (so * small[fmt]).repeat_interleave(blk)[:c]
+        yh = y.cpu().double()
+        e64 = max(e64, float(((yh - y64).abs() / torch.maximum(absq, tau))
+                             .max()))
+        n64 += float(((yh - y64) ** 2).sum())
+        d64 += float((y64 ** 2).sum())
+        # the plain FP32 path on the values before quantization
+        xs = synth.normal_with_outliers_f32(
+            8, c, synth.seed_for(5) * 1000 + b, 1e-2, device=dev)
+        yf = torch.empty(c, device=dev)
+        r = pc.Request([c], pc.FLOAT32, pc.SUM, 32, 8)
+        r.bind([xs], [yf], stream=stream)
+        r.start()
+        r.pready_range(0, 31)
+        r.wait()
+        r.free()
+        torch.cuda.synchronize()
+        absx = torch.stack([x.abs() for x in xs]).sum(0)
+        tiny = torch.full_like(absx, 2.0 ** -126)
+        eend = max(eend, float(((y - yf).abs() / torch.maximum(absx, tiny))
+                               .max()))
+        nend += float(((y - yf).double() ** 2).sum())
+        dend += float((yf.double() ** 2).sum())
+        del xs, yf, xq, y
+    return {"sample_buckets": len(pick), "sample_elements": tot,
+            "vs_fp64_payload_max_norm": e64,
+            "vs_fp64_payload_normwise": (n64 / d64) ** 0.5 if d64 else 0.0,
+            "vs_plain_fp32_path_max_norm": eend,
+            "vs_plain_fp32_path_normwise": (nend / dend) ** 0.5 if dend
+            else 0.0,
+            "gate_vs_fp64": {"e4m3": 6e-2, "mxfp8": 6e-2,
+                             "e5m2": 1 / 9 + 16 * 2.0 ** -24}[fmt]}
 
 
 
@@ -457,6 +585,7 @@ def extras(pc, torch, synth, warmup, reps):
         guard(key, run)
 
     put("copy_probe", probe_copy, pc, torch, 10)
+    put("stream_probe", probe_streams, pc, torch, 10)
     put("size_sweep", size_sweep, pc, torch, synth, stream)
     put("rank_readiness", rank_readiness, pc, torch, synth)
     put("graph_lifecycle", graph_lifecycle, pc, torch)
@@ -649,6 +778,7 @@ def main():
         for p in order:
             req.pready(p)
         e1.record(stream)  # enqueued behind the kernel on its stream
+        stream.query()  # submitted now, not at the next look at the stream
         req.wait()
         marks.append(time.perf_counter())
     torch.cuda.synchronize()
@@ -717,8 +847,16 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_extras:
         line["extras"] = extras(pc, torch, synth, 2, 5)
-        copy = line["extras"]["copy_probe"]["GBps"]
-        line["config"]["pct_of_copy_probe"] = round(100 * value / copy, 2)
+        ex = line["extras"]
+        if "GBps" in ex.get("copy_probe", {}):
+            line["config"]["pct_of_copy_probe"] = round(
+                100 * value / ex["copy_probe"]["GBps"], 2)
+        rw = ex.get("stream_probe", {}).get("read_write_tiles", {})
+        if "GBps" in rw:
+            # the reduce kernel against the same traffic without its
+            # protocol or arithmetic: the attainable rate of this mix
+            line["roofline"]["pct_of_attainable"] = round(
+                100 * achieved / rw["GBps"], 2)
     print(json.dumps(line), flush=True)
 
 

@@ -101,22 +101,40 @@ enum {
 
 /* ---------------------------------------------------------------- setup */
 
-/* Creates a request for one message of `count` elements (count >= 0) of
- * `dtype`, reduced with `op` over `nranks` ranks (1..PCOLL_MAX_RANKS), split
- * into `nparts` >= 1 partitions.  Allocates the request's flags (host-
- * coherent pinned memory) and counters (device memory) on the current HIP
- * device.  PCOLL_ERR_UNSUPPORTED for max on the 8-bit dtypes. */
-int pcoll_init(size_t count, int dtype, int op, int nparts, int nranks,
-               pcoll_req_t *out);
+/* Creates a persistent request for one message of `count` elements
+ * (count >= 0) of `dtype`, reduced with `op` over `nranks` ranks
+ * (1..PCOLL_MAX_RANKS), split into `nparts` >= 1 partitions by the chunk
+ * rule of Algorithm 1 (Section 4.3: equal ceil-length chunks at offsets
+ * fixed in advance, the last one clipped; see "Partitions" above).  The
+ * persistent-request life cycle (init once, then start / ready / wait per
+ * epoch) is the MPI-4 partitioned communication model, not the paper's,
+ * which issues one transfer per call.  Allocates the request's flags
+ * (host-coherent pinned memory) and counters (device memory) on the
+ * current HIP device; the request owns them until pcoll_free.
+ * PCOLL_ERR_ARG for a null `out`, an unknown dtype or op, nparts < 1 or
+ * nranks < 1; PCOLL_ERR_UNSUPPORTED for nranks > PCOLL_MAX_RANKS, max on
+ * the 8-bit dtypes and bf16 pairs, more than 2^24 partitions in all, or a
+ * partition longer than 2^31 elements; PCOLL_ERR_NOMEM if an allocation
+ * fails.  *out is NULL on error. */
+int pcoll_init(size_t count, pcoll_dtype_t dtype, pcoll_op_t op, int nparts,
+               int nranks, pcoll_req_t *out);
 
-/* Batched form: `nbuckets` >= 1 messages of counts[b] elements, each split
- * into `nparts_per_bucket` partitions; partition k of bucket b has the
- * global index b * nparts_per_bucket + k.  One start launches one
- * persistent kernel for all buckets. */
-int pcoll_init_batch(int nbuckets, const size_t *counts, int dtype, int op,
-                     int nparts_per_bucket, int nranks, pcoll_req_t *out);
+/* Batched form: `nbuckets` >= 1 messages of counts[b] elements (host
+ * array, read during the call), each split into `nparts_per_bucket`
+ * partitions; partition k of bucket b has the global index
+ * b * nparts_per_bucket + k.  One start launches one persistent kernel for
+ * all buckets (the paper records a whole multi-chunk transfer as one graph,
+ * Algorithm 1; here one kernel covers every chunk of every bucket).  Many
+ * uneven gradient buckets in one request are this library's extension, not
+ * the paper's.  Errors as pcoll_init, and PCOLL_ERR_ARG for nbuckets < 1 or
+ * a null `counts`. */
+int pcoll_init_batch(int nbuckets, const size_t *counts, pcoll_dtype_t dtype,
+                     pcoll_op_t op, int nparts_per_bucket, int nranks,
+                     pcoll_req_t *out);
 
-/* Binds data buffers and the stream kernels are enqueued on.
+/* Binds data buffers and the stream kernels are enqueued on (host arrays
+ * of device pointers, read during the call; the library keeps the
+ * pointers, the caller keeps ownership of the buffers).
  *   rank_bufs  nbuckets * nranks device pointers, bucket-major:
  *              rank_bufs[b * nranks + r] = contribution of rank r to b.
  *   outs       nbuckets device pointers (may equal a rank buffer only if
@@ -129,10 +147,17 @@ int pcoll_init_batch(int nbuckets, const size_t *counts, int dtype, int op,
  *              32) per bucket.  For PCOLL_BF16_PAIR rank_scales is NULL
  *              and out_scales holds the nbuckets lo arrays (bf16, count
  *              elements each, 16-byte aligned).
- * Not allowed while an epoch is active.  A binding seen before (same
- * pointers and stream) reuses its cached descriptor table and graph; each
- * request keeps the PCOLL_GRAPH_CACHE (environment, default 8) most
- * recently used bindings and frees the least recently used beyond that. */
+ * Not allowed while an epoch is active (PCOLL_ERR_STATE).  PCOLL_ERR_ARG
+ * for null arrays, null pointers of non-empty buckets, misaligned
+ * pointers, or second-output / scale arrays given for a dtype that has
+ * none (or missing for one that needs them).
+ * A binding seen before (same pointers and stream) reuses its cached
+ * descriptor table and graph: the cache of Section 4.2 (Framework
+ * Architecture), which keeps instantiated graphs in a fixed-size hash table
+ * keyed by the transfer's addresses and evicts the least recently used.
+ * Each request keeps the PCOLL_GRAPH_CACHE (environment, default 8) most
+ * recently used bindings and frees the least recently used beyond that
+ * (after the last kernel that used it has retired). */
 int pcoll_bind(pcoll_req_t req, const void *const *rank_bufs,
                void *const *outs, const void *const *rank_scales,
                void *const *out_scales, void *stream);
@@ -141,37 +166,56 @@ int pcoll_bind(pcoll_req_t req, const void *const *rank_bufs,
 
 /* Starts an epoch: asynchronously launches the persistent reduce kernel on
  * the bound stream (or, in graph mode, replays the cached graph; the graph
- * is captured and instantiated lazily on first use, after Algorithm 1's
- * LaunchGraph).  PCOLL_ERR_STATE if unbound or an epoch is still active.
+ * is captured and instantiated lazily on first use and launched from the
+ * cache afterwards, as Algorithm 1's LaunchGraph does, Section 4.3).
+ * PCOLL_ERR_STATE if unbound or an epoch is still active.  Epochs are the
+ * MPI-4 persistent-request model (MPI_Start), not the paper's. 
  *
  * The kernel occupies its stream until every partition is ready.  Work on
  * a stream that HIP placed on the same hardware queue runs after it (HIP
  * spreads a process's streams over GPU_MAX_HW_QUEUES queues, 4 by
  * default): do not make the readiness of an epoch wait for such work, for
- * example for another request's epoch whose stream shares the queue; the
- * epoch would end at its deadline with PCOLL_ERR_ABORTED. */
+ * example for another request's epoch whose stream shares the queue, or
+ * for producers on such a stream; the epoch would end at its deadline with
+ * PCOLL_ERR_ABORTED.  HIP does not say which streams share a queue; the
+ * Python helper paper_2604_22228_amd.streams.independent_streams finds
+ * streams that run beside a given one. */
 int pcoll_start(pcoll_req_t req);
 
 /* Marks partition `part` ready (host side, non-blocking, about a store to
- * pinned memory).  PCOLL_ERR_STATE if no epoch is active or the partition
- * was already readied this epoch; PCOLL_ERR_ARG if out of range. */
+ * pinned memory): MPI_Pready of the MPI-4 partitioned model, which the
+ * paper does not have; its nearest notion is the per-chunk synchronization
+ * point after which a chunk may proceed (Section 4.5).  PCOLL_ERR_STATE if
+ * no epoch is active or the partition was already readied this epoch;
+ * PCOLL_ERR_ARG if out of range. */
 int pcoll_pready(pcoll_req_t req, int part);
 
-/* Marks partitions first..last (inclusive) ready; all-or-nothing. */
+/* Marks partitions first..last (inclusive) ready; all-or-nothing
+ * (MPI_Pready_range).  Errors as pcoll_pready; PCOLL_ERR_ARG if
+ * last < first. */
 int pcoll_pready_range(pcoll_req_t req, int first, int last);
 
-/* Marks parts[0..n) ready; all-or-nothing (duplicates are an error).  The
- * partitions of one call become ready at the same instant, so the library
- * queues them in partition order (neighbouring partitions of a bucket are
- * then reduced together), whatever their order in `parts`. */
+/* Marks parts[0..n) (host array) ready; all-or-nothing, duplicates are
+ * PCOLL_ERR_ARG (MPI_Pready_list).  The partitions of one call become
+ * ready at the same instant, so the library queues them in partition order
+ * (neighbouring partitions of a bucket are then reduced together),
+ * whatever their order in `parts`. */
 int pcoll_pready_list(pcoll_req_t req, int n, const int *parts);
 
 /* Device-side ready signal: enqueues on `stream` a kernel that marks the
  * partitions in the device array parts_dev[0..n) ready when it runs, so
  * readiness can follow producer kernels in stream order (or be captured in
- * a graph).  `stream` must not be the bound stream (the reduce kernel
- * occupies it until every partition is ready).  Each partition must be
- * readied once per epoch; ids out of range are ignored.
+ * a graph).  Not in the paper (whose chunks are readied by events between
+ * graph nodes, Section 4.5); the device form of MPI_Pready.  The array must
+ * stay valid until the signal has run.  `stream` must not be the bound
+ * stream (PCOLL_ERR_ARG: the reduce kernel occupies it until every
+ * partition is ready); PCOLL_ERR_STATE if no epoch is active.  Ids out of
+ * range are ignored, and a partition signalled more than once in an epoch
+ * counts once.  The signal belongs to the epoch that was active when it
+ * was enqueued: if that epoch has ended by the time it runs (for example
+ * through pcoll_wait_timeout while it waited behind its producer), it
+ * readies nothing.  The request's launches leave room for producers from
+ * the next start on (config field `producers`).
  *
  * The signal must be able to run while the reduce kernel runs, so its
  * stream must not share the bound stream's hardware queue: HIP spreads a
@@ -184,20 +228,20 @@ int pcoll_pready_list(pcoll_req_t req, int n, const int *parts);
  *
  * Likewise the kernels that produce the data and precede the signal on
  * its stream must find room on the compute units beside the resident
- * reduce kernel, whose workgroups of `group_waves` waves (groups_per_cu of
- * them per unit) stay until the epoch ends.  A producer wave that needs
- * more registers or LDS than a unit has left cannot start, so readiness
- * never comes.  With matrix-core (MFMA) producers, whose waves can take
- * most of a SIMD's register file, leave room with pcoll_set_config: one
- * resident wave per SIMD (groups_per_cu = 1 and group_waves = 4, or fewer
- * groups) and unroll = 2 (about 115 instead of 160-190 VGPRs per wave at 8
- * ranks).  The tuned defaults are chosen for host-readied requests and may
- * put more waves on each unit. */
+ * reduce kernel, whose workgroups stay until the epoch ends.  A producer
+ * wave that needs more registers or LDS than a unit has left cannot start,
+ * so readiness never comes.  The producer mode (config field `producers`)
+ * keeps one resident wave per SIMD with about 115 instead of 160-190 VGPRs
+ * per wave at 8 ranks, which leaves matrix-core (MFMA) producers room; in
+ * the default automatic mode a request enters it from the start after its
+ * first device-side signal, so set `producers` = 1 before the first epoch
+ * whose readiness follows heavy producers. */
 int pcoll_pready_on_stream(pcoll_req_t req, const int *parts_dev, int n,
                            void *stream);
 
-/* Per-rank readiness (the receive side of a partitioned allreduce): rank
- * `rank` (0..nranks-1) has placed its contribution to partition `part`.
+/* Per-rank readiness (the receive side of a partitioned allreduce; the
+ * MPI-4 partitioned model, not in the paper): rank `rank` (0..nranks-1)
+ * has placed its contribution to partition `part`.
  * The partition becomes ready, exactly as by pcoll_pready, once every rank
  * has readied it this epoch; until then the kernel does not touch it.
  * Host-side bookkeeping only (no GPU call unless this completes the
@@ -206,20 +250,24 @@ int pcoll_pready_on_stream(pcoll_req_t req, const int *parts_dev, int n,
  * PCOLL_ERR_ARG if rank or part is out of range. */
 int pcoll_pready_rank(pcoll_req_t req, int rank, int part);
 
-/* Device-side per-rank readiness: enqueues on `stream` a kernel that marks
- * rank `rank`'s contributions to the partitions parts_dev[0..n) (device
- * array) in place when it runs, so each rank's marks can follow its
- * producer kernels in that rank's stream order.  A partition is queued
- * when the marks of all ranks for the current epoch are in; repeated marks
- * of one rank are idempotent and ids out of range are ignored.  All ranks
- * of one partition must mark it on the device (pcoll_pready_rank counts on
- * the host, apart).  `stream` must not be the bound stream, nor share its
- * hardware queue (see pcoll_pready_on_stream). */
+/* Device-side per-rank readiness (not in the paper): enqueues on `stream`
+ * a kernel that marks rank `rank`'s contributions to the partitions
+ * parts_dev[0..n) (device array, valid until the kernel has run) in place
+ * when it runs, so each rank's marks can follow its producer kernels in
+ * that rank's stream order.  A partition is queued when the marks of all
+ * ranks for the epoch that was active at enqueue time are in; repeated
+ * marks of one rank are idempotent, ids out of range are ignored, and a
+ * mark that runs after its epoch ended changes nothing (not even a later
+ * epoch's marks).  All ranks of one partition must mark it on the device
+ * (pcoll_pready_rank counts on the host, apart).  `stream` must not be the
+ * bound stream (PCOLL_ERR_ARG), nor share its hardware queue (see
+ * pcoll_pready_on_stream); PCOLL_ERR_ARG for a rank out of range,
+ * PCOLL_ERR_STATE if no epoch is active. */
 int pcoll_pready_rank_on_stream(pcoll_req_t req, int rank,
                                 const int *parts_dev, int n, void *stream);
 
-/* Non-blocking test of one partition: *flag = 1 once its output is final in
- * the current (or last completed) epoch.  PCOLL_ERR_STATE before the first
+/* Non-blocking test of one partition (MPI_Parrived): *flag = 1 once its
+ * output is final in the current (or last completed) epoch.  PCOLL_ERR_STATE before the first
  * start.  Arrival (Section 4.5: a partition counts only after all of its
  * chunks have landed) is signalled either by the partition's own flag,
  * which the kernel sets as soon as it has published the partition's last
@@ -230,30 +278,40 @@ int pcoll_pready_rank_on_stream(pcoll_req_t req, int rank,
  * hipEventQuery. */
 int pcoll_parrived(pcoll_req_t req, int part, int *flag);
 
-/* Non-blocking test of the whole epoch: *flag = 1 once every partition has
- * arrived; completes the epoch like pcoll_wait when it does. */
+/* Non-blocking test of the whole epoch (MPI_Test): *flag = 1 once every
+ * partition has arrived; completes the epoch like pcoll_wait when it does.
+ * Returns the epoch's error as pcoll_wait does. */
 int pcoll_test(pcoll_req_t req, int *flag);
 
 /* Blocks until every partition has arrived (by its flag, or by the
- * kernel's clean retirement; see pcoll_parrived) and the epoch is complete.
+ * kernel's clean retirement; see pcoll_parrived) and the epoch is complete
+ * (Section 4.5, Final Synchronization: completion only after every chunk's
+ * synchronization point; MPI_Wait of the MPI-4 model).
  * Returns PCOLL_ERR_ABORTED if the kernel gave up on its own deadline
  * (configurable, default 10 s) because some partition was never readied.
  * A request with no active epoch returns at once. */
 int pcoll_wait(pcoll_req_t req);
 
-/* As pcoll_wait, but gives up after `ms` milliseconds: the kernel is told
- * to stop waiting for unready partitions, the call returns
+/* As pcoll_wait, but gives up after `ms` milliseconds (not in the paper or
+ * the MPI-4 model; a way out of an epoch whose partitions never come): the
+ * kernel is told to stop waiting for unready partitions, the call returns
  * PCOLL_ERR_TIMEOUT once it has drained, and the epoch is over (partitions
- * that had arrived are final; the others are undefined). */
+ * that had arrived are final; the others are undefined).  Device-side
+ * signals of that epoch still queued ready nothing when they run.
+ * PCOLL_ERR_ARG for ms < 0. */
 int pcoll_wait_timeout(pcoll_req_t req, int ms);
 
 /* Makes `stream` wait (on the device) for the end of the current epoch's
- * kernel; does not block the host and does not complete the epoch (call
- * pcoll_wait or pcoll_test before the next start). */
+ * kernel: the non-blocking final synchronization of Section 4.5, which
+ * records an event after the transfer and makes the user's stream wait on
+ * it instead of blocking the host.  Does not complete the epoch (call
+ * pcoll_wait or pcoll_test before the next start).  PCOLL_ERR_STATE if no
+ * epoch is active. */
 int pcoll_wait_on_stream(pcoll_req_t req, void *stream);
 
-/* Releases the request (after waiting for its last kernel to retire).
- * PCOLL_ERR_STATE while an epoch is active. */
+/* Releases the request and everything it owns (flags, counters, cached
+ * descriptor tables and graphs), after waiting for its last kernel to
+ * retire (MPI_Request_free).  PCOLL_ERR_STATE while an epoch is active. */
 int pcoll_free(pcoll_req_t req);
 
 const char *pcoll_strerror(int code);
@@ -304,6 +362,20 @@ typedef struct {
                         fewer registers per wave and leaves room for
                         kernels that run beside the reduction (see
                         pcoll_pready_on_stream) */
+  int producers;     /* room for producer kernels beside the reduction:
+                        1 = the launch keeps one resident wave per SIMD
+                        (one workgroup per compute unit unless `groups` is
+                        given, at most 4 waves each) and 2 rows in flight
+                        per lane, so that the kernels producing the data
+                        that device-side signals follow (matrix-core ones
+                        included) find registers and wave slots while the
+                        reduce kernel waits; 0 = the tuned launch, for
+                        requests readied from the host; -1 (the default) =
+                        automatic: the tuned launch until the request's
+                        first device-side signal (pcoll_pready_on_stream,
+                        pcoll_pready_rank_on_stream), room from the next
+                        start on.  Overrides groups_per_cu, group_waves
+                        above 4 and unroll while room is kept. */
 } pcoll_config_t;
 
 /* Reads the request's configuration.  The defaults come from the tuned
@@ -311,7 +383,7 @@ typedef struct {
  * then from environment overrides: PCOLL_TILE, PCOLL_MIN_TILE, PCOLL_GROUPS,
  * PCOLL_GROUPS_PER_CU, PCOLL_COMP, PCOLL_GRAPH, PCOLL_TIMEOUT_MS,
  * PCOLL_DEBUG, PCOLL_INTERLEAVE, PCOLL_GUIDE, PCOLL_GROUP_WAVES,
- * PCOLL_PUBLISH_BATCH, PCOLL_UNROLL. */
+ * PCOLL_PUBLISH_BATCH, PCOLL_UNROLL, PCOLL_PRODUCERS. */
 int pcoll_get_config(pcoll_req_t req, pcoll_config_t *cfg);
 
 /* Replaces the configuration (not while an epoch is active).  Fields out of
@@ -339,7 +411,10 @@ typedef struct {
   float last_kernel_ms;       /* device time of the last epoch's kernel,
                                  if debug timing was on, else -1 */
   int groups;                 /* workgroups of the last launch */
-  int reserved;
+  int group_waves;            /* wavefronts per workgroup of the last launch */
+  int unroll;                 /* rows in flight per lane of the last launch
+                                 (2 or 4; the kernels above 8 ranks keep 1
+                                 whatever this says) */
 } pcoll_stats_t;
 
 int pcoll_get_stats(pcoll_req_t req, pcoll_stats_t *st);
@@ -350,13 +425,27 @@ int pcoll_get_stats(pcoll_req_t req, pcoll_stats_t *st);
 int pcoll_debug_tile_hits(pcoll_req_t req, uint32_t *hits, uint32_t *tiles,
                           int n);
 
+/* Test hook: clears every epoch stamp of the request (after waiting for the
+ * whole device to go idle, so that no ready signal of an ended epoch is
+ * still queued) and sets the epoch count so that the next start runs epoch
+ * last + 1, or epoch 2 when `last` is 2^32 - 1 (epoch 0 is never used).
+ * The library does the same clear by itself when the count wraps, since
+ * stamps left from 2^32 epochs earlier could pass for current ones; this
+ * call lets a test cross the wrap.  PCOLL_ERR_STATE while an epoch is
+ * active. */
+int pcoll_debug_set_epoch(pcoll_req_t req, uint32_t last);
+
 /* Host-only partition plan (no GPU needed): for a message of `count`
  * elements of `dtype` split into `nparts` partitions, writes the common
  * partition length to *psize and, if non-NULL, offsets/lengths of each. */
-int pcoll_plan(size_t count, int dtype, int nparts, size_t *psize,
+int pcoll_plan(size_t count, pcoll_dtype_t dtype, int nparts, size_t *psize,
                size_t *offsets, size_t *lengths);
 
 /* ------------------------------------------------------ producer packing */
+/* The producer side of the low-precision payloads (not in the paper, which
+ * moves bytes): encoders whose codes and scales the reduce kernels decode.
+ * Each enqueues one kernel on `stream`; PCOLL_ERR_ARG for null or
+ * misaligned pointers, PCOLL_ERR_HIP if the launch fails. */
 
 /* dst[i] = bf16 of src[i], round to nearest even.  n elements; src, dst
  * 16-byte aligned device pointers; enqueued on `stream`. */
@@ -387,6 +476,23 @@ int pcoll_pack_mxfp8(const float *src, uint8_t *dst, uint8_t *scales,
 /* Streaming copy of `bytes` (a multiple of 16) with 16-byte loads/stores:
  * the attainable-bandwidth reference of the device. */
 int pcoll_probe_copy(void *dst, const void *src, size_t bytes, void *stream);
+
+/* The reduce's memory traffic without its protocol or arithmetic: reads
+ * `nsrc` (1, 2, 4, 8 or 16) device buffers of `bytes` each (srcs is a host
+ * array of 16-byte aligned device pointers) with 16-byte nontemporal loads
+ * and, with write = 1, stores their bitwise XOR to `dst` (`bytes` bytes):
+ * nsrc read streams and one write stream, the mix of a reduction over nsrc
+ * ranks.  With write = 0 nothing is stored (`dst` must still hold 16
+ * bytes): read streams only.  layout 0: a grid-stride stream (thread i
+ * takes vectors i, i + T, ...; `bytes` a multiple of 16); layout 1: the
+ * reduce's own schedule (rows of 64 x 16 bytes, tiles of 32 rows in bands
+ * of 16 tiles, 2 workgroups of 8 waves per compute unit, each taking tiles
+ * in turn; `bytes` a multiple of 1024, at most 64 GiB), so that the reduce kernel's time
+ * against it is what its readiness and completion protocol costs.  The
+ * attainable-bandwidth references of the reduce kernels; PCOLL_ERR_ARG for
+ * other counts or sizes, null or misaligned pointers. */
+int pcoll_probe_stream(const void *const *srcs, int nsrc, void *dst,
+                       size_t bytes, int write, int layout, void *stream);
 
 /* Fills `bytes` (a multiple of 16) with a 32-bit pattern. */
 int pcoll_probe_fill(void *dst, size_t bytes, uint32_t value, void *stream);

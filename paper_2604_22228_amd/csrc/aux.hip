@@ -40,25 +40,68 @@ hipError_t launch_reduce(const ReduceArgs& a, int dtype, int op, bool comp,
 }
 
 // ------------------------------------------------------------ ready signal
-// Appends parts[0..n) to the device ready ring.  One workgroup reserves its
-// entries with a single atomic on the ring's 64-bit entry counter; entry c
-// goes to slot c % capacity as one 64-bit store ((uint32)c << 32) | part,
-// so a reader sees either the old or the new entry and can tell them apart.
-__global__ __launch_bounds__(256) void pready_kernel(PreadyArgs a) {
-  __shared__ uint64_t base;
-  const uint32_t i = blockIdx.x * 256u + threadIdx.x;
-  const uint32_t first = blockIdx.x * 256u;
-  const uint32_t cnt = a.n - first < 256u ? a.n - first : 256u;
-  if (threadIdx.x == 0)
-    base = __hip_atomic_fetch_add(&a.ring->dreserve, (uint64_t)cnt,
-                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __syncthreads();
-  if (i < a.n) {
-    const uint64_t c = base + threadIdx.x;
-    const uint64_t v = ((uint64_t)(uint32_t)c << 32) | (uint32_t)a.parts[i];
-    __hip_atomic_store(&a.dlist[c % a.capacity], v, __ATOMIC_RELEASE,
-                       __HIP_MEMORY_SCOPE_AGENT);
+// Appends the partitions `part` of the lanes with `want` set to the ready
+// ring of the signal's epoch.  Block-wide (256 threads, every thread calls
+// it).  Each partition first raises its stamp to the signal's epoch with an
+// atomic max: only the lane that moves it appends, so a partition enters a
+// ring at most once per epoch however often it is signalled (the ring never
+// overflows), and a signal of an older epoch than the stamp appends nothing.
+// Then one compare-and-swap reserves the block's entries, and only while
+// the ring's word carries the signal's epoch: the ring of an epoch that has
+// ended was reopened for a later one (or is about to be), and a late
+// signal must not count there.  Each entry is stored with a release atomic
+// max of (epoch << 32) | part, so a slot never goes back to an older
+// epoch's entry.
+__device__ __forceinline__ void ring_append(const RingArgs& a, bool want,
+                                            uint32_t part) {
+  __shared__ uint32_t wave_cnt[4];
+  __shared__ uint32_t base_sh;
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  if (want) {
+    const uint32_t old = __hip_atomic_fetch_max(
+        &a.dstamp[part], a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    want = old < a.epoch;
   }
+  const uint64_t m = __ballot(want);
+  if (lane == 0) wave_cnt[wave] = (uint32_t)__popcll(m);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t k = wave_cnt[0] + wave_cnt[1] + wave_cnt[2] + wave_cnt[3];
+    uint32_t base = ~0u;
+    if (k) {
+      RingCounters* rc = a.ring + (a.epoch & 1u);
+      uint64_t w = __hip_atomic_load(&rc->reserve, __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT);
+      // entries fit: each partition is appended once per epoch
+      while ((uint32_t)(w >> 32) == a.epoch &&
+             (uint64_t)(uint32_t)w + k <= a.capacity) {
+        if (__hip_atomic_compare_exchange_strong(
+                &rc->reserve, &w, w + k, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                __HIP_MEMORY_SCOPE_AGENT)) {
+          base = (uint32_t)w;
+          break;
+        }
+      }
+    }
+    base_sh = base;
+  }
+  __syncthreads();
+  const uint32_t base = base_sh;
+  if (want && base != ~0u) {
+    uint32_t c = base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+    for (uint32_t w = 0; w < wave; ++w) c += wave_cnt[w];
+    uint64_t* slot = a.dlist + (size_t)(a.epoch & 1u) * a.capacity + c;
+    __hip_atomic_fetch_max(slot, ((uint64_t)a.epoch << 32) | part,
+                           __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// Marks parts[0..n) ready in the signal's epoch; ids out of range are
+// ignored (they take no ring entry).
+__global__ __launch_bounds__(256) void pready_kernel(PreadyArgs a) {
+  const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+  const uint32_t part = i < a.n ? (uint32_t)a.parts[i] : ~0u;
+  ring_append(a.ring, part < a.ring.capacity, part);
 }
 
 hipError_t launch_pready(const PreadyArgs& a, hipStream_t s) {
@@ -72,50 +115,34 @@ hipError_t launch_pready(const PreadyArgs& a, hipStream_t s) {
 // epoch-tagged mask with a compare-and-swap (acquire-release: the ranks'
 // producers, ordered before their marks by their streams, are visible to
 // the lane whose mark completes the mask, which then publishes with a
-// release store).  Marks already set are idempotent, so a partition is
-// appended exactly once; the completing lanes of a wavefront reserve their
-// ring entries with one atomic.
+// release store).  A word of an older epoch counts as empty; a word of a
+// newer epoch is left alone (this mark's epoch has ended).  Marks already
+// set are idempotent, so a partition completes exactly once per epoch.
 __global__ __launch_bounds__(256) void pready_rank_kernel(PreadyRankArgs a) {
   const uint32_t i = blockIdx.x * 256u + threadIdx.x;
-  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t epoch = a.ring.epoch;
   bool done = false;
-  uint32_t part = 0;
-  if (i < a.n) {
-    part = (uint32_t)a.parts[i];
-    if (part < a.capacity) {
-      uint64_t* w = &a.rank_marks[part];
-      const uint64_t tag = (uint64_t)a.epoch << 32;
-      const uint64_t bit = 1ull << a.rank;
-      uint64_t old = __hip_atomic_load(w, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-      for (;;) {
-        const uint64_t cur = (old & ~0xffffffffull) == tag ? old : tag;
-        const uint64_t nw = cur | bit;
-        if (nw == old) break;  // this rank's mark is already in
-        if (__hip_atomic_compare_exchange_strong(
-                w, &old, nw, __ATOMIC_ACQ_REL, __ATOMIC_RELAXED,
-                __HIP_MEMORY_SCOPE_AGENT)) {
-          done = (uint32_t)nw == a.full && (uint32_t)cur != a.full;
-          break;
-        }
+  uint32_t part = i < a.n ? (uint32_t)a.parts[i] : ~0u;
+  if (part < a.ring.capacity) {
+    uint64_t* w = &a.rank_marks[part];
+    const uint64_t tag = (uint64_t)epoch << 32;
+    const uint64_t bit = 1ull << a.rank;
+    uint64_t old = __hip_atomic_load(w, __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT);
+    for (;;) {
+      if ((uint32_t)(old >> 32) > epoch) break;  // a newer epoch's marks
+      const uint64_t cur = (old & ~0xffffffffull) == tag ? old : tag;
+      const uint64_t nw = cur | bit;
+      if (nw == old) break;  // this rank's mark is already in
+      if (__hip_atomic_compare_exchange_strong(
+              w, &old, nw, __ATOMIC_ACQ_REL, __ATOMIC_RELAXED,
+              __HIP_MEMORY_SCOPE_AGENT)) {
+        done = (uint32_t)nw == a.full && (uint32_t)cur != a.full;
+        break;
       }
     }
   }
-  const uint64_t m = __ballot(done);
-  if (m == 0) return;
-  const uint32_t leader = (uint32_t)(__ffsll((long long)m) - 1);
-  uint64_t base = 0;
-  if (lane == leader)
-    base = __hip_atomic_fetch_add(&a.ring->dreserve,
-                                  (uint64_t)__popcll(m), __ATOMIC_RELAXED,
-                                  __HIP_MEMORY_SCOPE_AGENT);
-  base = __shfl(base, (int)leader);
-  if (done) {
-    const uint64_t c = base + __popcll(m & ((1ull << lane) - 1ull));
-    const uint64_t v = ((uint64_t)(uint32_t)c << 32) | part;
-    __hip_atomic_store(&a.dlist[c % a.capacity], v, __ATOMIC_RELEASE,
-                       __HIP_MEMORY_SCOPE_AGENT);
-  }
+  ring_append(a.ring, done, part);
 }
 
 hipError_t launch_pready_rank(const PreadyRankArgs& a, hipStream_t s) {
@@ -316,6 +343,135 @@ __global__ __launch_bounds__(256) void fill_kernel(uint4* dst, size_t nv,
     dev::st_stream(dst + i, val);
 }
 
+// The reduce's traffic without its protocol or arithmetic: reads P
+// streams of nv vectors and, with WRITE, stores their bitwise XOR to dst
+// (one write stream); without, each thread keeps the XOR and stores it only
+// if it matches a pattern the data never hold, so no load is dropped and
+// nothing is written.  U vectors per source in flight per lane.
+struct StreamSrcs {
+  const uint4* p[kMaxRanks];
+};
+
+template <int P, bool WRITE>
+__global__ __launch_bounds__(256) void stream_kernel(StreamSrcs s, uint4* dst,
+                                                     size_t nv) {
+  constexpr int U = P <= 2 ? 4 : (P <= 8 ? 2 : 1);
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint4 keep = make_uint4(0, 0, 0, 0);
+  for (; i + (U - 1) * stride < nv; i += U * stride) {
+    uint4 x[U][P];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int r = 0; r < P; ++r) x[u][r] = dev::ld_stream(s.p[r] + i + u * stride);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      uint4 a = x[u][0];
+#pragma unroll
+      for (int r = 1; r < P; ++r) {
+        a.x ^= x[u][r].x;
+        a.y ^= x[u][r].y;
+        a.z ^= x[u][r].z;
+        a.w ^= x[u][r].w;
+      }
+      if (WRITE) {
+        dev::st_stream(dst + i + u * stride, a);
+      } else {
+        keep.x ^= a.x;
+        keep.y += a.y;
+        keep.z ^= a.z;
+        keep.w += a.w;
+      }
+    }
+  }
+  for (; i < nv; i += stride) {
+    uint4 a = dev::ld_stream(s.p[0] + i);
+#pragma unroll
+    for (int r = 1; r < P; ++r) {
+      const uint4 b = dev::ld_stream(s.p[r] + i);
+      a.x ^= b.x;
+      a.y ^= b.y;
+      a.z ^= b.z;
+      a.w ^= b.w;
+    }
+    if (WRITE) {
+      dev::st_stream(dst + i, a);
+    } else {
+      keep.x ^= a.x;
+      keep.y += a.y;
+      keep.z ^= a.z;
+      keep.w += a.w;
+    }
+  }
+  if (!WRITE && keep.x == 0x9e3779b9u && keep.y == 0x7f4a7c15u &&
+      keep.z == 0xf39cc060u && keep.w == 0x5cedc834u)
+    dst[0] = keep;
+}
+
+// The same streams in the reduce's tile schedule, without its protocol:
+// the sources are cut into rows of 64 lanes x 16 bytes and tiles of
+// `tile_rows` rows laid out in bands of `band` tiles (dev::RowSet, as the
+// reduce lays out a partition); workgroup g takes tiles g, g + G, ... in
+// turn, its waves sharing each tile's rows (wave w takes rows w, w + W,
+// ...), 4 rows per lane in flight up to 8 sources.  No claims, no queue,
+// no completion: what is left of the reduce is its memory schedule.
+template <int P, bool WRITE>
+__global__ __launch_bounds__(512) void tile_stream_kernel(
+    StreamSrcs s, uint4* dst, uint32_t nrows, uint32_t tile_rows,
+    uint32_t band) {
+  constexpr int U = P <= 8 ? 4 : 1;
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  const uint32_t nwaves = blockDim.x >> 6;
+  const uint32_t nt = (nrows + tile_rows - 1) / tile_rows;
+  const uint32_t rpt = (nrows + nt - 1) / nt;
+  uint4 keep = make_uint4(0, 0, 0, 0);
+  auto combine = [&](const uint4(&x)[P], uint32_t v) {
+    uint4 a = x[0];
+#pragma unroll
+    for (int r = 1; r < P; ++r) {
+      a.x ^= x[r].x;
+      a.y ^= x[r].y;
+      a.z ^= x[r].z;
+      a.w ^= x[r].w;
+    }
+    if (WRITE) {
+      dev::st_stream(dst + v, a);
+    } else {
+      keep.x ^= a.x;
+      keep.y += a.y;
+      keep.z ^= a.z;
+      keep.w += a.w;
+    }
+  };
+  for (uint32_t t = blockIdx.x; t < nt; t += gridDim.x) {
+    const dev::RowSet rows(t, nt, rpt, band, nrows);
+    uint32_t k = wave;
+    for (; k + (U - 1) * nwaves < rows.limit; k += U * nwaves) {
+      uint4 x[U][P];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int r = 0; r < P; ++r)
+          x[u][r] = dev::ld_stream(s.p[r] + rows.row(k + u * nwaves) * 64u +
+                                   lane);
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        combine(x[u], rows.row(k + u * nwaves) * 64u + lane);
+    }
+    for (; k < rows.limit; k += nwaves) {
+      uint4 x[P];
+      const uint32_t v = rows.row(k) * 64u + lane;
+#pragma unroll
+      for (int r = 0; r < P; ++r) x[r] = dev::ld_stream(s.p[r] + v);
+      combine(x, v);
+    }
+  }
+  if (!WRITE && keep.x == 0x9e3779b9u && keep.y == 0x7f4a7c15u &&
+      keep.z == 0xf39cc060u && keep.w == 0x5cedc834u)
+    dst[0] = keep;
+}
+
 static unsigned probe_blocks(size_t nv) {
   size_t b = (nv + 255) / 256;
   if (b > 16384) b = 16384;
@@ -330,6 +486,50 @@ hipError_t launch_copy(void* dst, const void* src, size_t bytes,
                      static_cast<const uint4*>(src), static_cast<uint4*>(dst),
                      nv);
   return hipGetLastError();
+}
+
+template <bool WRITE>
+static hipError_t launch_stream_w(const StreamSrcs& srcs, int nsrc, uint4* dst,
+                                  size_t nv, const StreamTiles* t,
+                                  hipStream_t s) {
+#define PCOLL_STREAM_CASE(P)                                                \
+  case P:                                                                   \
+    if (t)                                                                  \
+      hipLaunchKernelGGL((tile_stream_kernel<P, WRITE>), dim3(t->groups),   \
+                         dim3(64 * t->waves), 0, s, srcs, dst,              \
+                         (uint32_t)(nv / 64), t->tile_rows, t->band);       \
+    else                                                                    \
+      hipLaunchKernelGGL((stream_kernel<P, WRITE>), dim3(probe_blocks(nv)), \
+                         dim3(256), 0, s, srcs, dst, nv);                   \
+    break;
+  switch (nsrc) {
+    PCOLL_STREAM_CASE(1)
+    PCOLL_STREAM_CASE(2)
+    PCOLL_STREAM_CASE(4)
+    PCOLL_STREAM_CASE(8)
+    PCOLL_STREAM_CASE(16)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef PCOLL_STREAM_CASE
+  return hipGetLastError();
+}
+
+hipError_t launch_stream(const void* const* srcs, int nsrc, void* dst,
+                         size_t bytes, bool write, const StreamTiles* tiles,
+                         hipStream_t s) {
+  if (nsrc < 1 || nsrc > kMaxRanks) return hipErrorInvalidValue;
+  const size_t nv = bytes / 16;
+  if (nv == 0) return hipSuccess;
+  // tile layout: whole rows, vector indexes below 2^32
+  if (tiles && (nv % 64 || nv > 0xffffffffu || tiles->groups < 1 ||
+                tiles->waves < 1 || tiles->waves > 8 || tiles->tile_rows < 1))
+    return hipErrorInvalidValue;
+  StreamSrcs a{};
+  for (int r = 0; r < nsrc; ++r) a.p[r] = static_cast<const uint4*>(srcs[r]);
+  uint4* d = static_cast<uint4*>(dst);
+  return write ? launch_stream_w<true>(a, nsrc, d, nv, tiles, s)
+               : launch_stream_w<false>(a, nsrc, d, nv, tiles, s);
 }
 
 hipError_t launch_fill(void* dst, size_t bytes, uint32_t value,

@@ -58,5 +58,14 @@ hipError_t launch_copy(void* dst, const void* src, size_t bytes,
                        hipStream_t s);
 hipError_t launch_fill(void* dst, size_t bytes, uint32_t value,
                        hipStream_t s);
+// The reduce's streams without its protocol: nsrc (1, 2, 4, 8 or 16) reads
+// of `bytes` each and, with `write`, one write of their XOR; grid-stride
+// (tiles = null) or in the reduce's tile schedule (whole 1 KiB rows).
+struct StreamTiles {
+  uint32_t groups, waves, tile_rows, band;
+};
+hipError_t launch_stream(const void* const* srcs, int nsrc, void* dst,
+                         size_t bytes, bool write, const StreamTiles* tiles,
+                         hipStream_t s);
 
 }  // namespace pcoll

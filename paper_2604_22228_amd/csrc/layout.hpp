@@ -76,18 +76,28 @@ struct EpochCounters {
   uint32_t ilock;                 // ingest lock (0 free, 1 held)
   uint32_t hconsumed;             // host ready entries already queued
   uint64_t queued_rows;           // rows of the partitions queued so far
-  uint32_t pad2[28];
+  uint32_t dconsumed;             // device ring entries already queued
+  uint32_t pad2[27];
   uint32_t error;                 // first error seen this epoch
   uint32_t pad3[31];
 };
 
-// Counters of the device ready ring, never cleared (they number its
-// entries across epochs, see ReduceArgs::dlist).
+// Device ready rings.  Device-side signals of epoch e append to ring e & 1
+// (slots dlist[(e & 1) * nparts_total ...]).  Its reservation word holds
+// (epoch << 32) | entries: a writer reserves with a compare-and-swap only
+// while the word carries the writer's own epoch, so a signal that runs
+// after its epoch ended (a wait_timeout ended it while the signal was still
+// queued behind its producer) reserves nothing in a later epoch's ring.
+// The launch of epoch e opens ring (e + 1) & 1 for epoch e + 1 by storing
+// ((e + 1) << 32) | 0 (the stream orders that launch before every signal
+// of epoch e + 1).  A slot holds (epoch << 32) | part, written with an
+// atomic max, so a late writer never overwrites a newer epoch's entry, and
+// a reader takes a slot as written only when it carries the reader's
+// epoch.  A partition is appended at most once per epoch (dstamp), so a
+// ring never holds more entries than partitions.
 struct RingCounters {
-  uint64_t dconsumed;             // device ready entries already queued
+  uint64_t reserve;               // (epoch << 32) | entries reserved
   uint32_t pad0[30];
-  uint64_t dreserve;              // device ready entries ever reserved
-  uint32_t pad1[30];
 };
 
 // Error codes a kernel can leave in HostShared::status.
@@ -106,11 +116,11 @@ struct ReduceArgs {
                           // partition, one half per epoch parity
   uint32_t* queued;       // [nparts_total] epoch stamp once queued
   uint32_t* tile_hits;    // [nparts_total] debug: tiles reduced, or null
-  uint64_t* dlist;        // [nparts_total] device ready ring: entry number
-                          // c lives in slot c % nparts_total as
-                          // ((uint32)c << 32) | part
+  uint64_t* dlist;        // [2][nparts_total] device ready rings, one per
+                          // epoch parity: entry c of epoch e's ring is slot
+                          // c, ((uint64)e << 32) | part once written
   EpochCounters* ctr;     // [2], one set per epoch parity
-  RingCounters* ring;
+  RingCounters* ring;     // [2], one per epoch parity
   HostShared* host;       // device-visible address of the host struct
   const uint64_t* hlist;  // device-visible host ready list: entry i of an
                           // epoch is ((uint64)epoch << 32) | part, so a
@@ -133,29 +143,38 @@ struct ReduceArgs {
   uint64_t timeout_ticks; // device wall-clock ticks before giving up
 };
 
+// Where a device-side ready signal appends: the rings of the request, and
+// the epoch the signal was enqueued in (fixed at enqueue time, so a signal
+// that runs late still names its own epoch).
+struct RingArgs {
+  uint64_t* dlist;        // [2][capacity]
+  RingCounters* ring;     // [2]
+  uint32_t* dstamp;       // [capacity] latest epoch each partition was
+                          // appended in (atomic max: once per epoch)
+  uint32_t capacity;      // partitions of the request
+  uint32_t epoch;
+};
+
 struct PreadyArgs {
   const int32_t* parts;   // device array of partition ids
   uint32_t n;
-  uint32_t capacity;      // slots in dlist (= partitions of the request)
-  uint64_t* dlist;
-  RingCounters* ring;
+  uint32_t reserved;
+  RingArgs ring;
 };
 
 // Per-rank readiness on the device: rank `rank` marks its contribution to
 // parts[0..n) in place.  rank_marks[p] = (epoch << 32) | mask of the ranks
-// that marked p in that epoch (a word of another epoch counts as empty);
-// the mark that completes the mask appends p to the ready ring.
+// that marked p in that epoch (a word of an older epoch counts as empty; a
+// mark never changes a word of a newer epoch); the mark that completes the
+// mask appends p to the ready ring.
 struct PreadyRankArgs {
   const int32_t* parts;
   uint32_t n;
-  uint32_t capacity;      // partitions of the request
   uint32_t rank;
-  uint32_t epoch;
   uint32_t full;          // mask of all ranks: (1 << nranks) - 1
   uint32_t reserved;
   uint64_t* rank_marks;   // [capacity]
-  uint64_t* dlist;
-  RingCounters* ring;
+  RingArgs ring;
 };
 
 

@@ -19,9 +19,9 @@
 //   2. wait until t is covered by the work queue.  While starved, the few
 //      workers at the front of the claim order try to move newly readied
 //      partitions into the queue: under a try-lock, read the host ready
-//      list (host-coherent memory, written by pready) and the device ready
-//      ring (written by the ready kernel), and append each partition not yet
-//      queued this epoch together with the running total of its tiles.
+//      list (host-coherent memory, written by pready) and this epoch's
+//      device ready ring (written by the ready kernels), and append each
+//      partition not yet queued this epoch together with the running total of its tiles.
 //      Partitions are reduced in the order they became ready (the chunk
 //      pipeline of Section 4.3: chunks proceed as soon as they can);
 //   3. find the queue entry covering t (64 entries per wave-wide probe),
@@ -187,6 +187,15 @@ __device__ __forceinline__ void queue_append(const ReduceArgs& a,
   qrows += uni(__shfl(rincl, 63));
 }
 
+// Entries reserved in this epoch's device ready ring (its word carries the
+// epoch from the previous launch on; a word of another epoch counts as
+// empty).
+__device__ __forceinline__ uint32_t ring_reserved(const ReduceArgs& a,
+                                                  uint32_t epoch) {
+  const uint64_t w = uni64(ld_rlx64(&a.ring[epoch & 1u].reserve));
+  return (uint32_t)(w >> 32) == epoch ? (uint32_t)w : 0u;
+}
+
 // Whether the ready lists may hold entries not yet queued: the host list's
 // next entry carries this epoch, or the device ring has reserved entries
 // beyond the consumed ones.  Relaxed reads, no lock: a stale answer only
@@ -205,8 +214,7 @@ __device__ __forceinline__ bool ready_lists_moved(const ReduceArgs& a,
     head = ld_rlx_sys64(&a.hlist[hcons]);
   if ((uint32_t)(uni64(head) >> 32) == epoch && hcons < a.nparts_total)
     return true;
-  return uni64(ld_rlx64(&a.ring->dreserve)) >
-         uni64(ld_rlx64(&a.ring->dconsumed));
+  return ring_reserved(a, epoch) > uni(ld_rlx(&c->dconsumed));
 }
 
 // Moves newly readied partitions into the queue.  Returns true if it queued
@@ -235,8 +243,8 @@ __device__ __forceinline__ bool try_ingest(const ReduceArgs& a, uint32_t epoch,
     return false;
   }
   uint32_t hcons = uni(ld_rlx(&c->hconsumed));
-  uint64_t dcons = uni64(ld_rlx64(&a.ring->dconsumed));
-  uint64_t dr = uni64(ld_rlx64(&a.ring->dreserve));
+  uint32_t dcons = uni(ld_rlx(&c->dconsumed));
+  uint32_t dr = ring_reserved(a, epoch);
   uint64_t qrows = uni64(ld_rlx64(&c->queued_rows));
   const uint32_t qtiles0 = qtiles;
 
@@ -268,7 +276,7 @@ __device__ __forceinline__ bool try_ingest(const ReduceArgs& a, uint32_t epoch,
     }
     if (prefix == 0u) {
       if (qtiles != qtiles0 || polls >= 7u) break;
-      dr = uni64(ld_rlx64(&a.ring->dreserve));
+      dr = ring_reserved(a, epoch);
       if (dr > dcons) break;
       __builtin_amdgcn_s_sleep(1);
       continue;
@@ -292,14 +300,15 @@ __device__ __forceinline__ bool try_ingest(const ReduceArgs& a, uint32_t epoch,
     polls = 8u;  // found entries: no more empty polls
   }
 
-  // device ready ring: entry c sits in slot c % nparts_total, stored as
-  // ((uint32)c << 32) | part; stop at the first reserved entry whose writer
-  // has not stored it yet (its slot still holds another tag)
+  // this epoch's device ready ring: entry c is slot c, stored as (epoch <<
+  // 32) | part; stop at the first reserved entry whose writer has not
+  // stored it yet (its slot still holds an older epoch's tag)
+  const uint64_t* ring = a.dlist + (size_t)(epoch & 1u) * a.nparts_total;
   while (dcons < dr) {
-    const uint64_t c = dcons + lane;
+    const uint32_t c = dcons + lane;
     const bool in = c < dr;
-    uint64_t v = in ? ld_rlx64(&a.dlist[c % a.nparts_total]) : 0ull;
-    const bool ok = in && (uint32_t)(v >> 32) == (uint32_t)c;
+    uint64_t v = in ? ld_rlx64(&ring[c]) : 0ull;
+    const bool ok = in && (uint32_t)(v >> 32) == epoch;
     const uint64_t pending = __ballot(in && !ok);
     const uint32_t lim =
         pending ? (uint32_t)(__ffsll((long long)pending) - 1) : 64u;
@@ -308,13 +317,13 @@ __device__ __forceinline__ bool try_ingest(const ReduceArgs& a, uint32_t epoch,
                                                             "agent");
     queue_append(a, queue_stamp(a, epoch, ok && lane < lim, (uint32_t)v),
                  qcount, qtiles, qrows);
-    const uint64_t avail = dr - dcons < 64u ? dr - dcons : 64u;
+    const uint32_t avail = dr - dcons < 64u ? dr - dcons : 64u;
     dcons += lim < avail ? lim : avail;
     if (pending) break;
   }
 
   st_rlx(&c->hconsumed, hcons);
-  st_rlx64(&a.ring->dconsumed, dcons);
+  st_rlx(&c->dconsumed, dcons);
   st_rlx64(&c->queued_rows, qrows);
   st_rel64(&c->qstate, ((uint64_t)qcount << 32) | qtiles);
   if (lane == 0) st_rel(&c->ilock, 0u);
@@ -512,11 +521,20 @@ struct TileJob {
   uint32_t nt;    // tiles of the partition
 };
 
+// The epoch after e (the host's rule: epoch 0 is never used, so after
+// 2^32 - 1 the count goes on at 2, which keeps the parity alternating).
+__device__ __forceinline__ uint32_t next_epoch(uint32_t e) {
+  return e + 1u == 0u ? 2u : e + 1u;
+}
+
 // Clears the counter set and done counters of the other epoch parity, for
-// the next launch: the previous launch, which used them, has retired (the
+// the next launch, and opens the other parity's device ready ring for the
+// next epoch: the previous launch, which used them, has retired (the
 // stream orders launches), and the next one starts only after this one.
 // Every workgroup clears its share of the done counters; workgroup 0 the
-// counter set.
+// counter set and the ring's reservation word.  A device-side signal of an
+// ended epoch that still tries to reserve in that ring then finds another
+// epoch in the word and appends nothing.
 __device__ __forceinline__ void clear_next_epoch(const ReduceArgs& args,
                                                  uint32_t epoch) {
   const uint32_t other = (epoch & 1u) ^ 1u;
@@ -531,7 +549,9 @@ __device__ __forceinline__ void clear_next_epoch(const ReduceArgs& args,
     st_rlx(&c->ilock, 0u);
     st_rlx(&c->hconsumed, 0u);
     st_rlx64(&c->queued_rows, 0ull);
+    st_rlx(&c->dconsumed, 0u);
     st_rlx(&c->error, 0u);
+    st_rlx64(&args.ring[other].reserve, (uint64_t)next_epoch(epoch) << 32);
   }
 }
 

@@ -142,7 +142,11 @@ struct pcoll_req_s {
   std::vector<PartDesc> parts;
   pcoll_config_t cfg{};
   uint64_t total_rows = 0;
-  int groups = 0;
+  int groups = 0;       // workgroups of the launch
+  int waves = 0;        // wavefronts per workgroup of the launch
+  bool deep = true;     // 4 rows in flight per lane (else 2)
+  bool device_signals = false;  // a device-side ready signal was enqueued
+  bool room_pending = false;    // ... and the launch does not leave room yet
   int cus = 0;
   int clock_khz = 0;
 
@@ -158,10 +162,11 @@ struct pcoll_req_s {
   uint32_t* d_queued = nullptr;
   uint32_t* d_hits = nullptr;
   uint32_t* d_tiles = nullptr;
-  uint64_t* d_dlist = nullptr;
+  uint64_t* d_dlist = nullptr;       // [2][partitions] device ready rings
+  uint32_t* d_dstamp = nullptr;      // [partitions] last epoch appended
   uint64_t* d_rank_marks = nullptr;  // [partitions] device per-rank marks
   EpochCounters* d_ctr = nullptr;  // [2]
-  RingCounters* d_ring = nullptr;
+  RingCounters* d_ring = nullptr;  // [2]
 
   hipStream_t stream = nullptr;
   hipStream_t launch_stream = nullptr;  // stream of the last launch
@@ -196,6 +201,55 @@ int drain(pcoll_req_t r) {
   return PCOLL_SUCCESS;
 }
 
+// The epoch after e: epoch 0 is never used (it tells a kernel to read the
+// stamp from host memory), so after 2^32 - 1 the count goes on at 2, which
+// keeps the parity alternating.  The kernel's next_epoch() is the same rule.
+uint32_t epoch_after(uint32_t e) { return e + 1u == 0u ? 2u : e + 1u; }
+
+// Opens the device ready rings for epochs `next` and the one after.
+int open_rings(pcoll_req_t r, uint32_t next) {
+  RingCounters rc[2];
+  std::memset(rc, 0, sizeof(rc));
+  const uint32_t after = epoch_after(next);
+  rc[next & 1u].reserve = (uint64_t)next << 32;
+  rc[after & 1u].reserve = (uint64_t)after << 32;
+  HIP_TRY(hipMemcpy(r->d_ring, rc, sizeof(rc), hipMemcpyHostToDevice));
+  return PCOLL_SUCCESS;
+}
+
+// Clears every epoch stamp of the request, so that the epoch after `last`
+// starts from a clean slate: the device's queued stamps, ready rings,
+// partition stamps, per-rank marks, counter sets and done counters, and the
+// host's ready list, arrived flags, status and readiness bookkeeping.  Stamps are compared with the
+// current epoch for equality (and the device's ready state by magnitude),
+// so once the 32-bit count wraps, a stamp left from 2^32 epochs earlier
+// could pass for a current one.  Waits for the whole device first: a
+// device-side ready signal of an ended epoch may still be queued on some
+// stream, and must not run after the clear.
+int reset_epoch_state(pcoll_req_t r, uint32_t last) {
+  HIP_TRY(hipDeviceSynchronize());
+  const size_t np = r->nparts_total;
+  HIP_TRY(hipMemset(r->d_queued, 0, sizeof(uint32_t) * np));
+  HIP_TRY(hipMemset(r->d_dlist, 0, sizeof(uint64_t) * 2 * np));
+  HIP_TRY(hipMemset(r->d_dstamp, 0, sizeof(uint32_t) * np));
+  HIP_TRY(hipMemset(r->d_rank_marks, 0, sizeof(uint64_t) * np));
+  // both counter sets and done halves: the next epoch's parity may be the
+  // one the last launch used
+  HIP_TRY(hipMemset(r->d_ctr, 0, 2 * sizeof(EpochCounters)));
+  HIP_TRY(hipMemset(r->d_done, 0, sizeof(uint32_t) * 2 * np));
+  std::memset(r->hlist, 0, sizeof(uint64_t) * np);
+  std::memset(r->arrived, 0, sizeof(uint32_t) * np);
+  r->host->status = 0;
+  r->host->status_epoch = 0;
+  std::fill(r->stamp.begin(), r->stamp.end(), 0u);
+  std::fill(r->rank_epoch.begin(), r->rank_epoch.end(), 0u);
+  std::fill(r->rank_mask.begin(), r->rank_mask.end(), 0u);
+  const int rc = open_rings(r, epoch_after(last));
+  if (rc) return rc;
+  r->epoch = last;
+  return PCOLL_SUCCESS;
+}
+
 void dispose_binding(Binding& b) {
   if (b.exec) (void)hipGraphExecDestroy(b.exec);
   if (b.table) (void)hipFree(b.table);
@@ -210,9 +264,9 @@ uint64_t launch_signature(const pcoll_req_s* r) {
                         (uint64_t)r->cfg.comp, (uint64_t)r->cfg.debug,
                         (uint64_t)r->cfg.timeout_ms, r->total_rows,
                         (uint64_t)r->cfg.interleave, (uint64_t)r->cfg.guide,
-                        (uint64_t)r->cfg.group_waves,
+                        (uint64_t)r->waves,
                         (uint64_t)r->cfg.publish_batch,
-                        (uint64_t)r->cfg.unroll};
+                        (uint64_t)r->deep};
   for (uint64_t x : v) {
     h ^= x;
     h *= 1099511628211ull;
@@ -243,7 +297,15 @@ int validate_config(const pcoll_req_s* r, const pcoll_config_t& c) {
     return PCOLL_ERR_ARG;
   if (c.publish_batch < 1 || c.publish_batch > kMaxPublishBatch)
     return PCOLL_ERR_ARG;
+  if (c.producers < -1 || c.producers > 1) return PCOLL_ERR_ARG;
   return PCOLL_SUCCESS;
+}
+
+// Whether the launch leaves room for kernels that run beside it (the
+// producers that device-side readiness follows): explicitly, or, in the
+// automatic mode, once the request has seen a device-side signal.
+bool producer_room(const pcoll_req_s* r, const pcoll_config_t& c) {
+  return c.producers == 1 || (c.producers == -1 && r->device_signals);
 }
 
 // Elements per row: 64 lanes x 16 bytes per rank.
@@ -253,7 +315,14 @@ uint64_t row_elems(int dtype) { return 1024u / (uint64_t)elem_bytes(dtype); }
 int apply_config(pcoll_req_t r, const pcoll_config_t& c) {
   int rc = validate_config(r, c);
   if (rc) return rc;
-  int groups = c.groups ? c.groups : c.groups_per_cu * r->cus;
+  // Producer room: one resident wave per SIMD (one workgroup of at most 4
+  // waves per compute unit, unless the workgroup count is given) and 2
+  // rows in flight per lane (about 115 instead of 160-190 VGPRs per wave
+  // at 8 ranks), so that producer waves, matrix-core ones included, find
+  // registers and wave slots beside the resident kernel.
+  const bool room = producer_room(r, c);
+  const int waves = room ? std::min(c.group_waves, 4) : c.group_waves;
+  int groups = c.groups ? c.groups : (room ? 1 : c.groups_per_cu) * r->cus;
   // No more workgroups than the launch has tiles for sure: every partition
   // has at least max(1, ceil(rows / largest tile)) tiles in any mode.  So
   // every workgroup owns a first tile (its own number), a small message
@@ -273,6 +342,9 @@ int apply_config(pcoll_req_t r, const pcoll_config_t& c) {
   if (rc) return rc;
   r->cfg = c;
   r->groups = groups;
+  r->waves = waves;
+  r->deep = !room && c.unroll != 2;
+  r->room_pending = false;
   r->sig = launch_signature(r);
   if (r->cache)  // graphs captured with the old arguments are stale
     r->cache->for_each([](const BindKey&, Binding& b) {
@@ -309,6 +381,8 @@ pcoll_config_t default_config(const pcoll_req_s* r) {
   c.comp = float_sum && comp ? 1 : 0;
   c.timeout_ms = env_int("PCOLL_TIMEOUT_MS", 10000);
   c.debug = env_int("PCOLL_DEBUG", 0) ? 1 : 0;
+  c.producers = env_int("PCOLL_PRODUCERS", -1);
+  if (c.producers < -1 || c.producers > 1) c.producers = -1;
   return c;
 }
 
@@ -407,17 +481,15 @@ int create(const std::vector<uint64_t>& counts, int dtype, int op,
   const size_t o_queued = take(sizeof(uint32_t) * np_total);
   const size_t o_hits = take(sizeof(uint32_t) * np_total);
   const size_t o_tiles = take(sizeof(uint32_t) * np_total);
-  const size_t o_dlist = take(sizeof(uint64_t) * np_total);
+  const size_t o_dlist = take(sizeof(uint64_t) * 2 * np_total);
+  const size_t o_dstamp = take(sizeof(uint32_t) * np_total);
   const size_t o_marks = take(sizeof(uint64_t) * np_total);
   const size_t o_ctr = take(2 * sizeof(EpochCounters));
-  const size_t o_ring = take(sizeof(RingCounters));
+  const size_t o_ring = take(2 * sizeof(RingCounters));
   e = hipMalloc(&r->arena, off);
   if (e != hipSuccess) return e == hipErrorOutOfMemory ? PCOLL_ERR_NOMEM
                                                        : hip_fail(e, "hipMalloc");
   HIP_TRY(hipMemset(r->arena, 0, off));
-  // ring slots start with a tag no entry number below 2^32 - 1 carries
-  HIP_TRY(hipMemset(static_cast<char*>(r->arena) + o_dlist, 0xff,
-                    sizeof(uint64_t) * np_total));
   char* base = static_cast<char*>(r->arena);
   r->d_parts = reinterpret_cast<PartDesc*>(base + o_parts);
   r->d_queue = reinterpret_cast<QEntry*>(base + o_queue);
@@ -429,9 +501,16 @@ int create(const std::vector<uint64_t>& counts, int dtype, int op,
                     sizeof(PartDesc) * r->parts.size(),
                     hipMemcpyHostToDevice));
   r->d_dlist = reinterpret_cast<uint64_t*>(base + o_dlist);
+  r->d_dstamp = reinterpret_cast<uint32_t*>(base + o_dstamp);
   r->d_rank_marks = reinterpret_cast<uint64_t*>(base + o_marks);
   r->d_ctr = reinterpret_cast<EpochCounters*>(base + o_ctr);
   r->d_ring = reinterpret_cast<RingCounters*>(base + o_ring);
+  // epoch stamps start at 0 (no epoch): slots, partition stamps and marks
+  // are zero; the rings are open for epochs 1 and 2
+  {
+    const int rc = open_rings(r.get(), 1u);
+    if (rc) return rc;
+  }
 
   HIP_TRY(hipStreamCreateWithFlags(&r->capture_stream, hipStreamNonBlocking));
   HIP_TRY(hipEventCreateWithFlags(&r->ev_end, hipEventDefault));
@@ -485,10 +564,20 @@ ReduceArgs make_args(const pcoll_req_s* r) {
 int launch_direct(pcoll_req_t r, hipStream_t s, uint32_t epoch) {
   ReduceArgs a = make_args(r);
   a.epoch = epoch;
-  HIP_TRY(launch_reduce(a, r->dtype, r->op, r->cfg.comp != 0,
-                        r->cfg.unroll != 2, r->nranks, r->groups,
-                        r->cfg.group_waves, s));
+  HIP_TRY(launch_reduce(a, r->dtype, r->op, r->cfg.comp != 0, r->deep,
+                        r->nranks, r->groups, r->waves, s));
   return PCOLL_SUCCESS;
+}
+
+// Hands the work enqueued on `s` to the device now.  The HIP runtime may
+// hold launches back until the host next looks at their stream (measured
+// on MI355X: kernels enqueued on a stream stayed unsubmitted for 100 ms,
+// and ran within microseconds of a query); a device-side ready signal held
+// back that way would never run while the host waits on pinned memory, so
+// every launch the host does not wait for is followed by a query.
+hipError_t submit(hipStream_t s) {
+  const hipError_t e = hipStreamQuery(s);
+  return e == hipErrorNotReady ? hipSuccess : e;
 }
 
 double ms_since(std::chrono::steady_clock::time_point t0) {
@@ -648,7 +737,7 @@ const char* pcoll_strerror(int code) {
   }
 }
 
-int pcoll_plan(size_t count, int dtype, int nparts, size_t* psize,
+int pcoll_plan(size_t count, pcoll_dtype_t dtype, int nparts, size_t* psize,
                size_t* offsets, size_t* lengths) {
   if (!valid_dtype(dtype) || nparts < 1 || !psize) return PCOLL_ERR_ARG;
   const uint64_t ps = plan_psize(count, (uint64_t)nparts, part_align(dtype));
@@ -661,10 +750,11 @@ int pcoll_plan(size_t count, int dtype, int nparts, size_t* psize,
   return PCOLL_SUCCESS;
 }
 
-int pcoll_init(size_t count, int dtype, int op, int nparts, int nranks,
-               pcoll_req_t* out) {
+int pcoll_init(size_t count, pcoll_dtype_t dtype, pcoll_op_t op, int nparts,
+               int nranks, pcoll_req_t* out) {
   try {
-    return create({(uint64_t)count}, dtype, op, nparts, nranks, out);
+    return create({(uint64_t)count}, (int)dtype, (int)op, nparts, nranks,
+                  out);
   } catch (const std::bad_alloc&) {
     return PCOLL_ERR_NOMEM;
   } catch (...) {
@@ -672,12 +762,15 @@ int pcoll_init(size_t count, int dtype, int op, int nparts, int nranks,
   }
 }
 
-int pcoll_init_batch(int nbuckets, const size_t* counts, int dtype, int op,
-                     int nparts_per_bucket, int nranks, pcoll_req_t* out) {
+int pcoll_init_batch(int nbuckets, const size_t* counts, pcoll_dtype_t dtype,
+                     pcoll_op_t op, int nparts_per_bucket, int nranks,
+                     pcoll_req_t* out) {
+  if (!out) return PCOLL_ERR_ARG;
+  *out = nullptr;
   if (nbuckets < 1 || !counts) return PCOLL_ERR_ARG;
   try {
     std::vector<uint64_t> c(counts, counts + nbuckets);
-    return create(c, dtype, op, nparts_per_bucket, nranks, out);
+    return create(c, (int)dtype, (int)op, nparts_per_bucket, nranks, out);
   } catch (const std::bad_alloc&) {
     return PCOLL_ERR_NOMEM;
   } catch (...) {
@@ -776,9 +869,19 @@ int pcoll_start(pcoll_req_t r) {
   if (!r->bound || r->active) return PCOLL_ERR_STATE;
   HIP_TRY(hipSetDevice(r->device));
   // epoch 0 means "read the stamp from host memory" to the kernel, and the
-  // counter sets alternate by parity: after wrapping, continue at 2
-  uint32_t e = r->epoch + 1;
-  if (e == 0) e = 2;
+  // counter sets alternate by parity: after wrapping, continue at 2, from
+  // cleared stamps
+  // the first device-side signal of a request in the automatic producer
+  // mode: leave room from this launch on
+  if (r->room_pending) {
+    const int rc = apply_config(r, r->cfg);
+    if (rc) return rc;
+  }
+  const uint32_t e = epoch_after(r->epoch);
+  if (e < r->epoch) {
+    const int rc = reset_epoch_state(r, r->epoch);
+    if (rc) return rc;
+  }
   // the previous launch may still be draining (its epoch completes when
   // every partition has arrived): a launch on another stream must follow it
   if (r->ev_end_recorded && r->launch_stream != r->stream)
@@ -801,6 +904,9 @@ int pcoll_start(pcoll_req_t r) {
   int rc = r->cfg.graph ? launch_graph(r) : launch_direct(r, r->stream, e);
   if (rc) return rc;
   HIP_TRY(hipEventRecord(r->ev_end, r->stream));
+  // the kernel starts now, not when the host next looks at the stream: it
+  // then runs while the host issues the epoch's ready signals
+  HIP_TRY(submit(r->stream));
   r->ev_end_recorded = true;
   r->launch_stream = r->stream;
   r->epoch = e;
@@ -808,7 +914,29 @@ int pcoll_start(pcoll_req_t r) {
   r->epoch_ok = false;
   r->stats.epochs++;
   r->stats.groups = r->groups;
+  r->stats.group_waves = r->waves;
+  r->stats.unroll = r->deep ? 4 : 2;
   return PCOLL_SUCCESS;
+}
+
+// A device-side signal was enqueued: in the automatic producer mode, the
+// next launch leaves room for producers (this epoch's kernel is running).
+static void note_device_signal(pcoll_req_t r) {
+  if (!r->device_signals) {
+    r->device_signals = true;
+    r->room_pending = r->cfg.producers == -1;
+  }
+}
+
+// Where the device-side signals of the current epoch append.
+static RingArgs ring_args(const pcoll_req_s* r) {
+  RingArgs a{};
+  a.dlist = r->d_dlist;
+  a.ring = r->d_ring;
+  a.dstamp = r->d_dstamp;
+  a.capacity = r->nparts_total;
+  a.epoch = r->epoch;
+  return a;
 }
 
 static int publish_ready(pcoll_req_t r, const int* parts, int n, int first) {
@@ -892,14 +1020,13 @@ int pcoll_pready_rank_on_stream(pcoll_req_t r, int rank, const int* parts_dev,
   PreadyRankArgs a{};
   a.parts = parts_dev;
   a.n = (uint32_t)n;
-  a.capacity = r->nparts_total;
   a.rank = (uint32_t)rank;
-  a.epoch = r->epoch;
   a.full = (1u << r->nranks) - 1u;
   a.rank_marks = r->d_rank_marks;
-  a.dlist = r->d_dlist;
-  a.ring = r->d_ring;
+  a.ring = ring_args(r);
   HIP_TRY(launch_pready_rank(a, static_cast<hipStream_t>(stream)));
+  HIP_TRY(submit(static_cast<hipStream_t>(stream)));
+  note_device_signal(r);
   return PCOLL_SUCCESS;
 }
 
@@ -924,10 +1051,10 @@ int pcoll_pready_on_stream(pcoll_req_t r, const int* parts_dev, int n,
   PreadyArgs a{};
   a.parts = parts_dev;
   a.n = (uint32_t)n;
-  a.capacity = r->nparts_total;
-  a.dlist = r->d_dlist;
-  a.ring = r->d_ring;
+  a.ring = ring_args(r);
   HIP_TRY(launch_pready(a, static_cast<hipStream_t>(stream)));
+  HIP_TRY(submit(static_cast<hipStream_t>(stream)));
+  note_device_signal(r);
   return PCOLL_SUCCESS;
 }
 
@@ -1027,6 +1154,13 @@ int pcoll_get_stats(pcoll_req_t r, pcoll_stats_t* st) {
   return PCOLL_SUCCESS;
 }
 
+int pcoll_debug_set_epoch(pcoll_req_t r, uint32_t last) {
+  if (check_req(r)) return PCOLL_ERR_ARG;
+  if (r->active) return PCOLL_ERR_STATE;
+  HIP_TRY(hipSetDevice(r->device));
+  return reset_epoch_state(r, last);
+}
+
 int pcoll_debug_tile_hits(pcoll_req_t r, uint32_t* hits, uint32_t* tiles,
                           int n) {
   if (check_req(r) || !hits || !tiles || n < (int)r->nparts_total)
@@ -1084,6 +1218,36 @@ int pcoll_probe_copy(void* dst, const void* src, size_t bytes, void* stream) {
                                ((uintptr_t)dst & 15u))))
     return PCOLL_ERR_ARG;
   HIP_TRY(launch_copy(dst, src, bytes, static_cast<hipStream_t>(stream)));
+  return PCOLL_SUCCESS;
+}
+
+int pcoll_probe_stream(const void* const* srcs, int nsrc, void* dst,
+                       size_t bytes, int write, int layout, void* stream) {
+  if (!srcs || (nsrc != 1 && nsrc != 2 && nsrc != 4 && nsrc != 8 &&
+                nsrc != 16) ||
+      (write != 0 && write != 1) || (layout != 0 && layout != 1) ||
+      bytes % (layout ? 1024 : 16) || (layout && bytes > (1ull << 36)) ||
+      !dst ||
+      ((uintptr_t)dst & 15u))
+    return PCOLL_ERR_ARG;
+  for (int r = 0; r < nsrc; ++r)
+    if (bytes && (!srcs[r] || ((uintptr_t)srcs[r] & 15u))) return PCOLL_ERR_ARG;
+  StreamTiles t{};
+  if (layout) {
+    // the headline reduce's launch: 2 workgroups of 8 waves per compute
+    // unit, tiles of 32 rows (8192 binary32 elements), bands of 16 tiles
+    int dev = 0, cus = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
+                                  dev));
+    t.groups = (uint32_t)(2 * std::max(cus, 1));
+    t.waves = 8;
+    t.tile_rows = 32;
+    t.band = 16;
+  }
+  HIP_TRY(launch_stream(srcs, nsrc, dst, bytes, write != 0,
+                        layout ? &t : nullptr,
+                        static_cast<hipStream_t>(stream)));
   return PCOLL_SUCCESS;
 }
 

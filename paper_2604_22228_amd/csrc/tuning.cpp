@@ -98,7 +98,9 @@ TuneChoice tune_lookup(const std::vector<TuneRow>& rows, int dtype, int op,
               r.publish_batch};
   }
   // built-in default: 16 KiB of output per tile, two groups per CU
-  int elem = dtype == 2 ? 2 : (dtype >= 3 ? 1 : 4);
+  // (element bytes: 2 for bf16 and bf16 pairs, 1 for the 8-bit floats)
+  const int elem = dtype == 2 || dtype == 6 ? 2
+                                            : (dtype >= 3 && dtype <= 5 ? 1 : 4);
   return {16384 / elem, 2, 0, 4, 16};
 }
 

@@ -42,7 +42,8 @@ class Config(C.Structure):
                 ("graph", C.c_int), ("timeout_ms", C.c_int),
                 ("debug", C.c_int), ("interleave", C.c_int),
                 ("group_waves", C.c_int), ("publish_batch", C.c_int),
-                ("guide", C.c_int), ("unroll", C.c_int)]
+                ("guide", C.c_int), ("unroll", C.c_int),
+                ("producers", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -56,7 +57,7 @@ class Stats(C.Structure):
                 ("last_capture_ms", C.c_double),
                 ("last_instantiate_ms", C.c_double),
                 ("last_kernel_ms", C.c_float), ("groups", C.c_int),
-                ("reserved", C.c_int)]
+                ("group_waves", C.c_int), ("unroll", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -91,6 +92,7 @@ _SIGS = {
     "pcoll_get_stats": [_p, C.POINTER(Stats)],
     "pcoll_debug_tile_hits": [_p, C.POINTER(C.c_uint32),
                               C.POINTER(C.c_uint32), _i],
+    "pcoll_debug_set_epoch": [_p, C.c_uint32],
     "pcoll_plan": [_sz, _i, _i, C.POINTER(_sz), C.POINTER(_sz),
                    C.POINTER(_sz)],
     "pcoll_pack_bf16": [_p, _p, _sz, _p],
@@ -99,6 +101,7 @@ _SIGS = {
     "pcoll_pack_mxfp8": [_p, _p, _p, _sz, _p],
     "pcoll_probe_copy": [_p, _p, _sz, _p],
     "pcoll_probe_fill": [_p, _sz, C.c_uint32, _p],
+    "pcoll_probe_stream": [C.POINTER(_p), _i, _p, _sz, _i, _i, _p],
     "pcoll_device_info": [C.POINTER(_i), C.POINTER(_i), C.c_char_p, _i],
     "pcoll_version": [],
 }
@@ -292,6 +295,10 @@ def pcoll_debug_tile_hits(h, n):
     return list(hits), list(tiles)
 
 
+def pcoll_debug_set_epoch(h, last):
+    _check(load().pcoll_debug_set_epoch(h, last), "pcoll_debug_set_epoch")
+
+
 def pcoll_plan(count, dtype, nparts):
     ps = _sz()
     offs = (_sz * nparts)()
@@ -326,6 +333,13 @@ def pcoll_pack_mxfp8(src, dst, scales, n, stream=None):
 def pcoll_probe_copy(dst, src, nbytes, stream=None):
     _check(load().pcoll_probe_copy(_ptr(dst), _ptr(src), nbytes,
                                    _stream(stream)), "pcoll_probe_copy")
+
+
+def pcoll_probe_stream(srcs, dst, nbytes, write, layout=0, stream=None):
+    arr = (_p * len(srcs))(*[_ptr(s) for s in srcs])
+    _check(load().pcoll_probe_stream(arr, len(srcs), _ptr(dst), nbytes,
+                                     int(write), int(layout), _stream(stream)),
+           "pcoll_probe_stream")
 
 
 def pcoll_probe_fill(dst, nbytes, value, stream=None):
@@ -439,6 +453,9 @@ class Request:
 
     def tile_hits(self):
         return pcoll_debug_tile_hits(self.h, self.nparts_total)
+
+    def debug_set_epoch(self, last):
+        pcoll_debug_set_epoch(self.h, last)
 
     def free(self):
         if self.h is not None:

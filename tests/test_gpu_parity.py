@@ -18,6 +18,7 @@ from _metrics import normalized_error
 from oracle import get as get_oracle
 from paper_2604_22228_amd import pcoll as pc
 from paper_2604_22228_amd import synth
+from paper_2604_22228_amd.streams import independent_streams
 
 pytestmark = pytest.mark.gpu
 
@@ -142,7 +143,7 @@ def test_partitions_arrive_before_the_epoch_ends(orc, stream):
                       publish_batch=64)
     req.bind([[x.to(DEV) for x in xs]], [out], stream=stream)
     want = as_u32(orc.sum_f32_f32([x.numpy() for x in xs]))
-    side = torch.cuda.Stream(DEV)
+    side = independent_streams(stream, 1)[0]  # runs beside the kernel
     first = [5, 0, 3, 6]
     req.start()
     req.pready_list(first)
@@ -386,7 +387,7 @@ def test_pready_on_stream(orc, stream):
     xs = synth.normal_f32(P, n, 91)
     out = torch.empty(n, device=DEV)
     req = new_request([n], pc.FLOAT32, pc.SUM, nparts, P)
-    side = torch.cuda.Stream(DEV)
+    side = independent_streams(stream, 1)[0]
     req.bind([[x.to(DEV) for x in xs]], [out], stream=stream)
     parts = torch.tensor(synth.permutation(nparts, 91), dtype=torch.int32,
                          device=DEV)
