@@ -390,6 +390,37 @@ int pcoll_get_config(pcoll_req_t req, pcoll_config_t *cfg);
  * range give PCOLL_ERR_ARG and leave the request unchanged. */
 int pcoll_set_config(pcoll_req_t req, const pcoll_config_t *cfg);
 
+/* ------------------------------------------------- allocation-free epoch */
+
+/* Most partitions pcoll_reduce_noalloc takes (its scratch array is fixed:
+ * 512 KiB per device, 80 bytes per partition). */
+#define PCOLL_NOALLOC_MAX_PARTS 4096
+
+/* For callers that cannot allocate (code under HIP graph capture, serving
+ * loops that must not call hipMalloc): one epoch of the request path for a
+ * single message -- pcoll_init, pcoll_bind, pcoll_start, every partition
+ * readied at once, and completion on `stream` -- with the same results,
+ * enqueued on `stream` without allocating anything (no hipMalloc, no pinned
+ * host memory, no events).  The partition table, bucket descriptor, work
+ * queue, counters and ready list live in a file-scope device array of
+ * 512 KiB that each device holds until the process ends; a set-up kernel
+ * rewrites what must start at zero before the reduce kernel runs.  Calls on
+ * one device share that array: calls that overlap on one device (two
+ * streams, or two threads) race and must be serialized by the caller.
+ * The output is final once `stream` has passed the call; nothing is
+ * waited for on the host.  Arguments as pcoll_init (count, dtype, op,
+ * nparts, nranks) and pcoll_bind for one bucket (rank_bufs: nranks device
+ * pointers; out; rank_scales / out_scale for the 8-bit floats, the lo
+ * array as out_scale for bf16 pairs); the launch configuration is the
+ * tuned default (and the PCOLL_* environment).  PCOLL_ERR_UNSUPPORTED for
+ * more than PCOLL_NOALLOC_MAX_PARTS partitions; other errors as pcoll_init
+ * and pcoll_bind.  The first call on a device looks the array's address
+ * up (and reads the tuned table once per process). */
+int pcoll_reduce_noalloc(size_t count, pcoll_dtype_t dtype, pcoll_op_t op,
+                         int nparts, int nranks, const void *const *rank_bufs,
+                         void *out, const void *const *rank_scales,
+                         void *out_scale, void *stream);
+
 /* ----------------------------------------------------------- inspection */
 
 /* Partitions of the request (nbuckets * nparts). */

@@ -25,7 +25,7 @@ ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 HIP_SOURCES = ["reduce_f32.hip", "reduce_i32.hip", "reduce_bf16.hip",
                "reduce_e4m3.hip", "reduce_e5m2.hip", "reduce_mx.hip",
-               "aux.hip"]
+               "aux.hip", "noalloc.hip"]
 CPP_SOURCES = ["runtime.cpp", "tuning.cpp"]
 
 HIPCC_FLAGS = [

@@ -36,7 +36,11 @@
 #include "kernels.hpp"
 #include "layout.hpp"
 #include "lru_cache.hpp"
+#include "noalloc.hpp"
 #include "pcoll.h"
+
+static_assert(pcoll::kNoallocMaxParts == PCOLL_NOALLOC_MAX_PARTS,
+              "the header states the scratch array's partition limit");
 #include "tuning.hpp"
 
 using namespace pcoll;
@@ -311,6 +315,25 @@ bool producer_room(const pcoll_req_s* r, const pcoll_config_t& c) {
 // Elements per row: 64 lanes x 16 bytes per rank.
 uint64_t row_elems(int dtype) { return 1024u / (uint64_t)elem_bytes(dtype); }
 
+// Workgroups of a launch: the configured count, but no more than the
+// launch has tiles for sure (every partition has at least max(1,
+// ceil(rows / largest tile)) tiles), so that every workgroup owns a first
+// tile.  `rows_of(k)` gives the rows of partition k.
+template <class RowsOf>
+int launch_groups(const pcoll_config_t& c, int cus, int dtype, uint32_t np,
+                  RowsOf rows_of) {
+  int groups = c.groups ? c.groups : c.groups_per_cu * cus;
+  const uint64_t tile_rows =
+      std::max<uint64_t>(1, (uint64_t)c.tile_elems / row_elems(dtype));
+  uint64_t max_tiles = 0;
+  for (uint32_t k = 0; k < np; ++k) {
+    const uint64_t rows = rows_of(k);
+    max_tiles += rows ? (rows + tile_rows - 1) / tile_rows : 1;
+  }
+  if ((uint64_t)groups > max_tiles) groups = (int)max_tiles;
+  return groups < 1 ? 1 : groups;
+}
+
 // Applies a configuration: workgroups and the signature of the launch.
 int apply_config(pcoll_req_t r, const pcoll_config_t& c) {
   int rc = validate_config(r, c);
@@ -322,22 +345,17 @@ int apply_config(pcoll_req_t r, const pcoll_config_t& c) {
   // registers and wave slots beside the resident kernel.
   const bool room = producer_room(r, c);
   const int waves = room ? std::min(c.group_waves, 4) : c.group_waves;
-  int groups = c.groups ? c.groups : (room ? 1 : c.groups_per_cu) * r->cus;
-  // No more workgroups than the launch has tiles for sure: every partition
-  // has at least max(1, ceil(rows / largest tile)) tiles in any mode.  So
-  // every workgroup owns a first tile (its own number), a small message
-  // does not dispatch workers that would only wait, and an epoch cannot
-  // complete before every workgroup of its launch has started; a graph
-  // replay, whose workgroups read the epoch stamp from host memory when
-  // they start, depends on that (the host writes the next stamp only
-  // after the epoch completed).
-  const uint64_t tile_rows =
-      std::max<uint64_t>(1, (uint64_t)c.tile_elems / row_elems(r->dtype));
-  uint64_t max_tiles = 0;
-  for (const PartDesc& p : r->parts)
-    max_tiles += p.rows ? (p.rows + tile_rows - 1) / tile_rows : 1;
-  if ((uint64_t)groups > max_tiles) groups = (int)max_tiles;
-  if (groups < 1) groups = 1;
+  pcoll_config_t eff = c;
+  if (room && !c.groups) eff.groups_per_cu = 1;
+  // No more workgroups than the launch has tiles for sure.  So every
+  // workgroup owns a first tile (its own number), a small message does not
+  // dispatch workers that would only wait, and an epoch cannot complete
+  // before every workgroup of its launch has started; a graph replay,
+  // whose workgroups read the epoch stamp from host memory when they
+  // start, depends on that (the host writes the next stamp only after the
+  // epoch completed).
+  const int groups = launch_groups(eff, r->cus, r->dtype, r->nparts_total,
+                                   [&](uint32_t k) { return r->parts[k].rows; });
   rc = drain(r);
   if (rc) return rc;
   r->cfg = c;
@@ -354,15 +372,14 @@ int apply_config(pcoll_req_t r, const pcoll_config_t& c) {
   return PCOLL_SUCCESS;
 }
 
-pcoll_config_t default_config(const pcoll_req_s* r) {
-  uint64_t bytes = 0;
-  for (uint64_t c : r->counts) bytes += c * (uint64_t)elem_bytes(r->dtype);
+// The default configuration of a request of `bytes` per rank: the tuned
+// table's row, then the environment overrides.
+pcoll_config_t config_for(int dtype, int op, int nranks, uint64_t bytes) {
   pcoll_config_t c{};
   // direct launch by default: the request's work is one kernel, and a
   // graph launch of one node costs more host time than a kernel launch
   c.graph = env_int("PCOLL_GRAPH", 0) ? 1 : 0;
-  TuneChoice t = tune_lookup(tune_rows(), r->dtype, r->op, r->nranks, c.graph,
-                             bytes);
+  TuneChoice t = tune_lookup(tune_rows(), dtype, op, nranks, c.graph, bytes);
   c.tile_elems = env_int("PCOLL_TILE", t.tile_elems);
   c.min_tile_elems = env_int("PCOLL_MIN_TILE", 4096);
   if (c.min_tile_elems > c.tile_elems) c.min_tile_elems = c.tile_elems;
@@ -373,10 +390,11 @@ pcoll_config_t default_config(const pcoll_req_s* r) {
   c.publish_batch = env_int("PCOLL_PUBLISH_BATCH", t.publish_batch);
   c.groups = env_int("PCOLL_GROUPS", 0);
   c.groups_per_cu = env_int("PCOLL_GROUPS_PER_CU", t.groups_per_cu);
-  const bool float_sum = r->op == PCOLL_SUM && r->dtype != PCOLL_INT32;
-  // compensated accumulation: on for e4m3 and for 16 ranks or more
-  int comp = float_sum && (is_fp8(r->dtype) || r->dtype == PCOLL_BF16_PAIR ||
-                           r->nranks >= 16);
+  const bool float_sum = op == PCOLL_SUM && dtype != PCOLL_INT32;
+  // compensated accumulation: on for the 8-bit floats, bf16 pairs and 16
+  // ranks or more
+  int comp = float_sum && (is_fp8(dtype) || dtype == PCOLL_BF16_PAIR ||
+                           nranks >= 16);
   comp = env_int("PCOLL_COMP", comp);
   c.comp = float_sum && comp ? 1 : 0;
   c.timeout_ms = env_int("PCOLL_TIMEOUT_MS", 10000);
@@ -385,6 +403,13 @@ pcoll_config_t default_config(const pcoll_req_s* r) {
   if (c.producers < -1 || c.producers > 1) c.producers = -1;
   return c;
 }
+
+pcoll_config_t default_config(const pcoll_req_s* r) {
+  uint64_t bytes = 0;
+  for (uint64_t c : r->counts) bytes += c * (uint64_t)elem_bytes(r->dtype);
+  return config_for(r->dtype, r->op, r->nranks, bytes);
+}
+
 
 void destroy(pcoll_req_t r) {
   if (!r) return;
@@ -1112,6 +1137,114 @@ int pcoll_free(pcoll_req_t r) {
   if (check_req(r)) return PCOLL_ERR_ARG;
   if (r->active) return PCOLL_ERR_STATE;
   destroy(r);
+  return PCOLL_SUCCESS;
+}
+
+int pcoll_reduce_noalloc(size_t count, pcoll_dtype_t dtype_, pcoll_op_t op_,
+                         int nparts, int nranks, const void* const* rank_bufs,
+                         void* out, const void* const* rank_scales,
+                         void* out_scale, void* stream) {
+  const int dtype = (int)dtype_, op = (int)op_;
+  // the argument rules of pcoll_init and pcoll_bind
+  if (!valid_dtype(dtype) || !valid_op(op) || nparts < 1 || nranks < 1)
+    return PCOLL_ERR_ARG;
+  if (nranks > PCOLL_MAX_RANKS) return PCOLL_ERR_UNSUPPORTED;
+  if ((is_fp8(dtype) || dtype == PCOLL_BF16_PAIR) && op == PCOLL_MAX)
+    return PCOLL_ERR_UNSUPPORTED;
+  // beyond the scratch array (the error path allocates nothing either)
+  if ((uint32_t)nparts > kNoallocMaxParts) return PCOLL_ERR_UNSUPPORTED;
+  if ((uint64_t)count > (1ull << 40)) return PCOLL_ERR_UNSUPPORTED;
+  const uint64_t ps = plan_psize(count, (uint64_t)nparts, part_align(dtype));
+  if (ps > (1ull << 31)) return PCOLL_ERR_UNSUPPORTED;
+  const bool fp8 = is_fp8(dtype);
+  const bool out2 = fp8 || dtype == PCOLL_BF16_PAIR;
+  if (!rank_bufs || fp8 != (rank_scales != nullptr) ||
+      out2 != (out_scale != nullptr))
+    return PCOLL_ERR_ARG;
+  auto bad = [&](const void* p, uintptr_t align) {
+    return p ? ((uintptr_t)p & (align - 1)) != 0 : count != 0;
+  };
+  for (int q = 0; q < nranks; ++q)
+    if (bad(rank_bufs[q], 16)) return PCOLL_ERR_ARG;
+  if (bad(out, 16)) return PCOLL_ERR_ARG;
+  if (fp8) {
+    const uintptr_t sa = dtype == PCOLL_MXFP8_E4M3 ? 1 : 4;
+    for (int q = 0; q < nranks; ++q)
+      if (bad(rank_scales[q], sa)) return PCOLL_ERR_ARG;
+    if (bad(out_scale, sa)) return PCOLL_ERR_ARG;
+  } else if (out2 && bad(out_scale, 16)) {
+    return PCOLL_ERR_ARG;
+  }
+  const uint32_t np = (uint32_t)nparts;
+  const NoallocLayout L = noalloc_layout(np);
+  if (L.total > kNoallocScratchBytes) return PCOLL_ERR_UNSUPPORTED;
+
+  int dev = 0, cus = 0, khz = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  void* scratch = nullptr;
+  HIP_TRY(noalloc_scratch(dev, &scratch));
+  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
+                                dev));
+  HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+  if (khz <= 0) khz = 100000;
+  const pcoll_config_t c = config_for(
+      dtype, op, nranks, (uint64_t)count * (uint64_t)elem_bytes(dtype));
+  const uint64_t re = row_elems(dtype);
+  auto len_of = [&](uint32_t k) {
+    const uint64_t off = std::min<uint64_t>((uint64_t)k * ps, count);
+    return std::min<uint64_t>(ps, count - off);
+  };
+  auto rows_of = [&](uint32_t k) { return (len_of(k) + re - 1) / re; };
+  const int groups = launch_groups(c, cus, dtype, np, rows_of);
+  uint64_t total_rows = 0;
+  for (uint32_t k = 0; k < np; ++k) total_rows += rows_of(k);
+
+  unsigned char* base = static_cast<unsigned char*>(scratch);
+  NoallocSetup s{};
+  s.base = base;
+  s.layout = L;
+  std::memset(&s.bucket, 0, sizeof(s.bucket));
+  for (int q = 0; q < nranks; ++q) {
+    s.bucket.in[q] = rank_bufs[q];
+    s.bucket.in_scale[q] = fp8 ? rank_scales[q] : nullptr;
+  }
+  s.bucket.out = out;
+  s.bucket.out_scale = out2 ? out_scale : nullptr;
+  s.bucket.count = count;
+  s.count = count;
+  s.psize = ps;
+  s.nparts = np;
+  s.row_elems = (uint32_t)re;
+  s.epoch = 1;  // every stamp is rewritten by the set-up launch
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  HIP_TRY(launch_noalloc_setup(s, st));
+
+  ReduceArgs a{};
+  a.buckets = reinterpret_cast<const BucketDesc*>(base + L.bucket);
+  a.parts = reinterpret_cast<const PartDesc*>(base + L.parts);
+  a.queue = reinterpret_cast<QEntry*>(base + L.queue);
+  a.done = reinterpret_cast<uint32_t*>(base + L.done);
+  a.queued = reinterpret_cast<uint32_t*>(base + L.queued);
+  a.dlist = reinterpret_cast<uint64_t*>(base + L.dlist);
+  a.ctr = reinterpret_cast<EpochCounters*>(base + L.ctr);
+  a.ring = reinterpret_cast<RingCounters*>(base + L.ring);
+  a.host = reinterpret_cast<HostShared*>(base + L.host);
+  a.hlist = reinterpret_cast<const uint64_t*>(base + L.hlist);
+  a.arrived = reinterpret_cast<uint32_t*>(base + L.arrived);
+  a.nparts_total = np;
+  a.total_groups = (uint32_t)groups;
+  a.total_rows = total_rows;
+  a.row_elems = (uint32_t)re;
+  a.min_tile_rows =
+      (uint32_t)std::max<uint64_t>(1, (uint64_t)c.min_tile_elems / re);
+  a.max_tile_rows = (uint32_t)std::max<uint64_t>(1, (uint64_t)c.tile_elems / re);
+  a.interleave = c.interleave == 1 ? (uint32_t)groups : (uint32_t)c.interleave;
+  a.guide = (uint32_t)c.guide;
+  a.publish_batch = (uint32_t)c.publish_batch;
+  a.epoch = s.epoch;
+  a.timeout_ticks = (uint64_t)c.timeout_ms * (uint64_t)khz;
+  HIP_TRY(launch_reduce(a, dtype, op, c.comp != 0, c.unroll != 2, nranks,
+                        groups, c.group_waves, st));
   return PCOLL_SUCCESS;
 }
 

@@ -24,6 +24,7 @@ SUCCESS = 0
 ERR_ARG, ERR_STATE, ERR_UNSUPPORTED, ERR_HIP = -1, -2, -3, -4
 ERR_TIMEOUT, ERR_NOMEM, ERR_ABORTED = -5, -6, -7
 MAX_RANKS = 16
+NOALLOC_MAX_PARTS = 4096  # PCOLL_NOALLOC_MAX_PARTS
 
 ELEM_BYTES = {INT32: 4, FLOAT32: 4, BFLOAT16: 2, FP8_E4M3: 1, FP8_E5M2: 1,
               MXFP8_E4M3: 1, BF16_PAIR: 2}
@@ -93,6 +94,8 @@ _SIGS = {
     "pcoll_debug_tile_hits": [_p, C.POINTER(C.c_uint32),
                               C.POINTER(C.c_uint32), _i],
     "pcoll_debug_set_epoch": [_p, C.c_uint32],
+    "pcoll_reduce_noalloc": [_sz, _i, _i, _i, _i, C.POINTER(_p), _p,
+                             C.POINTER(_p), _p, _p],
     "pcoll_plan": [_sz, _i, _i, C.POINTER(_sz), C.POINTER(_sz),
                    C.POINTER(_sz)],
     "pcoll_pack_bf16": [_p, _p, _sz, _p],
@@ -297,6 +300,17 @@ def pcoll_debug_tile_hits(h, n):
 
 def pcoll_debug_set_epoch(h, last):
     _check(load().pcoll_debug_set_epoch(h, last), "pcoll_debug_set_epoch")
+
+
+def pcoll_reduce_noalloc(count, dtype, op, nparts, rank_bufs, out,
+                         rank_scales=None, out_scale=None, stream=None):
+    bufs = (_p * len(rank_bufs))(*[_ptr(b) for b in rank_bufs])
+    scales = None if rank_scales is None else \
+        (_p * len(rank_scales))(*[_ptr(s) for s in rank_scales])
+    _check(load().pcoll_reduce_noalloc(count, dtype, op, nparts,
+                                       len(rank_bufs), bufs, _ptr(out), scales,
+                                       _ptr(out_scale), _stream(stream)),
+           "pcoll_reduce_noalloc")
 
 
 def pcoll_plan(count, dtype, nparts):
