@@ -74,6 +74,9 @@ def parse():
     ap.add_argument("--only-8bit", choices=sorted(EIGHT_BIT),
                     help="only time the 8-bit workload in this format "
                          "(for profiling) and exit")
+    ap.add_argument("--only", choices=sorted(ONLY) + sorted(EIGHT_BIT),
+                    help="only time this workload (for profiling): steps "
+                         "epochs after warmup ones, one JSON line, exit")
     return ap.parse_args()
 
 
@@ -434,7 +437,7 @@ EIGHT_BIT = {"e4m3": ("FP8_E4M3", "pcoll_pack_fp8", 256,
                        "mxfp8_batched_p8_1GiB")}
 
 
-def eight_bit(pc, torch, synth, fmt, stream, warmup, reps):
+def eight_bit(pc, torch, synth, fmt, stream, warmup, reps, errors=True):
     """The 8-bit workload: 8 ranks, 128 buckets totalling 2^30 elements per
     rank, N(0, 1e-2) with 1% outliers at 50x, packed to `fmt` (binary32
     scales per 256 elements, or E8M0 bytes per 32 for MX blocks)."""
@@ -469,8 +472,9 @@ def eight_bit(pc, torch, synth, fmt, stream, warmup, reps):
     res = {"host_ms": round(h, 4), "kernel_ms": round(d, 4),
            "GBps": round(nbytes / d / 1e6, 1), "comp": req.config().comp}
     req.free()
-    res["error"] = eight_bit_errors(pc, torch, synth, fmt, counts, qs, ss, ys,
-                                    yss, stream)
+    if errors:
+        res["error"] = eight_bit_errors(pc, torch, synth, fmt, counts, qs, ss,
+                                        ys, yss, stream)
     del qs, ss, ys, yss
     torch.cuda.empty_cache()
     return key, res
@@ -559,6 +563,74 @@ def eight_bit_errors(pc, torch, synth, fmt, counts, qs, ss, ys, yss, stream,
             "gate_vs_fp64": {"e4m3": 6e-2, "mxfp8": 6e-2,
                              "e5m2": 1 / 9 + 16 * 2.0 ** -24}[fmt]}
 
+
+
+def _bf16_buckets(pc, torch, synth, dev):
+    """The batched workload's buckets: FP32 N(0, 1e-3) per rank and their
+    bf16 packing."""
+    cur = torch.cuda.current_stream(dev)
+    counts = synth.batched_bf16_counts()
+    f32 = [synth.normal_f32(8, c, synth.seed_for(3) * 1000 + b, std=1e-3,
+                            device=dev) for b, c in enumerate(counts)]
+    bf = []
+    for bucket, c in zip(f32, counts):
+        row = []
+        for t in bucket:
+            o = torch.empty(c, dtype=torch.int16, device=dev)
+            pc.pcoll_pack_bf16(t, o, c, cur)
+            row.append(o)
+        bf.append(row)
+    torch.cuda.synchronize()
+    return counts, f32, bf
+
+
+def only_workload(pc, torch, synth, name, warmup, steps):
+    """One workload alone, for profiling: the batched bf16 buckets (8
+    ranks, 64 buckets, 32 partitions each) as bf16, bf16 pairs or FP32, or
+    int32 sum / max at 16 ranks and 2^24 elements (256 partitions).  Same
+    inputs, readiness order and timing as the extras."""
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(dev)
+    if name.startswith("int32"):
+        n4 = 1 << 24
+        xi = synth.uniform_i32(16, n4, synth.seed_for(4), -(1 << 20), 1 << 20,
+                               device=dev)
+        yi = torch.empty(n4, dtype=torch.int32, device=dev)
+        o4 = ready_array(synth.permutation(256, synth.seed_for(4)))
+        r = pc.Request([n4], pc.INT32, pc.SUM if name == "int32_sum"
+                       else pc.MAX, 256, 16)
+        r.bind([xi], [yi], stream=stream)
+        h, d = time_requests(torch, [r], [o4], stream, warmup, steps)
+        res = {"host_ms": round(h, 4), "kernel_ms": round(d, 4),
+               "GBps": round(17 * n4 * 4 / d / 1e6, 1)}
+        r.free()
+        return res
+    counts, f32, bf = _bf16_buckets(pc, torch, synth, dev)
+    n_el = sum(counts)
+    order = ready_array(synth.permutation(len(counts) * 32, 3))
+    if name == "batched_fp32":
+        ins, dt, nb = f32, pc.FLOAT32, 36 * n_el
+        outs = [torch.empty(c, device=dev) for c in counts]
+    else:
+        ins = bf
+        dt = pc.BF16_PAIR if name == "batched_bf16_pair" else pc.BFLOAT16
+        nb = (20 if dt == pc.BF16_PAIR else 18) * n_el
+        outs = [torch.empty(c, dtype=torch.int16, device=dev) for c in counts]
+    lo = [torch.empty(c, dtype=torch.int16, device=dev) for c in counts] \
+        if dt == pc.BF16_PAIR else None
+    r = pc.Request(counts, dt, pc.SUM, 32, 8, batched=True)
+    r.bind(ins, outs, out_scales=lo, stream=stream)
+    h, d = time_requests(torch, [r], [order], stream, warmup, steps)
+    cfg = r.config()
+    res = {"host_ms": round(h, 4), "kernel_ms": round(d, 4),
+           "GBps": round(nb / d / 1e6, 1), "tile_elems": cfg.tile_elems,
+           "group_waves": cfg.group_waves, "groups": r.stats().groups}
+    r.free()
+    return res
+
+
+ONLY = ("batched_bf16", "batched_bf16_pair", "batched_fp32", "int32_sum",
+        "int32_max")
 
 
 def extras(pc, torch, synth, warmup, reps):
@@ -742,10 +814,16 @@ def main():
         print(json.dumps({"probe_copy": probe_copy(pc, torch, args.steps)}),
               flush=True)
         return
-    if args.only_8bit:
-        key, res = eight_bit(pc, torch, synth, args.only_8bit,
-                             torch.cuda.Stream(dev), args.warmup, args.steps)
+    if args.only_8bit or args.only in EIGHT_BIT:
+        key, res = eight_bit(pc, torch, synth, args.only_8bit or args.only,
+                             torch.cuda.Stream(dev), args.warmup, args.steps,
+                             errors=False)
         print(json.dumps({key: res}), flush=True)
+        return
+    if args.only:
+        print(json.dumps({args.only: only_workload(
+            pc, torch, synth, args.only, args.warmup, args.steps)}),
+            flush=True)
         return
 
     P, n, nparts = args.ranks, 1 << args.log2n, args.nparts

@@ -15,8 +15,9 @@
  *
  * Partitions.  Each message is cut into `nparts` partitions by the chunk
  * rule of Algorithm 1 (Section 4.3): every partition has the same length
- * psize = ceil(count / nparts) rounded up to whole 16-byte vectors (to
- * whole scale blocks for the 8-bit floats: 256 elements, 32 for MX blocks),
+ * psize = ceil(count / nparts) rounded up to whole 128-byte cache lines
+ * (and whole scale blocks for the 8-bit floats: 256 elements, 128 for MX
+ * blocks of 32; with A = 1 the rule is Algorithm 1's exactly),
  * offsets are fixed in advance as running sums, and the last partitions
  * are clipped (possibly to zero length).  Destination regions are disjoint (Section 4.5, Ordering
  * Guarantee): each partition of the output is written exactly once per
@@ -36,7 +37,9 @@
  * e.g. torch tensors); the library keeps raw pointers only.  Rank buffers of
  * partition p must stay unchanged from pready(p) until p has arrived; the
  * output region of p must not be touched by others before that.  All device
- * pointers must be 16-byte aligned.  The library owns its flags, counters,
+ * pointers must be 16-byte aligned; buffers aligned to 128 bytes (as
+ * torch's allocations are) stream without cache lines shared between
+ * tiles.  The library owns its flags, counters,
  * descriptor tables, graphs and events.
  *
  * Errors.  Every call returns PCOLL_SUCCESS (0) or a negative code; on

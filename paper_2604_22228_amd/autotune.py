@@ -5,16 +5,20 @@ search and uses the results as defaults (environment variables override
 them), tuning graph and non-graph execution separately.  This tool does the
 same for the persistent reduce kernel: for each tuning key (dtype, op,
 ranks, graph mode, floor(log2(bytes per rank))) it times every
-(tile_elems, groups_per_cu, interleave, waves per workgroup, publish batch)
-combination of its grid on seeded synthetic inputs and writes the fastest
-into the text table the library reads at request creation (tuned_mi355x.txt
-next to libpcoll.so, or PCOLL_TUNE_FILE).  Rows of one (dtype, op, ranks,
-graph) cover contiguous size ranges: each key's row reaches down to the
-next smaller key's.
+(tile_elems, groups_per_cu, interleave, waves per workgroup, publish batch,
+rows in flight per lane) combination of its grid on seeded synthetic
+inputs and writes the fastest into the text table the library reads at
+request creation (tuned_mi355x.txt next to libpcoll.so, or
+PCOLL_TUNE_FILE).  Rows of one (dtype, op, ranks, graph) cover contiguous
+size ranges: each key's row reaches down to the next smaller key's.  The
+batched workloads are tuned for direct launches and for graph replays
+apart; a graph row is written before the direct one, whose graph column is
+"*" (it also serves graph replays of keys without a graph row of their
+own).
 
 Timing: median device time of `reps` epochs (HIP events on the bound
-stream around start), every partition readied at once in a seeded random
-order, after `warmup` epochs; for the FP32 sweep keys, the mean of that
+stream around start and the readiness call, submitted at once), every
+partition readied at once in a seeded random order, after `warmup` epochs; for the FP32 sweep keys, the mean of that
 over the sweep's partition counts 1, 4, 16 and 64.  Run on the target GPU:
 
     python -m paper_2604_22228_amd.autotune --out paper_2604_22228_amd/tuned_mi355x.txt
@@ -41,17 +45,22 @@ GROUPS_PER_CU = (1, 2)
 INTERLEAVE = (1, 4, 8, 16)
 WAVES = (4, 8)
 BATCH = (64,)
+# rows in flight per lane in the 16-byte-vector kernels at 3..8 ranks (the
+# 8-bit kernels load one row per lane at a time)
+UNROLL = (2, 4)
 # 8-bit payloads: the kernels are bound by instruction issue and hide
 # memory latency with more resident waves and longer tiles
 TILES_8BIT = (16384, 32768, 65536)
 GROUPS_PER_CU_8BIT = (2, 3)
-FALLBACK = "* * * * 0 63 8192 1 16 8 64"
+FALLBACK = "* * * * 0 63 8192 1 16 8 64 4"
 
 
-def grid_for(dtype):
+def grid_for(dtype, ranks=8):
     if dtype in (3, 4, 5):
-        return [TILES_8BIT, GROUPS_PER_CU_8BIT, INTERLEAVE, WAVES, BATCH]
-    return [TILES, GROUPS_PER_CU, INTERLEAVE, WAVES, BATCH]
+        return [TILES_8BIT, GROUPS_PER_CU_8BIT, INTERLEAVE, WAVES, BATCH,
+                (4,)]
+    return [TILES, GROUPS_PER_CU, INTERLEAVE, WAVES, BATCH,
+            UNROLL if 3 <= ranks <= 8 else (4,)]
 
 
 def default_keys():
@@ -65,23 +74,25 @@ def default_keys():
     keys.append((1, 0, 4, 0, [262144], 8))          # plain workload
     keys.append((0, 0, 16, 0, [1 << 24], 256))      # int32 sum
     keys.append((0, 1, 16, 0, [1 << 24], 256))      # int32 max
-    keys.append((2, 0, 8, 0, list(synth.batched_bf16_counts()), 32))
-    keys.append((6, 0, 8, 0, list(synth.batched_bf16_counts()), 32))
-    keys.append((3, 0, 8, 0, list(synth.fp8_bucket_counts()), 32))
-    keys.append((4, 0, 8, 0, list(synth.fp8_bucket_counts()), 32))
-    keys.append((5, 0, 8, 0, list(synth.fp8_bucket_counts()), 32))
+    # the batched workloads, direct launches and graph replays
+    for graph in (0, 1):
+        keys.append((2, 0, 8, graph, list(synth.batched_bf16_counts()), 32))
+        keys.append((6, 0, 8, graph, list(synth.batched_bf16_counts()), 32))
+        keys.append((3, 0, 8, graph, list(synth.fp8_bucket_counts()), 32))
+        keys.append((4, 0, 8, graph, list(synth.fp8_bucket_counts()), 32))
+        keys.append((5, 0, 8, graph, list(synth.fp8_bucket_counts()), 32))
     return keys
 
 
 def time_config(pc, torch, synth, dtype, op, ranks, graph, counts, nparts,
                 choice, warmup, reps, bufs):
-    tile, gpc, inter, waves, batch = choice
+    tile, gpc, inter, waves, batch, unroll = choice
     req = pc.Request(counts, dtype, op, nparts, ranks,
                      batched=len(counts) > 1)
     req.set_config(tile_elems=tile, min_tile_elems=min(tile, 4096),
                    groups_per_cu=gpc, graph=graph, groups=0,
                    interleave=inter, guide=0, group_waves=waves,
-                   publish_batch=batch)
+                   publish_batch=batch, unroll=unroll, producers=0)
     ins, outs, rsc, osc, stream = bufs
     req.bind(ins, outs, rsc, osc, stream=stream)
     order = synth.permutation(req.nparts_total, 1).astype("int32")
@@ -93,6 +104,7 @@ def time_config(pc, torch, synth, dtype, op, ranks, graph, counts, nparts,
         req.start()
         req.pready_list(order)
         e1.record(stream)
+        stream.query()  # the runtime may hold the record back until then
         req.wait()
         if it >= warmup:
             e1.synchronize()
@@ -164,7 +176,7 @@ def tune(keys, grid, warmup, reps, log=print):
         lg = int(math.floor(math.log2(max(nbytes, 1))))
         best = None
         parts_list = nparts if isinstance(nparts, tuple) else (nparts,)
-        for choice in itertools.product(*(grid or grid_for(dtype))):
+        for choice in itertools.product(*(grid or grid_for(dtype, ranks))):
             ms = statistics.mean(
                 time_config(pc, torch, synth, dtype, op, ranks, graph,
                             counts, np_, choice, warmup, reps, bufs)
@@ -174,13 +186,14 @@ def tune(keys, grid, warmup, reps, log=print):
                             "graph": graph, "log2_bytes": lg,
                             "tile": choice[0], "gpc": choice[1],
                             "interleave": choice[2], "waves": choice[3],
-                            "batch": choice[4], "ms": round(ms, 5)}))
+                            "batch": choice[4], "unroll": choice[5],
+                            "ms": round(ms, 5)}))
             if best is None or ms < best[0]:
                 best = (ms, choice)
-        # launch parameters do not depend on how the kernel is launched:
-        # the row serves graph and direct launches alike
-        rows.append((DTYPE_NAMES[dtype], OP_NAMES[op], ranks, "*", lg,
-                     best[1], best[0]))
+        # a direct launch's row also serves graph replays of keys tuned
+        # for direct launches only
+        rows.append((DTYPE_NAMES[dtype], OP_NAMES[op], ranks,
+                     "1" if graph else "*", lg, best[1], best[0]))
         del bufs
         torch.cuda.empty_cache()
     return rows
@@ -194,12 +207,13 @@ def read_table(path):
         for line in f:
             body, _, note = line.partition("#")
             v = body.split()
-            if len(v) != 11 or v[0] == "*":
+            if len(v) not in (11, 12) or v[0] == "*":
                 continue
             lg = int(note.split("2^")[1].split()[0])
             ms = float(note.split()[0])
-            rows.append((v[0], v[1], int(v[2]), v[3], lg,
-                         tuple(int(x) for x in v[6:11]), ms))
+            choice = tuple(int(x) for x in v[6:]) + ((4,) if len(v) == 11
+                                                      else ())
+            rows.append((v[0], v[1], int(v[2]), v[3], lg, choice, ms))
     return rows
 
 
@@ -212,14 +226,18 @@ def write_table(rows, path):
     lines = ["# Tuned launch parameters of libpcoll on MI355X (gfx950), "
              "written by paper_2604_22228_amd/autotune.py.",
              "# dtype op ranks graph log2_lo log2_hi tile_elems "
-             "groups_per_cu interleave waves batch   # median kernel ms"]
-    for key, rs in groups.items():
-        rs = sorted(rs, key=lambda r: r[4])
+             "groups_per_cu interleave waves batch unroll   # median kernel ms"]
+    # graph rows first: the first matching row wins, and a direct row
+    # ("*") also serves graph replays
+    keys = sorted(groups, key=lambda k: 0 if k[3] == "1" else 1)
+    keys = sorted(keys, key=lambda k: [kk[:3] for kk in groups].index(k[:3]))
+    for key in keys:
+        rs = sorted(groups[key], key=lambda r: r[4])
         lo = 0
-        for i, (d, o, rk, g, lg, (t, gpc, il, w, b), ms) in enumerate(rs):
+        for i, (d, o, rk, g, lg, (t, gpc, il, w, b, u), ms) in enumerate(rs):
             hi = 63 if i == len(rs) - 1 else lg
             lines.append(f"{d} {o} {rk} {g} {lo} {hi} {t} {gpc} {il} {w} {b}"
-                         f"   # {ms:.4f} at 2^{lg} B")
+                         f" {u}   # {ms:.4f} at 2^{lg} B")
             lo = hi + 1
     lines.append(FALLBACK + "   # fallback")
     with open(path, "w") as f:
@@ -237,22 +255,28 @@ def main():
     ap.add_argument("--only", default="",
                     help="comma-separated dtypes (f32, bf16, e4m3, ...) to "
                          "tune; the other rows of --out are kept")
+    ap.add_argument("--graph", choices=("0", "1", "both"), default="both",
+                    help="launch modes of the batched keys to tune")
     args = ap.parse_args()
     keys = default_keys()
+    if args.graph != "both":
+        keys = [k for k in keys if k[3] == int(args.graph)]
     grid = None
     if args.quick:
-        keys, grid = keys[-6:-4], [(16384, 131072), (1,), (1,), (4,), (64,)]
+        keys, grid = keys[-10:-8], [(16384, 65536), (1,), (1,), (4,), (64,),
+                                    (4,)]
     kept = []
     if args.only:
         only = set(args.only.split(","))
         keys = [k for k in keys if DTYPE_NAMES[k[0]] in only]
-        kept = [r for r in read_table(args.out) if r[0] not in only]
+        tuned = {(DTYPE_NAMES[k[0]], "1" if k[3] else "*") for k in keys}
+        kept = [r for r in read_table(args.out) if (r[0], r[3]) not in tuned]
     rows = tune(keys, grid, args.warmup, args.reps,
                 log=lambda s: print(s, flush=True))
     order = [DTYPE_NAMES[k[0]] + OP_NAMES[k[1]] + str(k[2])
              for k in default_keys()]
     rows = sorted(kept + rows, key=lambda r: (order.index(
-        r[0] + r[1] + str(r[2])), r[4]))
+        r[0] + r[1] + str(r[2])), r[3] != "1", r[4]))
     write_table(rows, args.out)
     print(f"wrote {args.out} ({len(rows)} rows)", flush=True)
 

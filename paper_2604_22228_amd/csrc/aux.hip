@@ -164,14 +164,10 @@ __global__ __launch_bounds__(256) void pack_bf16_kernel(const float* src,
     const uint4 b =
         dev::ld_stream(reinterpret_cast<const uint4*>(src) + 2 * v + 1);
     uint4 o;
-    o.x = dev::f_to_bf16(__uint_as_float(a.x)) |
-          (dev::f_to_bf16(__uint_as_float(a.y)) << 16);
-    o.y = dev::f_to_bf16(__uint_as_float(a.z)) |
-          (dev::f_to_bf16(__uint_as_float(a.w)) << 16);
-    o.z = dev::f_to_bf16(__uint_as_float(b.x)) |
-          (dev::f_to_bf16(__uint_as_float(b.y)) << 16);
-    o.w = dev::f_to_bf16(__uint_as_float(b.z)) |
-          (dev::f_to_bf16(__uint_as_float(b.w)) << 16);
+    o.x = dev::f_to_bf16x2(__uint_as_float(a.x), __uint_as_float(a.y));
+    o.y = dev::f_to_bf16x2(__uint_as_float(a.z), __uint_as_float(a.w));
+    o.z = dev::f_to_bf16x2(__uint_as_float(b.x), __uint_as_float(b.y));
+    o.w = dev::f_to_bf16x2(__uint_as_float(b.z), __uint_as_float(b.w));
     dev::st_stream(reinterpret_cast<uint4*>(dst) + v, o);
   }
   if (blockIdx.x == 0 && threadIdx.x < n - nv * 8) {

@@ -102,11 +102,14 @@ bool is_fp8(int d) {
 }
 bool valid_op(int o) { return o == PCOLL_SUM || o == PCOLL_MAX; }
 
-// Partition alignment in elements: whole 16-byte vectors, whole scale
-// blocks for the 8-bit floats (256 elements, 32 for MX blocks).
+// Partition alignment in elements: whole 128-byte cache lines, so that a
+// row (1 KiB of one rank) of a partition covers exactly eight lines when
+// the buffers are 128-byte aligned (rows of neighbouring tiles then never
+// share a line, which each would fetch again), and whole scale blocks for
+// the 8-bit floats (256 elements; 128 for MX blocks of 32).
 uint64_t part_align(int dtype) {
-  if (dtype == PCOLL_MXFP8_E4M3) return 32u;
-  return is_fp8(dtype) ? 256u : 16u / (uint64_t)elem_bytes(dtype);
+  if (dtype == PCOLL_MXFP8_E4M3) return 128u;
+  return is_fp8(dtype) ? 256u : 128u / (uint64_t)elem_bytes(dtype);
 }
 
 // Algorithm 1's chunk rule with the alignment above.
@@ -385,7 +388,7 @@ pcoll_config_t config_for(int dtype, int op, int nranks, uint64_t bytes) {
   if (c.min_tile_elems > c.tile_elems) c.min_tile_elems = c.tile_elems;
   c.interleave = env_int("PCOLL_INTERLEAVE", t.interleave);
   c.guide = env_int("PCOLL_GUIDE", 0);
-  c.unroll = env_int("PCOLL_UNROLL", 4);
+  c.unroll = env_int("PCOLL_UNROLL", t.unroll);
   c.group_waves = env_int("PCOLL_GROUP_WAVES", t.group_waves);
   c.publish_batch = env_int("PCOLL_PUBLISH_BATCH", t.publish_batch);
   c.groups = env_int("PCOLL_GROUPS", 0);

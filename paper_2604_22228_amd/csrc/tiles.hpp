@@ -4,9 +4,10 @@
 // tiles gives the same result, which is why partitions may be reduced in
 // any arrival order).
 //
-// Layout: every rank buffer and output is 16-byte aligned and every tile
-// starts on a 16-byte boundary (partition lengths are planned in multiples of
-// 16 bytes; 256 elements for e4m3).  Each lane streams 16-byte vectors
+// Layout: every rank buffer and output is 16-byte aligned and every
+// partition starts on a 128-byte line of its bucket (partition lengths are
+// planned in whole lines; 256 elements for the 8-bit floats), so a row of a
+// 128-byte aligned buffer covers whole lines.  Each lane streams 16-byte vectors
 // (dwordx4), 64 lanes cover 1 KiB per rank per step, and U steps are issued
 // back to back so that U * P loads are in flight per lane before the first
 // add.  Loads and stores carry the nontemporal hint: the data are touched
@@ -92,14 +93,21 @@ __device__ __forceinline__ float as_f(uint32_t u) { return __uint_as_float(u); }
 __device__ __forceinline__ float bf16_to_f(uint32_t h) {
   return __uint_as_float(h << 16);
 }
-// float -> bfloat16, round to nearest even (ties to the even code); every
-// NaN becomes the quiet NaN 0x7FC0 (sign and payload dropped); overflow
-// rounds to infinity.
+// Two floats -> a word of two bfloat16 codes (a in the low half), round
+// to nearest even (ties to the even code, subnormals kept, overflow to
+// infinity) with gfx950's v_cvt_pk_bf16_f32; every NaN becomes the quiet
+// NaN 0x7FC0 (sign and payload dropped) by converting the quiet NaN of
+// binary32 with an empty payload in its place.
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t f_to_bf16x2(float a, float b) {
+  const float qnan = __uint_as_float(0x7fc00000u);
+  const f32x2_t v = {__builtin_isnan(a) ? qnan : a,
+                     __builtin_isnan(b) ? qnan : b};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2_t));
+}
 __device__ __forceinline__ uint32_t f_to_bf16(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0u;
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return u >> 16;
+  return f_to_bf16x2(f, 0.0f) & 0xffffu;
 }
 
 // The two 8-bit formats: largest finite value (the block scale maps a
@@ -197,7 +205,7 @@ struct VecCombine<Acc, P, 2> {
         lo.add(bf16_to_f(w & 0xffffu));
         hi.add(bf16_to_f(w >> 16));
       }
-      o[j] = f_to_bf16(lo.get()) | (f_to_bf16(hi.get()) << 16);
+      o[j] = f_to_bf16x2(lo.get(), hi.get());
     }
     return make_uint4(o[0], o[1], o[2], o[3]);
   }

@@ -52,9 +52,9 @@ std::vector<TuneRow> parse_tune_table(const std::string& text) {
     auto hash = line.find('#');
     if (hash != std::string::npos) line.resize(hash);
     std::istringstream ls(line);
-    std::string f[11];
+    std::string f[12];
     int nf = 0;
-    while (nf < 11 && (ls >> f[nf])) ++nf;
+    while (nf < 12 && (ls >> f[nf])) ++nf;
     std::string extra;
     if (nf < 8 || (ls >> extra)) continue;
     TuneRow r;
@@ -75,8 +75,11 @@ std::vector<TuneRow> parse_tune_table(const std::string& text) {
     if (nf >= 10 && (!parse_int_or_any(f[9], &r.group_waves) ||
                      r.group_waves < 1 || r.group_waves > 8))
       continue;
-    if (nf == 11 && (!parse_int_or_any(f[10], &r.publish_batch) ||
+    if (nf >= 11 && (!parse_int_or_any(f[10], &r.publish_batch) ||
                      r.publish_batch < 1 || r.publish_batch > 64))
+      continue;
+    if (nf == 12 && (!parse_int_or_any(f[11], &r.unroll) ||
+                     (r.unroll != 2 && r.unroll != 4)))
       continue;
     if (r.log2_lo < 0) r.log2_lo = 0;
     if (r.log2_hi < 0) r.log2_hi = 63;
@@ -95,13 +98,13 @@ TuneChoice tune_lookup(const std::vector<TuneRow>& rows, int dtype, int op,
     if (match(r.dtype, dtype) && match(r.op, op) && match(r.ranks, ranks) &&
         match(r.graph, graph) && lg >= r.log2_lo && lg <= r.log2_hi)
       return {r.tile_elems, r.groups_per_cu, r.interleave, r.group_waves,
-              r.publish_batch};
+              r.publish_batch, r.unroll};
   }
   // built-in default: 16 KiB of output per tile, two groups per CU
   // (element bytes: 2 for bf16 and bf16 pairs, 1 for the 8-bit floats)
   const int elem = dtype == 2 || dtype == 6 ? 2
                                             : (dtype >= 3 && dtype <= 5 ? 1 : 4);
-  return {16384 / elem, 2, 0, 4, 16};
+  return {16384 / elem, 2, 0, 4, 16, 4};
 }
 
 }  // namespace pcoll

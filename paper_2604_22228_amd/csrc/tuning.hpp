@@ -5,17 +5,17 @@
 // tuned values are defaults that environment variables override.  Here the
 // search is done by the package's autotuner, which writes a text table:
 //
-//   # dtype op ranks graph log2_lo log2_hi tile groups_per_cu interleave waves batch
-//   f32     sum 8   0     24      28      4096   1             1          4     16
+//   # dtype op ranks graph log2_lo log2_hi tile groups_per_cu interleave waves batch unroll
+//   f32     sum 8   0     24      28      4096   1             1          4     16    4
 //
 // dtype in {i32, f32, bf16, e4m3, e5m2, mxfp8,
 // bf16pair, *}, op in {sum, max, *}, ranks a number
 // or *, graph 0 / 1 / *, and [log2_lo, log2_hi] the range of
 // floor(log2(bytes per rank of the whole request)); the trailing interleave
 // (tile layout, default 0; 1 = bands of the launch's workgroups, n >= 2 =
-// bands of n tiles), waves-per-workgroup (default 4) and publish-batch (default
-// 16) columns may be omitted, from the right.  The first
-// matching row wins.  Host-only C++17.
+// bands of n tiles), waves-per-workgroup (default 4), publish-batch (default
+// 16) and unroll (rows in flight per lane, 2 or 4, default 4) columns may be
+// omitted, from the right.  The first matching row wins.  Host-only C++17.
 #pragma once
 #include <cstdint>
 #include <string>
@@ -28,6 +28,7 @@ struct TuneRow {
   int log2_lo = 0, log2_hi = 63;
   int tile_elems = 0, groups_per_cu = 0, interleave = 0, group_waves = 4;
   int publish_batch = 16;
+  int unroll = 4;
 };
 
 struct TuneChoice {
@@ -36,6 +37,7 @@ struct TuneChoice {
   int interleave;
   int group_waves;
   int publish_batch;
+  int unroll;
 };
 
 // Parses a table; malformed lines are skipped.  Returns the rows.

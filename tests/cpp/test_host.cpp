@@ -53,14 +53,16 @@ int main() {
       "bf16 * * 1 * * 16384 4\n"
       "garbage line\n"
       "f32 sum 8 0 0 63 1000 2\n"  // tile not a multiple of 1024: skipped
-      "i32 max 16 0 0 63 2048 3 1 4 8 extra\n"  // 12 fields: skipped
+      "i32 max 16 0 0 63 2048 3 1 4 8 4 extra\n"  // 13 fields: skipped
+      "i32 max 16 0 0 63 2048 3 1 4 8 3\n"  // unroll 3: skipped
       "i32 max 16 0 0 63 2048 3 1 4 65\n"    // batch 65: skipped
       "i32 max 16 0 0 63 2048 3 1 9\n"        // 9 waves: skipped
       "i32 sum 16 0 0 63 2048 3 -1\n"       // negative interleave: skipped
       "i32 max 16 0 0 63 2048 3 1\n"
-      "bf16 max 4 0 0 63 8192 1 1 2 32\n";
+      "bf16 max 4 0 0 63 8192 1 1 2 32\n"
+      "e4m3 sum 8 1 0 63 32768 2 4 8 64 2\n";
   auto rows = pcoll::parse_tune_table(t);
-  CHECK(rows.size() == 5);
+  CHECK(rows.size() == 6);
   auto c1 = pcoll::tune_lookup(rows, 1, 0, 8, 0, 1ull << 26);
   CHECK(c1.tile_elems == 8192 && c1.groups_per_cu == 2);
   auto c2 = pcoll::tune_lookup(rows, 1, 0, 8, 0, 1ull << 20);
@@ -71,7 +73,11 @@ int main() {
   CHECK(c4.tile_elems == 4096 && c4.groups_per_cu == 2 && c4.interleave == 0);
   auto c6 = pcoll::tune_lookup(rows, 0, 1, 16, 0, 1ull << 26);
   CHECK(c6.tile_elems == 2048 && c6.groups_per_cu == 3 && c6.interleave == 1 &&
-        c6.group_waves == 4 && c6.publish_batch == 16);
+        c6.group_waves == 4 && c6.publish_batch == 16 && c6.unroll == 4);
+  auto c8 = pcoll::tune_lookup(rows, 3, 0, 8, 1, 1ull << 30);  // graph row
+  CHECK(c8.tile_elems == 32768 && c8.unroll == 2);
+  auto c9 = pcoll::tune_lookup(rows, 3, 0, 8, 0, 1ull << 30);  // no row
+  CHECK(c9.tile_elems == 16384 && c9.unroll == 4);
   auto c7 = pcoll::tune_lookup(rows, 2, 1, 4, 0, 1ull << 20);
   CHECK(c7.tile_elems == 8192 && c7.group_waves == 2 && c7.publish_batch == 32);
   auto c5 = pcoll::tune_lookup(rows, 1, 0, 8, 0, 1ull << 31);  // beyond 30

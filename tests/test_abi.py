@@ -59,12 +59,12 @@ def test_version_and_strerror():
         assert lib.pcoll_strerror(code)
 
 
-@pytest.mark.parametrize("dtype,align", [(pc.INT32, 4), (pc.FLOAT32, 4),
-                                         (pc.BFLOAT16, 8),
+@pytest.mark.parametrize("dtype,align", [(pc.INT32, 32), (pc.FLOAT32, 32),
+                                         (pc.BFLOAT16, 64),
                                          (pc.FP8_E4M3, 256),
                                          (pc.FP8_E5M2, 256),
-                                         (pc.MXFP8_E4M3, 32),
-                                         (pc.BF16_PAIR, 8)])
+                                         (pc.MXFP8_E4M3, 128),
+                                         (pc.BF16_PAIR, 64)])
 def test_plan_matches_oracle(dtype, align):
     orc = get_oracle()
     for count in list(range(0, 70)) + [255, 256, 1000, 262144, 262144 + 37,
@@ -139,13 +139,16 @@ def test_probe_and_pack_reject_unaligned_sizes():
     assert lib.pcoll_pack_bf16(None, None, 0, None) == 0
 
 
-def test_plan_partitions_are_aligned_for_vectors():
+def test_plan_partitions_are_aligned_for_lines():
+    """Partitions start on 128-byte lines (and 8-bit scale blocks)."""
     for dtype in (pc.INT32, pc.FLOAT32, pc.BFLOAT16, pc.FP8_E4M3,
-                  pc.FP8_E5M2, pc.MXFP8_E4M3):
+                  pc.FP8_E5M2, pc.MXFP8_E4M3, pc.BF16_PAIR):
         for count in (1, 7, 1000, 123457):
             ps, offs, lens = pc.pcoll_plan(count, dtype, 8)
             unit = {pc.FP8_E4M3: 256, pc.FP8_E5M2: 256,
-                    pc.MXFP8_E4M3: 32}.get(dtype, 16 // pc.ELEM_BYTES[dtype])
+                    pc.MXFP8_E4M3: 128}.get(dtype,
+                                            128 // pc.ELEM_BYTES[dtype])
+            assert ps % unit == 0
             assert all(o % unit == 0 for o, n in zip(offs, lens) if n)
             assert sum(lens) == count
             assert np.all(np.diff(offs) >= 0)
