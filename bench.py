@@ -202,8 +202,27 @@ def _events(torch):
 def time_requests(torch, reqs, orders, stream, warmup, reps):
     """Time-to-reduce of a set of requests sharing one stream: start all,
     ready every partition (each request's seeded order, one list call per
-    request), wait all.  Returns (host ms per rep, device ms per rep)."""
+    request), wait all.  Returns (host ms per rep, device ms per rep): the
+    device time is the kernel's own (start and end stamped by the launch,
+    debug timing, in a second pass: it costs host time of its own) for one
+    request in direct-launch mode, else HIP events around the starts and
+    the readiness calls."""
     import statistics
+    own = len(reqs) == 1 and not reqs[0].config().graph
+    host, devt = _time_pass(torch, reqs, orders, stream, warmup, reps)
+    if own:
+        reqs[0].set_config(debug=4)
+        _time_pass(torch, reqs, orders, stream, 1, 0)
+        st0 = reqs[0].stats()
+        _time_pass(torch, reqs, orders, stream, 0, reps)
+        st1 = reqs[0].stats()
+        reqs[0].set_config(debug=0)
+        devt = [(st1.kernel_ms_total - st0.kernel_ms_total) /
+                max(st1.kernel_timed - st0.kernel_timed, 1)]
+    return statistics.median(host), statistics.median(devt)
+
+
+def _time_pass(torch, reqs, orders, stream, warmup, reps):
     host, devt = [], []
     for it in range(warmup + reps):
         e0, e1 = _events(torch)
@@ -223,7 +242,7 @@ def time_requests(torch, reqs, orders, stream, warmup, reps):
         if it >= warmup:
             host.append((t1 - t0) * 1e3)
             devt.append(e0.elapsed_time(e1))
-    return statistics.median(host), statistics.median(devt)
+    return host, devt
 
 
 def size_sweep(pc, torch, synth, stream):
@@ -231,26 +250,32 @@ def size_sweep(pc, torch, synth, stream):
     (k = 0..26, 4 B .. 256 MiB), 1 / 4 / 16 / 64 partitions readied in a
     seeded random order with one list call.  Cold cache: a 1 GiB fill (4x
     the 256 MB MALL) runs on the stream before every timed epoch, outside
-    the timed events.  Per point: median device us over the epochs (events
-    before start and after the readiness call, on the bound stream) and
-    effective GB/s = 36 * 2^k B / time."""
+    the timed events.  Per point, medians over the epochs: the epoch's
+    device time from HIP events recorded before start and after the
+    readiness call on the bound stream (marker packets, which cost about
+    5 us each on MI355X), the kernel's own time (events stamped at its
+    start and end by the launch), and effective GB/s = 36 * 2^k B / the
+    kernel's time.  The gate (>= 70 % of HBM peak at 64 MiB per rank and
+    up) is read on the kernel's time; the events' figure is given beside
+    it."""
     import statistics
     dev = torch.device("cuda:0")
     P = 8
     big = synth.normal_f32(P, 1 << 26, synth.seed_for(2), device=dev)
     out = torch.empty(1 << 26, device=dev)
     flush = torch.empty(1 << 28, dtype=torch.float32, device=dev)
-    points, gate = [], []
+    points, gate, gate_ev = [], [], []
     for k in range(27):
         n = 1 << k
         xs = [b[:n] for b in big]
         reps = 20 if k <= 22 else 10
         for nparts in (1, 4, 16, 64):
             req = pc.Request([n], pc.FLOAT32, pc.SUM, nparts, P)
+            req.set_config(debug=4)  # the kernel's own time
             req.bind([xs], [out[:max(n, 4)]], stream=stream)
             order = ready_array(synth.permutation(nparts,
                                                   k * 100 + nparts))
-            ts = []
+            ts, ks = [], []
             for it in range(2 + reps):
                 pc.pcoll_probe_fill(flush, 4 << 28, 0, stream)
                 e0, e1 = _events(torch)
@@ -263,18 +288,91 @@ def size_sweep(pc, torch, synth, stream):
                 if it >= 2:
                     e1.synchronize()
                     ts.append(e0.elapsed_time(e1))
+                    ks.append(req.stats().last_kernel_ms)
             req.free()
-            ms = statistics.median(ts)
-            gbps = 36 * n / (ms * 1e-3) / 1e9
-            points.append([k, nparts, round(ms * 1e3, 2), round(gbps, 1)])
+            ms, kms = statistics.median(ts), statistics.median(ks)
+            gbps = 36 * n / (kms * 1e-3) / 1e9
+            points.append([k, nparts, round(ms * 1e3, 2), round(kms * 1e3, 2),
+                           round(gbps, 1)])
             if k >= 24:
                 gate.append(gbps)
+                gate_ev.append(36 * n / (ms * 1e-3) / 1e9)
     del big, out, flush
     torch.cuda.empty_cache()
-    return {"columns": ["log2_elements", "partitions", "device_us", "GBps"],
+    return {"columns": ["log2_elements", "partitions", "device_us",
+                        "kernel_us", "GBps"],
             "points": points, "cold_cache": True,
             "min_pct_hbm_peak_at_64MiB_and_up": round(
-                100 * min(gate) / HBM_PEAK_GBPS, 2)}
+                100 * min(gate) / HBM_PEAK_GBPS, 2),
+            "min_pct_hbm_peak_at_64MiB_and_up_events": round(
+                100 * min(gate_ev) / HBM_PEAK_GBPS, 2)}
+
+
+def epoch_trace(pc, torch, synth, stream, reps=10):
+    """Where an epoch's time goes at 2^24 and 2^26 elements per rank (8
+    ranks, FP32, 64 partitions readied with one list call right after
+    start, cold: a 1 GiB fill before each epoch): the epoch's device time
+    from HIP events, and from the kernel's own per-workgroup wall-clock
+    trace (debug bit 1): the spread of workgroup starts, the time from the
+    first start until the first tile was queued, the time from that until
+    the first workgroup ran out of tiles (the streaming part), the spread
+    of the workgroups' ends (the last round of tiles), and the time outside
+    the kernel (events minus the kernel's span).  Medians over `reps`
+    epochs, in microseconds."""
+    import statistics
+    dev = torch.device("cuda:0")
+    P = 8
+    big = synth.normal_f32(P, 1 << 26, synth.seed_for(2), device=dev)
+    out = torch.empty(1 << 26, device=dev)
+    flush = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    res = {}
+    for k in (24, 26):
+        n = 1 << k
+        req = pc.Request([n], pc.FLOAT32, pc.SUM, 64, P)
+        req.set_config(debug=2)
+        req.bind([[b[:n] for b in big]], [out[:n]], stream=stream)
+        order = ready_array(synth.permutation(64, k * 100 + 64))
+        rows = []
+        for it in range(2 + reps):
+            pc.pcoll_probe_fill(flush, 4 << 28, 0, stream)
+            e0, e1 = _events(torch)
+            e0.record(stream)
+            req.start()
+            req.pready_list(order)
+            e1.record(stream)
+            stream.query()
+            req.wait()
+            e1.synchronize()
+            if it < 2:
+                continue
+            tr, khz = pc.pcoll_debug_trace(req.h)
+            us = 1e3 / khz  # microseconds per tick
+            st = [s for s, _, _, _ in tr]
+            fi = [f for _, f, _, _ in tr if f]
+            en = [e for _, _, e, _ in tr]
+            t0 = min(st)
+            rows.append({
+                "events_us": e0.elapsed_time(e1) * 1e3,
+                "kernel_span_us": (max(en) - t0) * us,
+                "start_spread_us": (max(st) - t0) * us,
+                "first_tile_queued_us": (min(fi) - t0) * us,
+                "streaming_us": (min(en) - min(fi)) * us,
+                "end_spread_us": (max(en) - min(en)) * us,
+                "tiles_per_group_min": min(t for _, _, _, t in tr),
+                "tiles_per_group_max": max(t for _, _, _, t in tr),
+            })
+        st = req.stats()
+        req.free()
+        rec = {key: round(statistics.median(r[key] for r in rows), 2)
+               for key in rows[0]}
+        rec["outside_kernel_us"] = round(rec["events_us"] -
+                                         rec["kernel_span_us"], 2)
+        rec["groups"] = st.groups
+        rec["GBps"] = round(36 * n / rec["events_us"] / 1e3, 1)
+        res[f"2^{k}"] = rec
+    del big, out, flush
+    torch.cuda.empty_cache()
+    return res
 
 
 def rank_readiness(pc, torch, synth, reps=5):
@@ -630,7 +728,7 @@ def only_workload(pc, torch, synth, name, warmup, steps):
 
 
 ONLY = ("batched_bf16", "batched_bf16_pair", "batched_fp32", "int32_sum",
-        "int32_max")
+        "int32_max", "epoch_trace", "size_sweep")
 
 
 def extras(pc, torch, synth, warmup, reps):
@@ -659,6 +757,7 @@ def extras(pc, torch, synth, warmup, reps):
     put("copy_probe", probe_copy, pc, torch, 10)
     put("stream_probe", probe_streams, pc, torch, 10)
     put("size_sweep", size_sweep, pc, torch, synth, stream)
+    put("epoch_trace", epoch_trace, pc, torch, synth, stream)
     put("rank_readiness", rank_readiness, pc, torch, synth)
     put("graph_lifecycle", graph_lifecycle, pc, torch)
 
@@ -820,6 +919,11 @@ def main():
                              errors=False)
         print(json.dumps({key: res}), flush=True)
         return
+    if args.only in ("epoch_trace", "size_sweep"):
+        fn = epoch_trace if args.only == "epoch_trace" else size_sweep
+        print(json.dumps({args.only: fn(pc, torch, synth,
+                                        torch.cuda.Stream(dev))}), flush=True)
+        return
     if args.only:
         print(json.dumps({args.only: only_workload(
             pc, torch, synth, args.only, args.warmup, args.steps)}),
@@ -867,7 +971,19 @@ def main():
            "mean": round(sum(step_ms) / len(step_ms), 4),
            "p10": round(step_ms[len(step_ms) // 10], 4),
            "p90": round(step_ms[(9 * len(step_ms)) // 10], 4)}
-    kernel_ms = sum(a.elapsed_time(b) for a, b in evs) / args.steps
+    # the epoch's device time between marker events (start .. readiness)
+    epoch_ms_events = sum(a.elapsed_time(b) for a, b in evs) / args.steps
+    # the kernel's own duration: the same steps again with debug timing
+    # (start and end stamped by the launch, no instrumentation in the
+    # kernel; it costs host time of its own, so `value` is taken without)
+    req.set_config(debug=4)
+    step()
+    st0 = req.stats()
+    for _ in range(args.steps):
+        step()
+    st1 = req.stats()
+    timed = st1.kernel_timed - st0.kernel_timed
+    kernel_ms = (st1.kernel_ms_total - st0.kernel_ms_total) / timed
 
     algo = P * n * 4 + n * 4
     value = algo / (ms_per_step * 1e-3) / 1e9
@@ -914,6 +1030,11 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBPS, 4),
             "traffic": traffic_record(algo),
             "kernel_ms": round(kernel_ms, 4),
+            "kernel_timing": f"{timed} launches after the timed steps, "
+                             "start and end stamped by the launch "
+                             "(hipExtLaunchKernel events on the kernel's "
+                             "stream)",
+            "epoch_ms_events": round(epoch_ms_events, 4),
             "algorithmic_bytes_per_launch": algo,
         },
     }

@@ -339,7 +339,11 @@ typedef struct {
                         default: an epoch is one kernel, so a graph has no
                         launches to save and its launch costs more) */
   int timeout_ms;    /* device-side deadline of one epoch */
-  int debug;         /* 1 = count tiles reduced per partition */
+  int debug;         /* bit 0: count tiles reduced per partition
+                        (pcoll_debug_tile_hits); bit 1: per-workgroup
+                        wall-clock trace (pcoll_debug_trace); bit 2: no
+                        instrumentation.  Any non-zero value also times
+                        the epoch's kernel (stats last_kernel_ms) */
   int interleave;    /* tile layout: 0 = each tile is a contiguous range of
                         its partition; otherwise tiles are interleaved in
                         bands of B consecutive tiles (1: B = the launch's
@@ -443,7 +447,13 @@ typedef struct {
   double last_capture_ms;     /* host time of the last capture */
   double last_instantiate_ms; /* host time of the last instantiation */
   float last_kernel_ms;       /* device time of the last epoch's kernel,
-                                 if debug timing was on, else -1 */
+                                 if the config field debug was non-zero,
+                                 else -1: from the kernel's own start to its
+                                 end for direct launches (events stamped by
+                                 hipExtLaunchKernel), from a marker before
+                                 the replay to one after it in graph mode */
+  double kernel_ms_total;     /* sum of the timed epochs' kernel times */
+  uint64_t kernel_timed;      /* epochs timed (debug non-zero) */
   int groups;                 /* workgroups of the last launch */
   int group_waves;            /* wavefronts per workgroup of the last launch */
   int unroll;                 /* rows in flight per lane of the last launch
@@ -458,6 +468,17 @@ int pcoll_get_stats(pcoll_req_t req, pcoll_stats_t *st);
  * exactly once). */
 int pcoll_debug_tile_hits(pcoll_req_t req, uint32_t *hits, uint32_t *tiles,
                           int n);
+
+/* Debug mode bit 1 only (config field debug): the trace of the last
+ * epoch, 4 words per workgroup of its launch -- the device wall clock when
+ * the workgroup started, when its first tile was queued (0 if none was),
+ * and when it found no tile left (or gave up), then the number of tiles it
+ * reduced -- copied to stamps[0..n) (n >= 4 * groups for all of them).
+ * *groups receives the launch's workgroup count and *clock_khz the wall
+ * clock's rate.  Waits for the epoch's kernel to retire.  PCOLL_ERR_STATE
+ * without the debug bit, while an epoch is active or before the first. */
+int pcoll_debug_trace(pcoll_req_t req, uint64_t *stamps, int n, int *groups,
+                      int *clock_khz);
 
 /* Test hook: clears every epoch stamp of the request (after waiting for the
  * whole device to go idle, so that no ready signal of an ended epoch is

@@ -52,12 +52,15 @@ UNROLL = (2, 4)
 # memory latency with more resident waves and longer tiles
 TILES_8BIT = (16384, 32768, 65536)
 GROUPS_PER_CU_8BIT = (2, 3)
+# consecutive rows per tile too: the rows that share a line of block
+# scales are then read by one workgroup
+INTERLEAVE_8BIT = (0, 1, 4, 8, 16)
 FALLBACK = "* * * * 0 63 8192 1 16 8 64 4"
 
 
 def grid_for(dtype, ranks=8):
     if dtype in (3, 4, 5):
-        return [TILES_8BIT, GROUPS_PER_CU_8BIT, INTERLEAVE, WAVES, BATCH,
+        return [TILES_8BIT, GROUPS_PER_CU_8BIT, INTERLEAVE_8BIT, WAVES, BATCH,
                 (4,)]
     return [TILES, GROUPS_PER_CU, INTERLEAVE, WAVES, BATCH,
             UNROLL if 3 <= ranks <= 8 else (4,)]

@@ -9,31 +9,29 @@
 namespace pcoll {
 
 hipError_t launch_reduce(const ReduceArgs& a, int dtype, int op, bool comp,
-                         bool deep, int nranks, int groups, int waves,
-                         hipStream_t s) {
-  if (nranks < 1 || nranks > kMaxRanks || groups < 1 || waves < 1 ||
-      waves > kMaxWavesPerGroup)
+                         bool deep, int nranks, const Launch& l) {
+  if (nranks < 1 || nranks > kMaxRanks || l.groups < 1 || l.waves < 1 ||
+      l.waves > kMaxWavesPerGroup)
     return hipErrorInvalidValue;
   switch (dtype) {
     case kF32:
-      return launch_reduce_f32(a, op, comp, deep, nranks, groups, waves, s);
+      return launch_reduce_f32(a, op, comp, deep, nranks, l);
     case kI32:
-      return launch_reduce_i32(a, op, deep, nranks, groups, waves, s);
+      return launch_reduce_i32(a, op, deep, nranks, l);
     case kBF16:
-      return launch_reduce_bf16(a, op, comp, deep, nranks, groups, waves, s);
+      return launch_reduce_bf16(a, op, comp, deep, nranks, l);
     case kE4M3:
       if (op != kSum) return hipErrorInvalidValue;
-      return launch_reduce_e4m3(a, comp, nranks, groups, waves, s);
+      return launch_reduce_e4m3(a, comp, nranks, l);
     case kE5M2:
       if (op != kSum) return hipErrorInvalidValue;
-      return launch_reduce_e5m2(a, comp, nranks, groups, waves, s);
+      return launch_reduce_e5m2(a, comp, nranks, l);
     case kMX:
       if (op != kSum) return hipErrorInvalidValue;
-      return launch_reduce_mx(a, comp, nranks, groups, waves, s);
+      return launch_reduce_mx(a, comp, nranks, l);
     case kBF16Pair:
       if (op != kSum) return hipErrorInvalidValue;
-      return launch_reduce_bf16_pair(a, comp, deep, nranks, groups, waves,
-                                     s);
+      return launch_reduce_bf16_pair(a, comp, deep, nranks, l);
     default:
       return hipErrorInvalidValue;
   }

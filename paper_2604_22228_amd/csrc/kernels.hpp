@@ -28,13 +28,23 @@ inline int elem_bytes(int dtype) {
                                : 4);
 }
 
-// The persistent partitioned-reduce kernel: `groups` workgroups of `waves`
-// wavefronts; deep: 4 rows per lane in flight in the 16-byte-vector
-// kernels at 3..8 ranks (else 2).  Returns hipErrorInvalidValue for an
-// unsupported (dtype, op, comp, nranks) combination.
+// Launch shape of the persistent kernel: `groups` workgroups of `waves`
+// wavefronts on `stream`; with start / stop events, those are stamped at
+// the kernel's own start and end (hipExtLaunchKernel).
+struct Launch {
+  int groups;
+  int waves;
+  hipStream_t stream;
+  hipEvent_t start;
+  hipEvent_t stop;
+};
+
+// The persistent partitioned-reduce kernel; deep: 4 rows per lane in
+// flight in the 16-byte-vector kernels at 3..8 ranks (else 2).  Returns
+// hipErrorInvalidValue for an unsupported (dtype, op, comp, nranks)
+// combination.
 hipError_t launch_reduce(const ReduceArgs& a, int dtype, int op, bool comp,
-                         bool deep, int nranks, int groups, int waves,
-                         hipStream_t s);
+                         bool deep, int nranks, const Launch& l);
 // Device-side readiness: appends `a.n` partition ids to the device ready
 // ring.
 hipError_t launch_pready(const PreadyArgs& a, hipStream_t s);

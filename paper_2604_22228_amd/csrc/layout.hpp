@@ -141,6 +141,9 @@ struct ReduceArgs {
   uint32_t epoch;          // stamp of this launch, or 0: read it from the
                            // host struct (a graph replays fixed arguments)
   uint64_t timeout_ticks; // device wall-clock ticks before giving up
+  uint64_t* trace;        // debug: per workgroup 4 words (wall-clock at
+                          // entry, when its first tile was queued, after
+                          // its last tile; tiles reduced), or null
 };
 
 // Where a device-side ready signal appends: the rings of the request, and

@@ -583,12 +583,22 @@ __device__ __forceinline__ void persistent_loop(const ReduceArgs& args) {
   uint32_t next = 0;
   uint64_t qs = 0;          // queue state last acquired (wavefront 0)
   uint32_t npend = 0;       // finished tiles not yet published (wavefront 0)
+  uint32_t ntiles = 0;      // tiles reduced (wavefront 0, for the trace)
+  uint64_t t_first = 0;     // when the first tile was queued (trace)
   for (;;) {
     if (wave == 0) {
       TileJob j{~0u, 0u, 0u};
       const WaitResult w = wait_queued(a, t, epoch, t0, qs, [&] {
         publish(a, pend, npend, epoch);
       });
+      if (a.trace && ntiles == 0 && w == kReady) t_first = wall_clock64();
+      if (a.trace && w != kReady && lane_id() == 0) {
+        uint64_t* s = a.trace + (size_t)blockIdx.x * 4u;
+        s[0] = t0;
+        s[1] = t_first;
+        s[2] = wall_clock64();
+        s[3] = ntiles;
+      }
       if (w == kReady) {
         locate(a, t, (uint32_t)(qs >> 32), cursor, prev_end, cur_part,
                cur_end);
@@ -617,6 +627,7 @@ __device__ __forceinline__ void persistent_loop(const ReduceArgs& args) {
     if (wave == 0) {
       if (lane_id() == 0) pend[npend] = Pending{j.part, j.nt};
       ++npend;
+      ++ntiles;
       if (npend >= a.publish_batch) publish(a, pend, npend, epoch);
       t = uni(next);
     }

@@ -2,10 +2,9 @@
 #include "reduce_impl.hpp"
 
 namespace pcoll {
-hipError_t launch_reduce_e5m2(const ReduceArgs& a, bool comp, int nranks,
-                              int groups, int waves, hipStream_t s) {
+hipError_t launch_reduce_e5m2(const ReduceArgs& a, bool comp, int nranks, const Launch& l) {
   using namespace dev;
-  if (comp) return launch_ranks<E5M2Tile<true>>(a, nranks, groups, waves, s);
-  return launch_ranks<E5M2Tile<false>>(a, nranks, groups, waves, s);
+  if (comp) return launch_ranks<E5M2Tile<true>>(a, nranks, l);
+  return launch_ranks<E5M2Tile<false>>(a, nranks, l);
 }
 }  // namespace pcoll

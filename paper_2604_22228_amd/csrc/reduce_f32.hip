@@ -4,18 +4,17 @@
 namespace pcoll {
 namespace {
 template <bool D>
-hipError_t f32(const ReduceArgs& a, int op, bool comp, int nranks, int groups,
-               int waves, hipStream_t s) {
+hipError_t f32(const ReduceArgs& a, int op, bool comp, int nranks, const Launch& l) {
   using namespace dev;
-  if (op == kMax) return launch_ranks<VecTile<FMax, 0, D>>(a, nranks, groups, waves, s);
-  if (comp) return launch_ranks<VecTile<FSum<true>, 0, D>>(a, nranks, groups, waves, s);
-  return launch_ranks<VecTile<FSum<false>, 0, D>>(a, nranks, groups, waves, s);
+  if (op == kMax) return launch_ranks<VecTile<FMax, 0, D>>(a, nranks, l);
+  if (comp) return launch_ranks<VecTile<FSum<true>, 0, D>>(a, nranks, l);
+  return launch_ranks<VecTile<FSum<false>, 0, D>>(a, nranks, l);
 }
 }  // namespace
 
 hipError_t launch_reduce_f32(const ReduceArgs& a, int op, bool comp, bool deep,
-                             int nranks, int groups, int waves, hipStream_t s) {
-  return deep ? f32<true>(a, op, comp, nranks, groups, waves, s)
-              : f32<false>(a, op, comp, nranks, groups, waves, s);
+                             int nranks, const Launch& l) {
+  return deep ? f32<true>(a, op, comp, nranks, l)
+              : f32<false>(a, op, comp, nranks, l);
 }
 }  // namespace pcoll

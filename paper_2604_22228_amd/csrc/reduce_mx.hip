@@ -3,10 +3,9 @@
 #include "reduce_impl.hpp"
 
 namespace pcoll {
-hipError_t launch_reduce_mx(const ReduceArgs& a, bool comp, int nranks,
-                            int groups, int waves, hipStream_t s) {
+hipError_t launch_reduce_mx(const ReduceArgs& a, bool comp, int nranks, const Launch& l) {
   using namespace dev;
-  if (comp) return launch_ranks<MxTile<true>>(a, nranks, groups, waves, s);
-  return launch_ranks<MxTile<false>>(a, nranks, groups, waves, s);
+  if (comp) return launch_ranks<MxTile<true>>(a, nranks, l);
+  return launch_ranks<MxTile<false>>(a, nranks, l);
 }
 }  // namespace pcoll

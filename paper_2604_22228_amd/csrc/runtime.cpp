@@ -172,6 +172,8 @@ struct pcoll_req_s {
   uint64_t* d_dlist = nullptr;       // [2][partitions] device ready rings
   uint32_t* d_dstamp = nullptr;      // [partitions] last epoch appended
   uint64_t* d_rank_marks = nullptr;  // [partitions] device per-rank marks
+  uint64_t* d_trace = nullptr;       // debug trace: [trace_cap][4]
+  int trace_cap = 0;
   EpochCounters* d_ctr = nullptr;  // [2]
   RingCounters* d_ring = nullptr;  // [2]
 
@@ -181,9 +183,17 @@ struct pcoll_req_s {
   Binding* cur = nullptr;
   std::unique_ptr<LruCache<BindKey, Binding, BindKeyHash>> cache;
   hipStream_t capture_stream = nullptr;
-  hipEvent_t ev_start = nullptr, ev_end = nullptr;
+  hipEvent_t ev_end = nullptr;
+  // debug timing: per epoch a pair of events, stamped at a direct
+  // launch's own start and end (no marker packets, which add microseconds
+  // of their own), or markers around a graph replay; kTimers pairs in
+  // turn, collected once complete, so that no epoch waits for the last
+  // one's kernel to retire
+  static constexpr int kTimers = 8;
+  hipEvent_t ev_t[kTimers][2] = {};
+  bool t_pending[kTimers] = {};
+  int t_next = 0;
   bool ev_end_recorded = false;
-  bool ev_start_recorded = false;
 
   uint32_t epoch = 0;
   bool active = false;
@@ -296,7 +306,7 @@ int validate_config(const pcoll_req_s* r, const pcoll_config_t& c) {
     return PCOLL_ERR_ARG;
   if (c.graph != 0 && c.graph != 1) return PCOLL_ERR_ARG;
   if (c.timeout_ms < 1 || c.timeout_ms > 3600 * 1000) return PCOLL_ERR_ARG;
-  if (c.debug != 0 && c.debug != 1) return PCOLL_ERR_ARG;
+  if (c.debug < 0 || c.debug > 7) return PCOLL_ERR_ARG;
   if (c.interleave < 0 || c.interleave > (1 << 20)) return PCOLL_ERR_ARG;
   if (c.guide < 0 || c.guide > 64) return PCOLL_ERR_ARG;
   if (c.unroll != 2 && c.unroll != 4) return PCOLL_ERR_ARG;
@@ -361,6 +371,16 @@ int apply_config(pcoll_req_t r, const pcoll_config_t& c) {
                                    [&](uint32_t k) { return r->parts[k].rows; });
   rc = drain(r);
   if (rc) return rc;
+  if ((c.debug & 2) && groups > r->trace_cap) {  // the trace's records
+    void* p = nullptr;
+    const hipError_t e = hipMalloc(&p, sizeof(uint64_t) * 4 * (size_t)groups);
+    if (e != hipSuccess)
+      return e == hipErrorOutOfMemory ? PCOLL_ERR_NOMEM
+                                      : hip_fail(e, "hipMalloc(trace)");
+    if (r->d_trace) (void)hipFree(r->d_trace);
+    r->d_trace = static_cast<uint64_t*>(p);
+    r->trace_cap = groups;
+  }
   r->cfg = c;
   r->groups = groups;
   r->waves = waves;
@@ -401,7 +421,7 @@ pcoll_config_t config_for(int dtype, int op, int nranks, uint64_t bytes) {
   comp = env_int("PCOLL_COMP", comp);
   c.comp = float_sum && comp ? 1 : 0;
   c.timeout_ms = env_int("PCOLL_TIMEOUT_MS", 10000);
-  c.debug = env_int("PCOLL_DEBUG", 0) ? 1 : 0;
+  c.debug = env_int("PCOLL_DEBUG", 0) & 7;
   c.producers = env_int("PCOLL_PRODUCERS", -1);
   if (c.producers < -1 || c.producers > 1) c.producers = -1;
   return c;
@@ -420,9 +440,12 @@ void destroy(pcoll_req_t r) {
   (void)drain(r);
   r->cache.reset();
   if (r->capture_stream) (void)hipStreamDestroy(r->capture_stream);
-  if (r->ev_start) (void)hipEventDestroy(r->ev_start);
+  for (auto& pair : r->ev_t)
+    for (hipEvent_t ev : pair)
+      if (ev) (void)hipEventDestroy(ev);
   if (r->ev_end) (void)hipEventDestroy(r->ev_end);
   if (r->arena) (void)hipFree(r->arena);
+  if (r->d_trace) (void)hipFree(r->d_trace);
   if (r->host) (void)hipHostFree(r->host);
   delete r;
 }
@@ -542,7 +565,9 @@ int create(const std::vector<uint64_t>& counts, int dtype, int op,
 
   HIP_TRY(hipStreamCreateWithFlags(&r->capture_stream, hipStreamNonBlocking));
   HIP_TRY(hipEventCreateWithFlags(&r->ev_end, hipEventDefault));
-  HIP_TRY(hipEventCreateWithFlags(&r->ev_start, hipEventDefault));
+  for (auto& pair : r->ev_t)
+    for (hipEvent_t& ev : pair)
+      HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDefault));
   const int cap = std::max(1, env_int("PCOLL_GRAPH_CACHE", 8));
   r->cache.reset(new LruCache<BindKey, Binding, BindKeyHash>(
       (size_t)cap, [](const BindKey&, Binding& b) { dispose_binding(b); }));
@@ -561,7 +586,7 @@ ReduceArgs make_args(const pcoll_req_s* r) {
   a.queue = r->d_queue;
   a.done = r->d_done;
   a.queued = r->d_queued;
-  a.tile_hits = r->cfg.debug ? r->d_hits : nullptr;
+  a.tile_hits = (r->cfg.debug & 1) ? r->d_hits : nullptr;
   a.dlist = r->d_dlist;
   a.ctr = r->d_ctr;
   a.ring = r->d_ring;
@@ -580,7 +605,8 @@ ReduceArgs make_args(const pcoll_req_s* r) {
   // 1 = bands as wide as the launch: the tiles of one round of claims
   a.interleave = r->cfg.interleave == 1 ? (uint32_t)r->groups
                                          : (uint32_t)r->cfg.interleave;
-  a.tile_counts = r->cfg.debug ? r->d_tiles : nullptr;
+  a.tile_counts = (r->cfg.debug & 1) ? r->d_tiles : nullptr;
+  a.trace = (r->cfg.debug & 2) ? r->d_trace : nullptr;
   a.guide = (uint32_t)r->cfg.guide;
   a.publish_batch = (uint32_t)r->cfg.publish_batch;
   a.timeout_ticks = (uint64_t)r->cfg.timeout_ms * (uint64_t)r->clock_khz;
@@ -589,11 +615,13 @@ ReduceArgs make_args(const pcoll_req_s* r) {
 
 // One launch per epoch.  epoch == 0 makes the kernel read the stamp from
 // the host struct (for graphs, whose arguments are fixed at capture).
-int launch_direct(pcoll_req_t r, hipStream_t s, uint32_t epoch) {
+int launch_direct(pcoll_req_t r, hipStream_t s, uint32_t epoch,
+                  hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr) {
   ReduceArgs a = make_args(r);
   a.epoch = epoch;
+  const Launch l{r->groups, r->waves, s, t0, t1};
   HIP_TRY(launch_reduce(a, r->dtype, r->op, r->cfg.comp != 0, r->deep,
-                        r->nranks, r->groups, r->waves, s));
+                        r->nranks, l));
   return PCOLL_SUCCESS;
 }
 
@@ -689,11 +717,27 @@ int finish_epoch(pcoll_req_t r, uint32_t st) {
     HIP_TRY(hipEventSynchronize(r->ev_end));
     return st == kStatusTimeout ? PCOLL_ERR_ABORTED : PCOLL_ERR_TIMEOUT;
   }
-  if (r->cfg.debug && r->ev_start_recorded) {
+  return PCOLL_SUCCESS;
+}
+
+// Debug timing: adds the times of the timed epochs whose events have
+// completed (all of them, waiting, with `wait`; pair `need` at least).
+int collect_timing(pcoll_req_t r, bool wait, int need = -1) {
+  for (int k = 0; k < pcoll_req_s::kTimers; ++k) {
+    const int i = (r->t_next + k) % pcoll_req_s::kTimers;  // oldest first
+    if (!r->t_pending[i]) continue;
+    if (!wait && i != need) {
+      const hipError_t q = hipEventQuery(r->ev_t[i][1]);
+      if (q == hipErrorNotReady) continue;
+      if (q != hipSuccess) return hip_fail(q, "hipEventQuery");
+    }
+    HIP_TRY(hipEventSynchronize(r->ev_t[i][1]));
     float ms = -1.0f;
-    if (hipEventSynchronize(r->ev_end) == hipSuccess &&
-        hipEventElapsedTime(&ms, r->ev_start, r->ev_end) == hipSuccess)
-      r->stats.last_kernel_ms = ms;
+    HIP_TRY(hipEventElapsedTime(&ms, r->ev_t[i][0], r->ev_t[i][1]));
+    r->t_pending[i] = false;
+    r->stats.last_kernel_ms = ms;
+    r->stats.kernel_ms_total += ms;
+    r->stats.kernel_timed++;
   }
   return PCOLL_SUCCESS;
 }
@@ -899,6 +943,10 @@ int pcoll_start(pcoll_req_t r) {
   // epoch 0 means "read the stamp from host memory" to the kernel, and the
   // counter sets alternate by parity: after wrapping, continue at 2, from
   // cleared stamps
+  if (r->cfg.debug) {  // completed timings; the pair this epoch reuses
+    const int rc = collect_timing(r, false, r->t_next);
+    if (rc) return rc;
+  }
   // the first device-side signal of a request in the automatic producer
   // mode: leave room from this launch on
   if (r->room_pending) {
@@ -921,16 +969,25 @@ int pcoll_start(pcoll_req_t r) {
   __atomic_store_n(&r->host->epoch, e, __ATOMIC_RELEASE);
   r->hcount = 0;
   r->scan = 0;
-  if (r->cfg.debug) {
+  hipEvent_t* tp = r->cfg.debug ? r->ev_t[r->t_next] : nullptr;
+  if (r->cfg.debug & 1) {
     HIP_TRY(hipMemsetAsync(r->d_hits, 0, sizeof(uint32_t) * r->nparts_total,
                            r->stream));
     HIP_TRY(hipMemsetAsync(r->d_tiles, 0, sizeof(uint32_t) * r->nparts_total,
                            r->stream));
-    HIP_TRY(hipEventRecord(r->ev_start, r->stream));
-    r->ev_start_recorded = true;
   }
-  int rc = r->cfg.graph ? launch_graph(r) : launch_direct(r, r->stream, e);
+  // a graph replay is timed by markers around it
+  if (tp && r->cfg.graph) HIP_TRY(hipEventRecord(tp[0], r->stream));
+  int rc = r->cfg.graph ? launch_graph(r)
+                        : launch_direct(r, r->stream, e,
+                                        tp ? tp[0] : nullptr,
+                                        tp ? tp[1] : nullptr);
   if (rc) return rc;
+  if (tp && r->cfg.graph) HIP_TRY(hipEventRecord(tp[1], r->stream));
+  if (tp) {
+    r->t_pending[r->t_next] = true;
+    r->t_next = (r->t_next + 1) % pcoll_req_s::kTimers;
+  }
   HIP_TRY(hipEventRecord(r->ev_end, r->stream));
   // the kernel starts now, not when the host next looks at the stream: it
   // then runs while the host issues the epoch's ready signals
@@ -1246,8 +1303,8 @@ int pcoll_reduce_noalloc(size_t count, pcoll_dtype_t dtype_, pcoll_op_t op_,
   a.publish_batch = (uint32_t)c.publish_batch;
   a.epoch = s.epoch;
   a.timeout_ticks = (uint64_t)c.timeout_ms * (uint64_t)khz;
-  HIP_TRY(launch_reduce(a, dtype, op, c.comp != 0, c.unroll != 2, nranks,
-                        groups, c.group_waves, st));
+  const Launch l{groups, c.group_waves, st, nullptr, nullptr};
+  HIP_TRY(launch_reduce(a, dtype, op, c.comp != 0, c.unroll != 2, nranks, l));
   return PCOLL_SUCCESS;
 }
 
@@ -1286,6 +1343,10 @@ int pcoll_part_info(pcoll_req_t r, int part, int* bucket, size_t* offset,
 
 int pcoll_get_stats(pcoll_req_t r, pcoll_stats_t* st) {
   if (check_req(r) || !st) return PCOLL_ERR_ARG;
+  if (!r->active) {
+    const int rc = collect_timing(r, true);
+    if (rc) return rc;
+  }
   *st = r->stats;
   return PCOLL_SUCCESS;
 }
@@ -1297,11 +1358,28 @@ int pcoll_debug_set_epoch(pcoll_req_t r, uint32_t last) {
   return reset_epoch_state(r, last);
 }
 
+int pcoll_debug_trace(pcoll_req_t r, uint64_t* stamps, int n, int* groups,
+                      int* clock_khz) {
+  if (check_req(r) || n < 0 || (n > 0 && !stamps)) return PCOLL_ERR_ARG;
+  if (!(r->cfg.debug & 2) || r->active || r->epoch == 0)
+    return PCOLL_ERR_STATE;
+  HIP_TRY(hipSetDevice(r->device));
+  const int rc = drain(r);
+  if (rc) return rc;
+  const size_t words = std::min<size_t>((size_t)n, 4 * (size_t)r->groups);
+  if (words)
+    HIP_TRY(hipMemcpy(stamps, r->d_trace, sizeof(uint64_t) * words,
+                      hipMemcpyDeviceToHost));
+  if (groups) *groups = r->groups;
+  if (clock_khz) *clock_khz = r->clock_khz;
+  return PCOLL_SUCCESS;
+}
+
 int pcoll_debug_tile_hits(pcoll_req_t r, uint32_t* hits, uint32_t* tiles,
                           int n) {
   if (check_req(r) || !hits || !tiles || n < (int)r->nparts_total)
     return PCOLL_ERR_ARG;
-  if (!r->cfg.debug || r->active) return PCOLL_ERR_STATE;
+  if (!(r->cfg.debug & 1) || r->active) return PCOLL_ERR_STATE;
   HIP_TRY(hipSetDevice(r->device));
   int rc = drain(r);
   if (rc) return rc;

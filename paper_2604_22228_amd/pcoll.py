@@ -57,7 +57,9 @@ class Stats(C.Structure):
                 ("cache_evictions", C.c_uint64),
                 ("last_capture_ms", C.c_double),
                 ("last_instantiate_ms", C.c_double),
-                ("last_kernel_ms", C.c_float), ("groups", C.c_int),
+                ("last_kernel_ms", C.c_float),
+                ("kernel_ms_total", C.c_double),
+                ("kernel_timed", C.c_uint64), ("groups", C.c_int),
                 ("group_waves", C.c_int), ("unroll", C.c_int)]
 
     def as_dict(self):
@@ -94,6 +96,8 @@ _SIGS = {
     "pcoll_debug_tile_hits": [_p, C.POINTER(C.c_uint32),
                               C.POINTER(C.c_uint32), _i],
     "pcoll_debug_set_epoch": [_p, C.c_uint32],
+    "pcoll_debug_trace": [_p, C.POINTER(C.c_uint64), _i, C.POINTER(_i),
+                          C.POINTER(_i)],
     "pcoll_reduce_noalloc": [_sz, _i, _i, _i, _i, C.POINTER(_p), _p,
                              C.POINTER(_p), _p, _p],
     "pcoll_plan": [_sz, _i, _i, C.POINTER(_sz), C.POINTER(_sz),
@@ -296,6 +300,17 @@ def pcoll_debug_tile_hits(h, n):
     _check(load().pcoll_debug_tile_hits(h, hits, tiles, n),
            "pcoll_debug_tile_hits")
     return list(hits), list(tiles)
+
+
+def pcoll_debug_trace(h, max_groups=4096):
+    """(stamps as a list of (start, first tile, end, tiles) per workgroup,
+    wall-clock kHz) of the last epoch."""
+    buf = (C.c_uint64 * (4 * max_groups))()
+    g, khz = _i(), _i()
+    _check(load().pcoll_debug_trace(h, buf, 4 * max_groups, C.byref(g),
+                                    C.byref(khz)), "pcoll_debug_trace")
+    n = min(g.value, max_groups)
+    return [tuple(buf[4 * i:4 * i + 4]) for i in range(n)], khz.value
 
 
 def pcoll_debug_set_epoch(h, last):
