@@ -27,11 +27,11 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, published
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles",
                                "reduce_f32_p8_256MiB_traffic.json")
-# what the counted launch depends on: the kernel's sources and the tuned
-# launch parameters
+# what the counted launch depends on: the kernel's sources, the code that
+# sizes its grid and the tuned launch parameters
 KERNEL_SOURCES = ["csrc/persistent.hpp", "csrc/tiles.hpp",
                   "csrc/reduce_impl.hpp", "csrc/reduce_f32.hip",
-                  "csrc/layout.hpp", "tuned_mi355x.txt"]
+                  "csrc/layout.hpp", "csrc/runtime.cpp", "tuned_mi355x.txt"]
 
 
 def kernel_hash():
@@ -133,10 +133,10 @@ def probe_streams(pc, torch, steps, P=8, log2n=26):
                 "bytes_per_launch": total, "ms": round(ms, 4),
                 "GBps": round(total / (ms * 1e-3) / 1e9, 1)}
     res["streams"] = f"{P} reads of {nbytes >> 20} MiB (+ 1 write)"
-    res["layouts"] = ("tiles: the headline reduce's schedule (8192-element "
-                      "tiles in bands of 16, 2 workgroups of 8 waves per "
-                      "compute unit, tiles taken in turn) without its "
-                      "protocol; grid_stride: thread i takes vectors i, "
+    res["layouts"] = ("tiles: the headline reduce's tile schedule "
+                      "(8192-element tiles in bands of 16, taken in turn) "
+                      "without its protocol, on 2 workgroups of 8 waves per "
+                      "compute unit; grid_stride: thread i takes vectors i, "
                       "i + T, ...")
     del srcs, dst
     torch.cuda.empty_cache()
@@ -220,6 +220,30 @@ def time_requests(torch, reqs, orders, stream, warmup, reps):
         devt = [(st1.kernel_ms_total - st0.kernel_ms_total) /
                 max(st1.kernel_timed - st0.kernel_timed, 1)]
     return statistics.median(host), statistics.median(devt)
+
+
+def trace_span_ms(pc, torch, req, order, stream, reps):
+    """The kernel's own span (first workgroup start to last workgroup end)
+    from its per-workgroup wall-clock trace (debug bit 2), median over
+    `reps` epochs after one warmup.  It works for graph replays too, where
+    no launch events can stamp the kernel."""
+    import statistics
+    dbg = req.config().debug
+    req.set_config(debug=dbg | 2)
+    spans = []
+    for it in range(1 + reps):
+        torch.cuda.synchronize()
+        req.start()
+        req.pready_list(order)
+        stream.query()
+        req.wait()
+        torch.cuda.synchronize()  # the last workgroup's stamp is written
+        if it:
+            tr, khz = pc.pcoll_debug_trace(req.h)
+            spans.append((max(e for _, _, e, _ in tr) -
+                          min(s for s, _, _, _ in tr)) / khz)
+    req.set_config(debug=dbg)
+    return statistics.median(spans)
 
 
 def _time_pass(torch, reqs, orders, stream, warmup, reps):
@@ -464,6 +488,141 @@ def rank_readiness(pc, torch, synth, reps=5):
     return res
 
 
+def staggered_arrivals(pc, torch, synth, reps=5, gap_us=50.0):
+    """Stragglers, the case per-rank readiness is for: 8 ranks, FP32, 2^26
+    elements per rank (inputs resident), 8 or 64 partitions; rank r's
+    partition j arrives at (j + lag_r) x D (partitions in order, as a
+    backward pass emits gradient buckets; lag_r a seeded per-rank lag of up
+    to 3, D = `gap_us`).  The arrivals are played on a side stream (one
+    that runs beside the reduce kernel's) as timed spins in arrival order,
+    each followed by a one-element kernel: the mark
+    (pcoll_pready_rank_on_stream of that rank and partition) where the mode
+    marks per arrival, else a one-element torch kernel, so that every mode
+    plays the same kernels.  The whole schedule is enqueued behind a gate
+    spin longer than the host takes to enqueue it, so the device sets the
+    pace (`device_paced`: the gate was still running when the host was
+    done, in every epoch).  Three ways to ready the partitions:
+      per_rank: the reduce starts first and each arrival is marked right
+        after its spin, so a partition is reduced as soon as its last rank
+        has arrived;
+      bulk_marked: the reduce starts first, but every partition is marked
+        once, after the last arrival (pcoll_pready_on_stream of all);
+      bulk_started: the reduce is launched after the last arrival (its
+        stream waits for it), every partition ready (a reduction that
+        begins when its data are complete).
+    Device times from HIP events: `window_us` from the end of the gate to
+    the last arrival, `after_last_us` from the last arrival to the end of
+    the reduce (what readiness per rank hides), `epoch_us` from the end of
+    the gate to the end of the reduce; medians over `reps` epochs.
+    `identical`: every epoch of every mode gives the same output bits.  The
+    reduce runs in its tuned launch (producers = 0): the spins and marks
+    are small kernels."""
+    import statistics
+    dev = torch.device("cuda:0")
+    P, n = 8, 1 << 26
+    xs = synth.normal_f32(P, n, synth.seed_for(2) + 5, device=dev)
+    out = torch.empty(n, device=dev)
+    one = torch.zeros(1, device=dev)
+    from paper_2604_22228_amd.streams import independent_streams
+    stream = torch.cuda.Stream(dev)
+    side = independent_streams(stream, 1)[0]
+    rng = np.random.default_rng(synth.seed_for(2) + 11)
+    lag = rng.uniform(0.0, 3.0, size=P)  # in units of D
+    # spin cycles per microsecond: torch's spin counts shader clocks
+    cyc_us = 2000
+    res = {"gap_us": gap_us, "rank_lag_in_gaps": [round(float(x), 3)
+                                                  for x in lag]}
+    ref = None
+    identical = paced = True
+    for nparts in (8, 64):
+        req = pc.Request([n], pc.FLOAT32, pc.SUM, nparts, P)
+        req.set_config(producers=0)
+        req.bind([xs], [out], stream=stream)
+        ids = torch.arange(nparts, dtype=torch.int32, device=dev)
+        arrivals = sorted((j + lag[r], r, j) for r in range(P)
+                          for j in range(nparts))
+        allp = ready_array(range(nparts))
+        gate_ms = 5.0
+        torch.cuda.synchronize()
+
+        def play(mark):
+            t = 0.0
+            for when, r, j in arrivals:
+                cycles = int((when - t) * gap_us * cyc_us)
+                t = when
+                with torch.cuda.stream(side):
+                    if cycles > 0:
+                        torch.cuda._sleep(cycles)
+                    if not mark:
+                        one.add_(1.0)
+                if mark:
+                    req.pready_rank_on_stream(r, ids[j:j + 1], 1, side)
+
+        rec = {}
+        for mode in ("per_rank", "bulk_marked", "bulk_started"):
+            window, after, whole = [], [], []
+            for it in range(2 + reps):
+                out.fill_(float("nan"))
+                torch.cuda.synchronize()
+                e0, e_last = _events(torch)
+                e_done = torch.cuda.Event(enable_timing=True)
+                if mode != "bulk_started":
+                    req.start()
+                    e_done.record(stream)
+                    stream.query()  # submits the launch now
+                h0 = time.perf_counter()
+                with torch.cuda.stream(side):
+                    torch.cuda._sleep(int(gate_ms * 1e3 * cyc_us))
+                e0.record(side)
+                side.query()  # the gate starts now
+                play(mode == "per_rank")
+                e_last.record(side)
+                side.query()  # submits what is still held back
+                gate_open = e0.query()
+                enq_ms = (time.perf_counter() - h0) * 1e3
+                if mode == "bulk_marked":
+                    req.pready_on_stream(ids, nparts, side)
+                side.query()
+                if mode == "bulk_started":
+                    stream.wait_event(e_last)
+                    req.start()
+                    req.pready_list(allp)
+                    e_done.record(stream)
+                    stream.query()
+                req.wait()
+                torch.cuda.synchronize()
+                gate_ms = max(gate_ms, 2.0 * enq_ms)
+                if it < 2:
+                    continue
+                paced = paced and not gate_open
+                window.append(e0.elapsed_time(e_last) * 1e3)
+                after.append(e_last.elapsed_time(e_done) * 1e3)
+                whole.append(e0.elapsed_time(e_done) * 1e3)
+                if ref is None:
+                    ref = out.clone()
+                elif not torch.equal(out, ref):
+                    identical = False
+            rec[mode] = {"window_us": round(statistics.median(window), 1),
+                         "after_last_us": round(statistics.median(after), 1),
+                         "epoch_us": round(statistics.median(whole), 1)}
+        for b in ("bulk_started", "bulk_marked"):
+            rec[f"after_last_speedup_vs_{b}"] = round(
+                rec[b]["after_last_us"] / rec["per_rank"]["after_last_us"], 2)
+            rec[f"epoch_speedup_vs_{b}"] = round(
+                rec[b]["epoch_us"] / rec["per_rank"]["epoch_us"], 3)
+        st = req.stats()
+        rec["groups"], rec["group_waves"] = st.groups, st.group_waves
+        req.free()
+        res[f"{nparts}_partitions"] = rec
+    res["identical"] = identical
+    res["device_paced"] = paced
+    res["workload"] = ("8 ranks, FP32, 2^26 elements per rank, rank r's "
+                       "partition j arriving at (j + lag_r) x gap_us")
+    del xs, out, ref
+    torch.cuda.empty_cache()
+    return res
+
+
 def graph_lifecycle(pc, torch, reps=20):
     """Graph against direct launch over bucket counts (equal buckets, FP32,
     8 ranks) at 2 MiB and 512 MiB per rank: bind (descriptor table upload),
@@ -684,7 +843,8 @@ def _bf16_buckets(pc, torch, synth, dev):
 
 def only_workload(pc, torch, synth, name, warmup, steps):
     """One workload alone, for profiling: the batched bf16 buckets (8
-    ranks, 64 buckets, 32 partitions each) as bf16, bf16 pairs or FP32, or
+    ranks, 64 buckets, 32 partitions each) as bf16 (direct launch or graph
+    replay), bf16 pairs or FP32, or
     int32 sum / max at 16 ranks and 2^24 elements (256 partitions).  Same
     inputs, readiness order and timing as the extras."""
     dev = torch.device("cuda:0")
@@ -717,18 +877,22 @@ def only_workload(pc, torch, synth, name, warmup, steps):
     lo = [torch.empty(c, dtype=torch.int16, device=dev) for c in counts] \
         if dt == pc.BF16_PAIR else None
     r = pc.Request(counts, dt, pc.SUM, 32, 8, batched=True)
+    if name == "batched_bf16_graph":
+        r.set_config(graph=1)
     r.bind(ins, outs, out_scales=lo, stream=stream)
     h, d = time_requests(torch, [r], [order], stream, warmup, steps)
     cfg = r.config()
-    res = {"host_ms": round(h, 4), "kernel_ms": round(d, 4),
+    res = {"host_ms": round(h, 4),
+           "events_ms" if cfg.graph else "kernel_ms": round(d, 4),
            "GBps": round(nb / d / 1e6, 1), "tile_elems": cfg.tile_elems,
            "group_waves": cfg.group_waves, "groups": r.stats().groups}
     r.free()
     return res
 
 
-ONLY = ("batched_bf16", "batched_bf16_pair", "batched_fp32", "int32_sum",
-        "int32_max", "epoch_trace", "size_sweep")
+ONLY = ("batched_bf16", "batched_bf16_graph", "batched_bf16_pair",
+        "batched_fp32", "int32_sum", "int32_max", "epoch_trace",
+        "size_sweep", "staggered_arrivals", "rank_readiness")
 
 
 def extras(pc, torch, synth, warmup, reps):
@@ -759,6 +923,7 @@ def extras(pc, torch, synth, warmup, reps):
     put("size_sweep", size_sweep, pc, torch, synth, stream)
     put("epoch_trace", epoch_trace, pc, torch, synth, stream)
     put("rank_readiness", rank_readiness, pc, torch, synth)
+    put("staggered_arrivals", staggered_arrivals, pc, torch, synth)
     put("graph_lifecycle", graph_lifecycle, pc, torch)
 
     def w1():
@@ -805,7 +970,12 @@ def extras(pc, torch, synth, warmup, reps):
             rb.bind(bf, yb, stream=stream)
             h, d = time_requests(torch, [rb], [order], stream, warmup, reps)
             st = rb.stats()
-            res[key] = {"host_ms": round(h, 4), "kernel_ms": round(d, 4),
+            span = trace_span_ms(pc, torch, rb, order, stream, reps)
+            # direct: the kernel's own time from its launch events; graph:
+            # HIP events around the replay and the readiness call
+            res[key] = {"host_ms": round(h, 4),
+                        "events_ms" if graph else "kernel_ms": round(d, 4),
+                        "kernel_span_ms": round(span, 4),
                         "GBps": round(n_el * 2 * (P + 1) / d / 1e6, 1),
                         "graph": rb.config().graph}
             if graph:
@@ -855,6 +1025,9 @@ def extras(pc, torch, synth, warmup, reps):
                                "kernel_ms": round(d, 4),
                                "GBps": round(n_el * 4 * (P + 1) / d / 1e6, 1)}
         rf.free()
+        res["graph_vs_direct_kernel_span"] = round(
+            res["batched_bf16_graph"]["kernel_span_ms"] /
+            res["batched_bf16"]["kernel_span_ms"], 4)
         res["bf16_batched_speedup_vs_plain_fp32"] = round(
             res["plain_fp32_separate"]["host_ms"] /
             res["batched_bf16"]["host_ms"], 3)
@@ -923,6 +1096,11 @@ def main():
         fn = epoch_trace if args.only == "epoch_trace" else size_sweep
         print(json.dumps({args.only: fn(pc, torch, synth,
                                         torch.cuda.Stream(dev))}), flush=True)
+        return
+    if args.only in ("staggered_arrivals", "rank_readiness"):
+        fn = staggered_arrivals if args.only == "staggered_arrivals" \
+            else rank_readiness
+        print(json.dumps({args.only: fn(pc, torch, synth)}), flush=True)
         return
     if args.only:
         print(json.dumps({args.only: only_workload(

@@ -331,7 +331,10 @@ typedef struct {
                         the end of an epoch (guided self-scheduling) */
   int min_tile_elems; /* smallest tile; a multiple of 1024, <= tile_elems */
   int groups;        /* workgroups of the persistent kernel; 0 =
-                        groups_per_cu x compute units */
+                        groups_per_cu x compute units, but no more than
+                        the device holds at once (HIP's occupancy of the
+                        selected kernel).  Either way no more than the
+                        message has tiles */
   int groups_per_cu; /* used when groups = 0 */
   int comp;          /* float sums: 1 = Sum2 compensated, 0 = plain */
   int graph;         /* 1 = start replays a cached graph (captured once per

@@ -30,13 +30,16 @@ inline int elem_bytes(int dtype) {
 
 // Launch shape of the persistent kernel: `groups` workgroups of `waves`
 // wavefronts on `stream`; with start / stop events, those are stamped at
-// the kernel's own start and end (hipExtLaunchKernel).
+// the kernel's own start and end (hipExtLaunchKernel).  With `per_cu` set,
+// nothing is launched: *per_cu receives how many workgroups of `waves`
+// wavefronts of the selected kernel fit on one compute unit at once.
 struct Launch {
   int groups;
   int waves;
   hipStream_t stream;
   hipEvent_t start;
   hipEvent_t stop;
+  int* per_cu = nullptr;
 };
 
 // The persistent partitioned-reduce kernel; deep: 4 rows per lane in

@@ -380,18 +380,24 @@ __device__ __forceinline__ WaitResult wait_queued(const ReduceArgs& a,
     if ((uint32_t)(qs >> 32) >= a.nparts_total) return kStop;
     // about to wait: finished tiles must not sit behind the wait
     publish_pending();
-    // The workers near the queue's end ingest.  So does, every 16th poll,
-    // any worker that has waited 64 polls: a launch can have more
+    // The workers near the queue's end ingest.  So does, every 128th
+    // poll, any worker that has waited 64 polls: a launch can have more
     // workgroups than fit on the device at once, and the tiles at the
     // queue's end may belong to workgroups that start only when resident
-    // ones leave, so ingesting must not depend on them.
+    // ones leave, so ingesting must not depend on them.  Those far from the
+    // end read host memory (the ready list, the abort word) that rarely:
+    // a read of host memory crosses the bus, and a few hundred waiting
+    // workers that read it every few polls load the bus enough to slow
+    // the dispatch of kernels on other streams (the producers an epoch
+    // waits for).
     const bool near = t - qt < 8u;
     const bool stuck = spins >= 64u;
-    const bool front = near || (stuck && (spins & 15u) == 0u);
+    const bool front = near || (stuck && (spins & 127u) == 0u);
     if (front && try_ingest(a, epoch, spins >= 16u)) continue;
     if (uni(ld_rlx(&a.ctr->error)) != 0u) return kBail;
     if ((spins & 7u) == 7u) {
-      if ((near || stuck) && uni(ld_rlx_sys(&a.host->abort)) == epoch) {
+      const bool poll_abort = near || (stuck && (spins & 255u) == 255u);
+      if (poll_abort && uni(ld_rlx_sys(&a.host->abort)) == epoch) {
         set_error(a, kStatusAborted, epoch);
         return kBail;
       }

@@ -19,13 +19,16 @@ __global__ __launch_bounds__(64 * kMaxWavesPerGroup) void reduce_persistent(
 
 // With timing events, the launch goes through hipExtLaunchKernel, which
 // stamps the events at the kernel's own start and end (no marker packets
-// around it).
+// around it).  With l.per_cu set, only the kernel's residency is read.
 template <class Tile>
 hipError_t launch_ranks(const ReduceArgs& a, int nranks, const Launch& l) {
   const dim3 grid(l.groups), block(64 * l.waves);
   switch (nranks) {
 #define PCOLL_CASE(P)                                                        \
   case P:                                                                    \
+    if (l.per_cu)                                                            \
+      return hipOccupancyMaxActiveBlocksPerMultiprocessor(                   \
+          l.per_cu, reduce_persistent<Tile, P>, 64 * l.waves, 0);            \
     if (l.start || l.stop)                                                   \
       hipExtLaunchKernelGGL((reduce_persistent<Tile, P>), grid, block, 0,    \
                             l.stream, l.start, l.stop, 0, a);                \

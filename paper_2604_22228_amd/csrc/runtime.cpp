@@ -347,6 +347,22 @@ int launch_groups(const pcoll_config_t& c, int cus, int dtype, uint32_t np,
   return groups < 1 ? 1 : groups;
 }
 
+// Workgroups of `waves` wavefronts of the selected kernel that the device
+// holds at once (`cus` compute units), or 0 if HIP cannot say.  The
+// persistent kernel launches no more than that: a workgroup beyond them
+// would start only when a resident one has run out of tiles and exited, and
+// would then reduce its own first tile alone at the end of the epoch.
+int resident_groups(int dtype, int op, bool comp, bool deep, int nranks,
+                    int waves, int cus) {
+  int per_cu = 0;
+  Launch l{1, waves, nullptr, nullptr, nullptr};
+  l.per_cu = &per_cu;
+  const ReduceArgs a{};
+  if (launch_reduce(a, dtype, op, comp, deep, nranks, l) != hipSuccess)
+    return 0;
+  return per_cu > 0 ? per_cu * cus : 0;
+}
+
 // Applies a configuration: workgroups and the signature of the launch.
 int apply_config(pcoll_req_t r, const pcoll_config_t& c) {
   int rc = validate_config(r, c);
@@ -360,15 +376,21 @@ int apply_config(pcoll_req_t r, const pcoll_config_t& c) {
   const int waves = room ? std::min(c.group_waves, 4) : c.group_waves;
   pcoll_config_t eff = c;
   if (room && !c.groups) eff.groups_per_cu = 1;
-  // No more workgroups than the launch has tiles for sure.  So every
+  // Unless the count is given, no more workgroups than the device holds at
+  // once (resident_groups); and no more than the launch has tiles for
+  // sure.  So every
   // workgroup owns a first tile (its own number), a small message does not
   // dispatch workers that would only wait, and an epoch cannot complete
   // before every workgroup of its launch has started; a graph replay,
   // whose workgroups read the epoch stamp from host memory when they
   // start, depends on that (the host writes the next stamp only after the
   // epoch completed).
-  const int groups = launch_groups(eff, r->cus, r->dtype, r->nparts_total,
-                                   [&](uint32_t k) { return r->parts[k].rows; });
+  const bool deep = !room && c.unroll != 2;
+  int groups = launch_groups(eff, r->cus, r->dtype, r->nparts_total,
+                             [&](uint32_t k) { return r->parts[k].rows; });
+  const int fit = resident_groups(r->dtype, r->op, c.comp != 0, deep,
+                                  r->nranks, waves, r->cus);
+  if (!c.groups && fit > 0 && groups > fit) groups = fit;
   rc = drain(r);
   if (rc) return rc;
   if ((c.debug & 2) && groups > r->trace_cap) {  // the trace's records
@@ -384,7 +406,7 @@ int apply_config(pcoll_req_t r, const pcoll_config_t& c) {
   r->cfg = c;
   r->groups = groups;
   r->waves = waves;
-  r->deep = !room && c.unroll != 2;
+  r->deep = deep;
   r->room_pending = false;
   r->sig = launch_signature(r);
   if (r->cache)  // graphs captured with the old arguments are stale
@@ -1255,7 +1277,10 @@ int pcoll_reduce_noalloc(size_t count, pcoll_dtype_t dtype_, pcoll_op_t op_,
     return std::min<uint64_t>(ps, count - off);
   };
   auto rows_of = [&](uint32_t k) { return (len_of(k) + re - 1) / re; };
-  const int groups = launch_groups(c, cus, dtype, np, rows_of);
+  int groups = launch_groups(c, cus, dtype, np, rows_of);
+  const int fit = resident_groups(dtype, op, c.comp != 0, c.unroll != 2,
+                                  nranks, c.group_waves, cus);
+  if (!c.groups && fit > 0 && groups > fit) groups = fit;
   uint64_t total_rows = 0;
   for (uint32_t k = 0; k < np; ++k) total_rows += rows_of(k);
 

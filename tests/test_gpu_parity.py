@@ -680,13 +680,16 @@ def test_unroll_rejects_other_depths(stream):
 
 def test_more_workgroups_than_resident_with_slow_readiness(orc, stream):
     """A launch with more workgroups than the device holds at once (bf16 at
-    8 ranks, 2 groups of 8 waves per compute unit) and readiness trickling
-    in, so that ingestion is partial: the tiles at the queue's end can
-    belong to workgroups that have not started, and the waiting resident
-    ones must ingest instead.  Bitwise against the oracle."""
+    8 ranks, twice as many groups of 8 waves as compute units, given as an
+    exact count: a count from groups_per_cu is capped at the residency)
+    and readiness trickling in, so that ingestion is partial: the tiles at
+    the queue's end can belong to workgroups that have not started, and
+    the waiting resident ones must ingest instead.  Bitwise against the
+    oracle."""
     import time
     P, nparts = 8, 64
     n = nparts * 16 * 1024  # 16 one-row-pair tiles per partition
+    cus = torch.cuda.get_device_properties(DEV).multi_processor_count
     say(f"case oversubscribed grid, slow readiness n={n}")
     xs = [t.to(torch.bfloat16).view(torch.int16)
           for t in synth.normal_f32(P, n, 81)]
@@ -695,7 +698,7 @@ def test_more_workgroups_than_resident_with_slow_readiness(orc, stream):
     out = torch.empty(n, dtype=torch.int16, device=DEV)
     req = new_request([n], pc.BFLOAT16, pc.SUM, nparts, P, comp=0,
                       tile_elems=1024, min_tile_elems=1024,
-                      groups_per_cu=2, group_waves=8, interleave=0)
+                      groups=2 * cus, group_waves=8, interleave=0)
     req.bind([[x.to(DEV) for x in xs]], [out], stream=stream)
     for epoch in range(2):
         req.start()
@@ -705,5 +708,5 @@ def test_more_workgroups_than_resident_with_slow_readiness(orc, stream):
         req.wait()
         torch.cuda.synchronize()
         assert np.array_equal(out.cpu().numpy().view(np.uint16), want)
-    assert req.stats().groups > 256
+    assert req.stats().groups == 2 * cus
     req.free()
