@@ -202,19 +202,22 @@ def _events(torch):
 def time_requests(torch, reqs, orders, stream, warmup, reps):
     """Time-to-reduce of a set of requests sharing one stream: start all,
     ready every partition (each request's seeded order, one list call per
-    request), wait all.  Returns (host ms per rep, device ms per rep): the
-    device time is the kernel's own (start and end stamped by the launch,
-    debug timing, in a second pass: it costs host time of its own) for one
-    request in direct-launch mode, else HIP events around the starts and
-    the readiness calls."""
+    request), wait all.  Returns (host ms per rep, device ms per rep),
+    medians.  The host time comes from a pass with nothing else on the
+    stream; the device time from a second pass: the kernel's own (start and
+    end stamped by the launch, debug timing) for one request in
+    direct-launch mode, else HIP events around the starts and the
+    readiness calls."""
     import statistics
     own = len(reqs) == 1 and not reqs[0].config().graph
-    host, devt = _time_pass(torch, reqs, orders, stream, warmup, reps)
+    host, _ = _time_pass(torch, reqs, orders, stream, warmup, reps,
+                         events=False)
+    _, devt = _time_pass(torch, reqs, orders, stream, 0, reps)
     if own:
         reqs[0].set_config(debug=4)
-        _time_pass(torch, reqs, orders, stream, 1, 0)
+        _time_pass(torch, reqs, orders, stream, 1, 0, events=False)
         st0 = reqs[0].stats()
-        _time_pass(torch, reqs, orders, stream, 0, reps)
+        _time_pass(torch, reqs, orders, stream, 0, reps, events=False)
         st1 = reqs[0].stats()
         reqs[0].set_config(debug=0)
         devt = [(st1.kernel_ms_total - st0.kernel_ms_total) /
@@ -224,13 +227,15 @@ def time_requests(torch, reqs, orders, stream, warmup, reps):
 
 def trace_span_ms(pc, torch, req, order, stream, reps):
     """The kernel's own span (first workgroup start to last workgroup end)
-    from its per-workgroup wall-clock trace (debug bit 2), median over
-    `reps` epochs after one warmup.  It works for graph replays too, where
-    no launch events can stamp the kernel."""
+    and its busy span (first tile queued to last workgroup end, which
+    leaves out the wait for the host's readiness call) from its
+    per-workgroup wall-clock trace (debug bit 2), medians over `reps`
+    epochs after one warmup.  It works for graph replays too, where no
+    launch events can stamp the kernel."""
     import statistics
     dbg = req.config().debug
     req.set_config(debug=dbg | 2)
-    spans = []
+    spans, busy = [], []
     for it in range(1 + reps):
         torch.cuda.synchronize()
         req.start()
@@ -240,32 +245,41 @@ def trace_span_ms(pc, torch, req, order, stream, reps):
         torch.cuda.synchronize()  # the last workgroup's stamp is written
         if it:
             tr, khz = pc.pcoll_debug_trace(req.h)
-            spans.append((max(e for _, _, e, _ in tr) -
-                          min(s for s, _, _, _ in tr)) / khz)
+            end = max(e for _, _, e, _ in tr)
+            spans.append((end - min(s for s, _, _, _ in tr)) / khz)
+            busy.append((end - min(f for _, f, _, _ in tr if f)) / khz)
     req.set_config(debug=dbg)
-    return statistics.median(spans)
+    return statistics.median(spans), statistics.median(busy)
 
 
-def _time_pass(torch, reqs, orders, stream, warmup, reps):
+def _time_pass(torch, reqs, orders, stream, warmup, reps, events=True):
+    """Host ms per rep and, with `events`, device ms per rep between HIP
+    events recorded before the starts and after the readiness calls (the
+    host time of a pass with events includes the markers' cost)."""
     host, devt = [], []
     for it in range(warmup + reps):
-        e0, e1 = _events(torch)
+        if events:
+            e0, e1 = _events(torch)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        e0.record(stream)
+        if events:
+            e0.record(stream)
         for r in reqs:
             r.start()
         for r, o in zip(reqs, orders):
             r.pready_list(o)
-        e1.record(stream)
-        stream.query()  # the HIP runtime may hold the record back until then
+        if events:
+            e1.record(stream)
+            stream.query()  # the HIP runtime may hold the record back
         for r in reqs:
             r.wait()
         t1 = time.perf_counter()
-        e1.synchronize()
+        if events:
+            e1.synchronize()
         if it >= warmup:
             host.append((t1 - t0) * 1e3)
-            devt.append(e0.elapsed_time(e1))
+            if events:
+                devt.append(e0.elapsed_time(e1))
     return host, devt
 
 
@@ -970,12 +984,13 @@ def extras(pc, torch, synth, warmup, reps):
             rb.bind(bf, yb, stream=stream)
             h, d = time_requests(torch, [rb], [order], stream, warmup, reps)
             st = rb.stats()
-            span = trace_span_ms(pc, torch, rb, order, stream, reps)
+            span, busy = trace_span_ms(pc, torch, rb, order, stream, reps)
             # direct: the kernel's own time from its launch events; graph:
             # HIP events around the replay and the readiness call
             res[key] = {"host_ms": round(h, 4),
                         "events_ms" if graph else "kernel_ms": round(d, 4),
                         "kernel_span_ms": round(span, 4),
+                        "kernel_busy_ms": round(busy, 4),
                         "GBps": round(n_el * 2 * (P + 1) / d / 1e6, 1),
                         "graph": rb.config().graph}
             if graph:
@@ -1025,9 +1040,10 @@ def extras(pc, torch, synth, warmup, reps):
                                "kernel_ms": round(d, 4),
                                "GBps": round(n_el * 4 * (P + 1) / d / 1e6, 1)}
         rf.free()
-        res["graph_vs_direct_kernel_span"] = round(
-            res["batched_bf16_graph"]["kernel_span_ms"] /
-            res["batched_bf16"]["kernel_span_ms"], 4)
+        for k in ("span", "busy"):
+            res[f"graph_vs_direct_kernel_{k}"] = round(
+                res["batched_bf16_graph"][f"kernel_{k}_ms"] /
+                res["batched_bf16"][f"kernel_{k}_ms"], 4)
         res["bf16_batched_speedup_vs_plain_fp32"] = round(
             res["plain_fp32_separate"]["host_ms"] /
             res["batched_bf16"]["host_ms"], 3)
@@ -1127,19 +1143,12 @@ def main():
         step()
     torch.cuda.synchronize()
 
-    evs = [(torch.cuda.Event(enable_timing=True),
-            torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    torch.cuda.synchronize()
+    # the timed steps: nothing but the steps (no events: a marker packet
+    # costs the stream about 5 us)
     marks = []
     t0 = time.perf_counter()
-    for e0, e1 in evs:
-        e0.record(stream)
-        req.start()
-        for p in order:
-            req.pready(p)
-        e1.record(stream)  # enqueued behind the kernel on its stream
-        stream.query()  # submitted now, not at the next look at the stream
-        req.wait()
+    for _ in range(args.steps):
+        step()
         marks.append(time.perf_counter())
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -1149,7 +1158,19 @@ def main():
            "mean": round(sum(step_ms) / len(step_ms), 4),
            "p10": round(step_ms[len(step_ms) // 10], 4),
            "p90": round(step_ms[(9 * len(step_ms)) // 10], 4)}
-    # the epoch's device time between marker events (start .. readiness)
+    # the epoch's device time between marker events (start .. readiness),
+    # the same steps again with events around them
+    evs = [(torch.cuda.Event(enable_timing=True),
+            torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for e0, e1 in evs:
+        e0.record(stream)
+        req.start()
+        for p in order:
+            req.pready(p)
+        e1.record(stream)  # enqueued behind the kernel on its stream
+        stream.query()  # submitted now, not at the next look at the stream
+        req.wait()
+    torch.cuda.synchronize()
     epoch_ms_events = sum(a.elapsed_time(b) for a, b in evs) / args.steps
     # the kernel's own duration: the same steps again with debug timing
     # (start and end stamped by the launch, no instrumentation in the
