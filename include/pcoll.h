@@ -545,10 +545,14 @@ int pcoll_probe_copy(void *dst, const void *src, size_t bytes, void *stream);
  * takes vectors i, i + T, ...; `bytes` a multiple of 16); layout 1: the
  * reduce's own schedule (rows of 64 x 16 bytes, tiles of 32 rows in bands
  * of 16 tiles, 2 workgroups of 8 waves per compute unit, each taking tiles
- * in turn; `bytes` a multiple of 1024, at most 64 GiB), so that the reduce kernel's time
- * against it is what its readiness and completion protocol costs.  The
+ * in turn; `bytes` a multiple of 1024, at most 64 GiB), so that the reduce
+ * kernel's time against it is what its readiness and completion protocol
+ * costs; layout 2: contiguous shares (4 workgroups of 256 threads per
+ * compute unit, each streaming its own 1 / (4 x units) of every buffer,
+ * 8 / nsrc vectors per source in flight per thread, at least 1; `bytes` a
+ * multiple of 16), the fastest pattern for plain streams.  The
  * attainable-bandwidth references of the reduce kernels; PCOLL_ERR_ARG for
- * other counts or sizes, null or misaligned pointers. */
+ * other counts, layouts or sizes, null or misaligned pointers. */
 int pcoll_probe_stream(const void *const *srcs, int nsrc, void *dst,
                        size_t bytes, int write, int layout, void *stream);
 

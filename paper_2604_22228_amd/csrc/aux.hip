@@ -466,6 +466,59 @@ __global__ __launch_bounds__(512) void tile_stream_kernel(
     dst[0] = keep;
 }
 
+// The same streams with each workgroup on its own contiguous share of
+// every buffer (vectors [g c, (g + 1) c) of each, c = `chunk`), its 256
+// threads taking vectors b + t, b + t + 256, ...; 8 / P vectors per source
+// in flight per thread (at least 1).  The pattern that streams HBM fastest
+// on MI355X: reads alone reach about 90 % of the peak this way.
+template <int P, bool WRITE>
+__global__ __launch_bounds__(256) void chunk_stream_kernel(StreamSrcs s,
+                                                           uint4* dst,
+                                                           size_t nv,
+                                                           size_t chunk) {
+  constexpr int U = P >= 8 ? 1 : 8 / P;
+  const size_t b0 = (size_t)blockIdx.x * chunk;
+  const size_t b1 = b0 + chunk < nv ? b0 + chunk : nv;
+  uint4 keep = make_uint4(0, 0, 0, 0);
+  auto combine = [&](const uint4(&x)[P], size_t v) {
+    uint4 a = x[0];
+#pragma unroll
+    for (int r = 1; r < P; ++r) {
+      a.x ^= x[r].x;
+      a.y ^= x[r].y;
+      a.z ^= x[r].z;
+      a.w ^= x[r].w;
+    }
+    if (WRITE) {
+      dev::st_stream(dst + v, a);
+    } else {
+      keep.x ^= a.x;
+      keep.y += a.y;
+      keep.z ^= a.z;
+      keep.w += a.w;
+    }
+  };
+  size_t i = b0 + threadIdx.x;
+  for (; i + (U - 1) * 256u < b1; i += U * 256u) {
+    uint4 x[U][P];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int r = 0; r < P; ++r) x[u][r] = dev::ld_stream(s.p[r] + i + u * 256u);
+#pragma unroll
+    for (int u = 0; u < U; ++u) combine(x[u], i + u * 256u);
+  }
+  for (; i < b1; i += 256u) {
+    uint4 x[P];
+#pragma unroll
+    for (int r = 0; r < P; ++r) x[r] = dev::ld_stream(s.p[r] + i);
+    combine(x, i);
+  }
+  if (!WRITE && keep.x == 0x9e3779b9u && keep.y == 0x7f4a7c15u &&
+      keep.z == 0xf39cc060u && keep.w == 0x5cedc834u)
+    dst[0] = keep;
+}
+
 static unsigned probe_blocks(size_t nv) {
   size_t b = (nv + 255) / 256;
   if (b > 16384) b = 16384;
@@ -488,7 +541,11 @@ static hipError_t launch_stream_w(const StreamSrcs& srcs, int nsrc, uint4* dst,
                                   hipStream_t s) {
 #define PCOLL_STREAM_CASE(P)                                                \
   case P:                                                                   \
-    if (t)                                                                  \
+    if (t && t->chunked)                                                    \
+      hipLaunchKernelGGL((chunk_stream_kernel<P, WRITE>), dim3(t->groups),  \
+                         dim3(256), 0, s, srcs, dst, nv,                    \
+                         (nv + t->groups - 1) / t->groups);                 \
+    else if (t)                                                             \
       hipLaunchKernelGGL((tile_stream_kernel<P, WRITE>), dim3(t->groups),   \
                          dim3(64 * t->waves), 0, s, srcs, dst,              \
                          (uint32_t)(nv / 64), t->tile_rows, t->band);       \
@@ -516,9 +573,11 @@ hipError_t launch_stream(const void* const* srcs, int nsrc, void* dst,
   const size_t nv = bytes / 16;
   if (nv == 0) return hipSuccess;
   // tile layout: whole rows, vector indexes below 2^32
-  if (tiles && (nv % 64 || nv > 0xffffffffu || tiles->groups < 1 ||
-                tiles->waves < 1 || tiles->waves > 8 || tiles->tile_rows < 1))
+  if (tiles && !tiles->chunked &&
+      (nv % 64 || nv > 0xffffffffu || tiles->groups < 1 || tiles->waves < 1 ||
+       tiles->waves > 8 || tiles->tile_rows < 1))
     return hipErrorInvalidValue;
+  if (tiles && tiles->chunked && tiles->groups < 1) return hipErrorInvalidValue;
   StreamSrcs a{};
   for (int r = 0; r < nsrc; ++r) a.p[r] = static_cast<const uint4*>(srcs[r]);
   uint4* d = static_cast<uint4*>(dst);

@@ -73,9 +73,13 @@ hipError_t launch_fill(void* dst, size_t bytes, uint32_t value,
                        hipStream_t s);
 // The reduce's streams without its protocol: nsrc (1, 2, 4, 8 or 16) reads
 // of `bytes` each and, with `write`, one write of their XOR; grid-stride
-// (tiles = null) or in the reduce's tile schedule (whole 1 KiB rows).
+// (tiles = null), in the reduce's tile schedule (whole 1 KiB rows), or in
+// contiguous shares per workgroup (tiles->chunked).
 struct StreamTiles {
   uint32_t groups, waves, tile_rows, band;
+  uint32_t chunked;  // 1: each of `groups` workgroups of 256 threads
+                     // streams its own contiguous share (waves, tile_rows
+                     // and band unused)
 };
 hipError_t launch_stream(const void* const* srcs, int nsrc, void* dst,
                          size_t bytes, bool write, const StreamTiles* tiles,

@@ -1464,8 +1464,9 @@ int pcoll_probe_stream(const void* const* srcs, int nsrc, void* dst,
                        size_t bytes, int write, int layout, void* stream) {
   if (!srcs || (nsrc != 1 && nsrc != 2 && nsrc != 4 && nsrc != 8 &&
                 nsrc != 16) ||
-      (write != 0 && write != 1) || (layout != 0 && layout != 1) ||
-      bytes % (layout ? 1024 : 16) || (layout && bytes > (1ull << 36)) ||
+      (write != 0 && write != 1) || layout < 0 || layout > 2 ||
+      bytes % (layout == 1 ? 1024 : 16) ||
+      (layout == 1 && bytes > (1ull << 36)) ||
       !dst ||
       ((uintptr_t)dst & 15u))
     return PCOLL_ERR_ARG;
@@ -1473,16 +1474,23 @@ int pcoll_probe_stream(const void* const* srcs, int nsrc, void* dst,
     if (bytes && (!srcs[r] || ((uintptr_t)srcs[r] & 15u))) return PCOLL_ERR_ARG;
   StreamTiles t{};
   if (layout) {
-    // the headline reduce's launch: 2 workgroups of 8 waves per compute
-    // unit, tiles of 32 rows (8192 binary32 elements), bands of 16 tiles
     int dev = 0, cus = 0;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
                                   dev));
-    t.groups = (uint32_t)(2 * std::max(cus, 1));
-    t.waves = 8;
-    t.tile_rows = 32;
-    t.band = 16;
+    if (layout == 1) {
+      // the headline reduce's tile schedule: tiles of 32 rows (8192
+      // binary32 elements), bands of 16 tiles, 2 workgroups of 8 waves per
+      // compute unit
+      t.groups = (uint32_t)(2 * std::max(cus, 1));
+      t.waves = 8;
+      t.tile_rows = 32;
+      t.band = 16;
+    } else {
+      // contiguous shares: 4 workgroups of 256 threads per compute unit
+      t.groups = (uint32_t)(4 * std::max(cus, 1));
+      t.chunked = 1;
+    }
   }
   HIP_TRY(launch_stream(srcs, nsrc, dst, bytes, write != 0,
                         layout ? &t : nullptr,

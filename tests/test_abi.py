@@ -139,6 +139,34 @@ def test_probe_and_pack_reject_unaligned_sizes():
     assert lib.pcoll_pack_bf16(None, None, 0, None) == 0
 
 
+def test_probe_stream_rejects_bad_layouts_and_sizes():
+    """Argument checks of pcoll_probe_stream, all taken before any device
+    call: source counts, layouts 0..2, sizes per layout, alignment."""
+    import ctypes as C
+    lib = pc.load()
+    buf = (C.c_uint64 * 4)()  # 16-byte aligned host stand-ins: never read
+    addr = C.addressof(buf)
+    srcs = (C.c_void_p * 8)(*([addr] * 8))
+    ok_dst = C.c_void_p(addr)
+    for layout in (-1, 3):
+        assert lib.pcoll_probe_stream(srcs, 8, ok_dst, 1024, 1, layout,
+                                      None) == pc.ERR_ARG
+    for nsrc in (0, 3, 17):
+        assert lib.pcoll_probe_stream(srcs, nsrc, ok_dst, 1024, 1, 2,
+                                      None) == pc.ERR_ARG
+    assert lib.pcoll_probe_stream(srcs, 8, ok_dst, 1024, 2, 2,
+                                  None) == pc.ERR_ARG       # write not 0/1
+    assert lib.pcoll_probe_stream(srcs, 8, ok_dst, 24, 1, 2,
+                                  None) == pc.ERR_ARG       # not 16 B units
+    assert lib.pcoll_probe_stream(srcs, 8, ok_dst, 1040, 1, 1,
+                                  None) == pc.ERR_ARG       # not whole rows
+    assert lib.pcoll_probe_stream(srcs, 8, None, 1024, 1, 2,
+                                  None) == pc.ERR_ARG       # no destination
+    bad = (C.c_void_p * 8)(*([addr + 4] * 8))
+    assert lib.pcoll_probe_stream(bad, 8, ok_dst, 1024, 1, 2,
+                                  None) == pc.ERR_ARG       # misaligned
+
+
 def test_plan_partitions_are_aligned_for_lines():
     """Partitions start on 128-byte lines (and 8-bit scale blocks)."""
     for dtype in (pc.INT32, pc.FLOAT32, pc.BFLOAT16, pc.FP8_E4M3,
