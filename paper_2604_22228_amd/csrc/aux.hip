@@ -47,9 +47,17 @@ hipError_t launch_reduce(const ReduceArgs& a, int dtype, int op, bool comp,
 // Then one compare-and-swap reserves the block's entries, and only while
 // the ring's word carries the signal's epoch: the ring of an epoch that has
 // ended was reopened for a later one (or is about to be), and a late
-// signal must not count there.  Each entry is stored with a release atomic
-// max of (epoch << 32) | part, so a slot never goes back to an older
-// epoch's entry.
+// signal must not count there.  Each entry is stored with an atomic max
+// of (epoch << 32) | part, so a slot never goes back to an older epoch's
+// entry.
+//
+// Every atomic of a signal is relaxed.  A signal runs after the work it
+// readies in its stream's order, and the end of that work (a kernel, a
+// copy) has already made its stores visible device-wide; a signal writes
+// nothing else, so it needs no fence.  (An agent-scope release would write
+// back this XCD's L2, with the producers' dirty lines in it, and an
+// acquire would invalidate it, at every signal.)  The reduce kernel takes
+// an acquire fence before it queues what a ring entry readies.
 __device__ __forceinline__ void ring_append(const RingArgs& a, bool want,
                                             uint32_t part) {
   __shared__ uint32_t wave_cnt[4];
@@ -90,7 +98,7 @@ __device__ __forceinline__ void ring_append(const RingArgs& a, bool want,
     for (uint32_t w = 0; w < wave; ++w) c += wave_cnt[w];
     uint64_t* slot = a.dlist + (size_t)(a.epoch & 1u) * a.capacity + c;
     __hip_atomic_fetch_max(slot, ((uint64_t)a.epoch << 32) | part,
-                           __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -110,12 +118,13 @@ hipError_t launch_pready(const PreadyArgs& a, hipStream_t s) {
 }
 
 // Per-rank marks.  Each lane sets its rank's bit in the partition's
-// epoch-tagged mask with a compare-and-swap (acquire-release: the ranks'
-// producers, ordered before their marks by their streams, are visible to
-// the lane whose mark completes the mask, which then publishes with a
-// release store).  A word of an older epoch counts as empty; a word of a
-// newer epoch is left alone (this mark's epoch has ended).  Marks already
-// set are idempotent, so a partition completes exactly once per epoch.
+// epoch-tagged mask with a relaxed compare-and-swap (each rank's producers
+// finished before its mark, in its stream's order, so their stores are
+// already visible; see ring_append).  A word of an older epoch counts as
+// empty; a word of a newer epoch is left alone (this mark's epoch has
+// ended).  Marks already set are idempotent, so a partition completes
+// exactly once per epoch, and the lane whose mark completes it appends it
+// to the ring.
 __global__ __launch_bounds__(256) void pready_rank_kernel(PreadyRankArgs a) {
   const uint32_t i = blockIdx.x * 256u + threadIdx.x;
   const uint32_t epoch = a.ring.epoch;
@@ -133,7 +142,7 @@ __global__ __launch_bounds__(256) void pready_rank_kernel(PreadyRankArgs a) {
       const uint64_t nw = cur | bit;
       if (nw == old) break;  // this rank's mark is already in
       if (__hip_atomic_compare_exchange_strong(
-              w, &old, nw, __ATOMIC_ACQ_REL, __ATOMIC_RELAXED,
+              w, &old, nw, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
               __HIP_MEMORY_SCOPE_AGENT)) {
         done = (uint32_t)nw == a.full && (uint32_t)cur != a.full;
         break;

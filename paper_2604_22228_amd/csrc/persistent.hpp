@@ -312,7 +312,9 @@ __device__ __forceinline__ bool try_ingest(const ReduceArgs& a, uint32_t epoch,
     const uint64_t pending = __ballot(in && !ok);
     const uint32_t lim =
         pending ? (uint32_t)(__ffsll((long long)pending) - 1) : 64u;
-    // entries were stored with release after their producers: acquire
+    // the producers of these partitions ended before their signals ran
+    // (stream order), which made their stores visible device-wide;
+    // acquire, so that no stale line of them is read from this XCD's caches
     if (__ballot(ok && lane < lim)) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE,
                                                             "agent");
     queue_append(a, queue_stamp(a, epoch, ok && lane < lim, (uint32_t)v),
