@@ -710,3 +710,64 @@ def test_more_workgroups_than_resident_with_slow_readiness(orc, stream):
         assert np.array_equal(out.cpu().numpy().view(np.uint16), want)
     assert req.stats().groups == 2 * cus
     req.free()
+
+
+def test_grid_is_capped_at_residency(orc, stream):
+    """A grid asked for as 4 workgroups of 8 waves per compute unit (more
+    than the fp32 kernel's registers allow at once) is capped at what the
+    device holds: every workgroup starts within a few microseconds of the
+    first (its per-workgroup trace), each reduces tiles, and the output is
+    bitwise the oracle's.  An exact `groups` count is not capped."""
+    P, nparts = 8, 64
+    n = 1 << 22
+    cus = torch.cuda.get_device_properties(DEV).multi_processor_count
+    say(f"case residency cap n={n} cus={cus}")
+    xs = synth.normal_f32(P, n, 91)
+    dx = [x.to(DEV) for x in xs]
+    out = torch.full((n,), float("nan"), device=DEV)
+    req = new_request([n], pc.FLOAT32, pc.SUM, nparts, P, comp=0,
+                      tile_elems=4096, groups_per_cu=4, group_waves=8,
+                      unroll=4, debug=2)
+    req.bind([dx], [out], stream=stream)
+    run_epoch(req, synth.permutation(nparts, 92), stream, mode="list")
+    st = req.stats()
+    tr, khz = pc.pcoll_debug_trace(req.h)
+    assert 1 <= st.groups < 4 * cus and len(tr) == st.groups
+    starts = [s for s, _, _, _ in tr]
+    spread_us = (max(starts) - min(starts)) * 1e3 / khz
+    say(f"groups {st.groups}, start spread {spread_us:.1f} us")
+    assert spread_us < 50.0, "a workgroup started late: not all resident"
+    assert all(t >= 1 for _, _, _, t in tr)
+    want = orc.sum_f32_f32([x.numpy() for x in xs], comp=False)
+    assert np.array_equal(as_u32(out.cpu().numpy()), as_u32(want))
+    # an exact count is taken as given
+    req.set_config(groups=4 * cus, debug=0)
+    run_epoch(req, synth.permutation(nparts, 93), stream, mode="list")
+    assert req.stats().groups == 4 * cus
+    assert np.array_equal(as_u32(out.cpu().numpy()), as_u32(want))
+    req.free()
+
+
+@pytest.mark.parametrize("layout", [0, 1, 2])
+@pytest.mark.parametrize("nsrc", [1, 8])
+def test_probe_stream_writes_the_xor(stream, layout, nsrc):
+    """pcoll_probe_stream with write = 1 stores the bitwise XOR of its
+    sources in every layout (sizes with a ragged end where the layout
+    allows one); with write = 0 it leaves the destination alone."""
+    nbytes = (1 << 20) + (0 if layout == 1 else 48)
+    say(f"case probe_stream layout={layout} nsrc={nsrc} bytes={nbytes}")
+    g = torch.Generator(device=DEV).manual_seed(1000 + 10 * layout + nsrc)
+    n = nbytes // 4
+    srcs = [torch.randint(-2**31, 2**31 - 1, (n,), generator=g, device=DEV,
+                          dtype=torch.int32) for _ in range(nsrc)]
+    dst = torch.zeros(n, dtype=torch.int32, device=DEV)
+    want = srcs[0].clone()
+    for s in srcs[1:]:
+        want ^= s
+    pc.pcoll_probe_stream(srcs, dst, nbytes, 1, layout, stream)
+    torch.cuda.synchronize()
+    assert torch.equal(dst, want)
+    dst.fill_(7)
+    pc.pcoll_probe_stream(srcs, dst, nbytes, 0, layout, stream)
+    torch.cuda.synchronize()
+    assert bool((dst == 7).all())
