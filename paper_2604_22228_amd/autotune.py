@@ -18,8 +18,11 @@ own).
 
 Timing: median device time of `reps` epochs (HIP events on the bound
 stream around start and the readiness call, submitted at once), every
-partition readied at once in a seeded random order, after `warmup` epochs; for the FP32 sweep keys, the mean of that
-over the sweep's partition counts 1, 4, 16 and 64.  Run on the target GPU:
+partition readied at once in a seeded random order, after `warmup` epochs;
+for the FP32 sweep keys, the mean of that over the sweep's partition
+counts 1, 4, 16 and 64 (the table keys on size alone: at each size from
+64 MiB per rank on, the four partition counts take times within 1 % of
+each other).  Run on the target GPU:
 
     python -m paper_2604_22228_amd.autotune --out paper_2604_22228_amd/tuned_mi355x.txt
 """
@@ -44,6 +47,11 @@ GROUPS_PER_CU = (1, 2)
 # tile layout: bands of one launch's worth of tiles, or of 4, 8, 16 tiles
 INTERLEAVE = (1, 4, 8, 16)
 WAVES = (4, 8)
+# finished tiles a workgroup publishes together: larger is faster all the
+# way (publish batch 8 / 16 / 32 / 64: headline kernel 0.424 / 0.400 /
+# 0.388 / 0.380 ms, batched bf16 1.181 / 1.082 / 0.999 / 0.964 ms), and 64
+# is the most one wave-wide atomic instruction publishes, so it is not
+# searched
 BATCH = (64,)
 # rows in flight per lane in the 16-byte-vector kernels at 3..8 ranks (the
 # 8-bit kernels load one row per lane at a time)
