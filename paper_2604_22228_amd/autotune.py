@@ -53,8 +53,9 @@ WAVES = (4, 8)
 # is the most one wave-wide atomic instruction publishes, so it is not
 # searched
 BATCH = (64,)
-# rows in flight per lane in the 16-byte-vector kernels at 3..8 ranks (the
-# 8-bit kernels load one row per lane at a time)
+# rows in flight per lane in the 16-byte-vector kernels from 3 ranks on (4
+# or 2 up to 8 ranks, 2 or 1 above; the 8-bit kernels load one row per lane
+# at a time)
 UNROLL = (2, 4)
 # 8-bit payloads: the kernels are bound by instruction issue and hide
 # memory latency with more resident waves and longer tiles
@@ -71,7 +72,7 @@ def grid_for(dtype, ranks=8):
         return [TILES_8BIT, GROUPS_PER_CU_8BIT, INTERLEAVE_8BIT, WAVES, BATCH,
                 (4,)]
     return [TILES, GROUPS_PER_CU, INTERLEAVE, WAVES, BATCH,
-            UNROLL if 3 <= ranks <= 8 else (4,)]
+            UNROLL if ranks >= 3 else (4,)]
 
 
 def default_keys():

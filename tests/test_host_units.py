@@ -32,7 +32,8 @@ def test_autotune_table_round_trip(tmp_path):
     assert autotune.grid_for(3)[0] == autotune.TILES_8BIT
     assert autotune.grid_for(1)[0] == autotune.TILES
     assert autotune.grid_for(1, 8)[5] == autotune.UNROLL
-    assert autotune.grid_for(0, 16)[5] == (4,)
+    assert autotune.grid_for(0, 16)[5] == autotune.UNROLL
+    assert autotune.grid_for(1, 2)[5] == (4,)
 
 
 def test_autotune_graph_rows_precede_direct_rows(tmp_path):
