@@ -639,6 +639,50 @@ def staggered_arrivals(pc, torch, synth, reps=5, gap_us=50.0):
     return res
 
 
+def pack_kernels(pc, torch, reps=10):
+    """The producer-side packers, timed apart from the reduction: 2^28 FP32
+    values (1 GiB) to bf16, to e4m3 or e5m2 codes with a binary32 scale per
+    256 values, and to MX blocks (e4m3 codes, an E8M0 scale byte per 32).
+    Mean device time of `reps` launches between HIP events; GB/s of the
+    algorithmic bytes (4 B read + the codes and scales written per
+    value)."""
+    dev = torch.device("cuda:0")
+    n = 1 << 28
+    g = torch.Generator(device=dev).manual_seed(22228)
+    x = torch.randn(n, generator=g, device=dev) * 1e-2
+    s = torch.cuda.current_stream()
+    bf = torch.empty(n, dtype=torch.int16, device=dev)
+    q = torch.empty(n, dtype=torch.uint8, device=dev)
+    sc = torch.empty(n // 256, device=dev)
+    mx = torch.empty(n // 32, dtype=torch.uint8, device=dev)
+    cases = {
+        "bf16": (lambda: pc.pcoll_pack_bf16(x, bf, n, s), 6 * n),
+        "e4m3": (lambda: pc.pcoll_pack_fp8(x, q, sc, n, s),
+                 5 * n + 4 * (n // 256)),
+        "e5m2": (lambda: pc.pcoll_pack_e5m2(x, q, sc, n, s),
+                 5 * n + 4 * (n // 256)),
+        "mxfp8": (lambda: pc.pcoll_pack_mxfp8(x, q, mx, n, s),
+                  5 * n + n // 32),
+    }
+    res = {}
+    for name, (fn, nbytes) in cases.items():
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = _events(torch)
+        e0.record(s)
+        for _ in range(reps):
+            fn()
+        e1.record(s)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        res[name] = {"ms": round(ms, 4), "bytes": nbytes,
+                     "GBps": round(nbytes / (ms * 1e-3) / 1e9, 1)}
+    res["values"] = n
+    del x, bf, q, sc, mx
+    torch.cuda.empty_cache()
+    return res
+
+
 def graph_lifecycle(pc, torch, reps=20):
     """Graph against direct launch over bucket counts (equal buckets, FP32,
     8 ranks) at 2 MiB and 512 MiB per rank: bind (descriptor table upload),
@@ -908,7 +952,8 @@ def only_workload(pc, torch, synth, name, warmup, steps):
 
 ONLY = ("batched_bf16", "batched_bf16_graph", "batched_bf16_pair",
         "batched_fp32", "int32_sum", "int32_max", "epoch_trace",
-        "size_sweep", "staggered_arrivals", "rank_readiness")
+        "size_sweep", "staggered_arrivals", "rank_readiness",
+        "pack_kernels")
 
 
 def extras(pc, torch, synth, warmup, reps):
@@ -943,20 +988,31 @@ def extras(pc, torch, synth, warmup, reps):
     put("graph_lifecycle", graph_lifecycle, pc, torch)
 
     def w1():
-        # workload 1: 4 ranks, FP32, 262144 elements, 8 partitions in order
+        # workload 1: 4 ranks, FP32, 262144 elements, 8 partitions in order;
+        # 1000 epochs (a 1 MiB message), host time statistics, warm: its
+        # 5 MiB stay in the caches between epochs
+        import statistics
         xs = synth.uniform_f32(4, 262144, synth.seed_for(1), device=dev)
         y = torch.empty(262144, device=dev)
         req = pc.Request([262144], pc.FLOAT32, pc.SUM, 8, 4)
         req.bind([xs], [y], stream=stream)
-        h, d = time_requests(torch, [req], [list(range(8))], stream, warmup,
-                             max(reps, 50))
+        order = [list(range(8))]
+        host, _ = _time_pass(torch, [req], order, stream, warmup, 1000,
+                             events=False)
+        _, d = time_requests(torch, [req], order, stream, 0, 50)
+        host = sorted(host)
         out["plain_fp32_p4_1MiB"] = {
-            "host_us": round(h * 1e3, 1), "kernel_us": round(d * 1e3, 1),
-            "GBps": round(5 * 262144 * 4 / d / 1e6, 1)}
+            "host_us": round(statistics.median(host) * 1e3, 1),
+            "host_us_mean": round(statistics.mean(host) * 1e3, 1),
+            "host_us_p10": round(host[len(host) // 10] * 1e3, 1),
+            "host_us_p90": round(host[(9 * len(host)) // 10] * 1e3, 1),
+            "kernel_us": round(d * 1e3, 1), "epochs": len(host),
+            "GBps": round(5 * 262144 * 4 / d / 1e6, 1), "cache": "warm"}
         req.free()
         del xs, y
 
     guard("plain_fp32_p4_1MiB", w1)
+    put("pack_kernels", pack_kernels, pc, torch)
 
     def w3():
         # workload 3: 64 bf16 gradient buckets, batched graph vs separate fp32
@@ -1114,6 +1170,9 @@ def main():
         fn = epoch_trace if args.only == "epoch_trace" else size_sweep
         print(json.dumps({args.only: fn(pc, torch, synth,
                                         torch.cuda.Stream(dev))}), flush=True)
+        return
+    if args.only == "pack_kernels":
+        print(json.dumps({args.only: pack_kernels(pc, torch)}), flush=True)
         return
     if args.only in ("staggered_arrivals", "rank_readiness"):
         fn = staggered_arrivals if args.only == "staggered_arrivals" \
