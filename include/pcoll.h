@@ -461,8 +461,9 @@ typedef struct {
   int group_waves;            /* wavefronts per workgroup of the last launch */
   int unroll;                 /* rows each lane of the last launch keeps
                                  loading at once: 4 or 2 up to 8 ranks, 2
-                                 or 1 above (config `unroll` 4 or 2), 1 in
-                                 the 8-bit kernels */
+                                 or 1 above (config `unroll` 4 or 2), at
+                                 most 2 for bf16 max, 1 in the 8-bit
+                                 kernels */
 } pcoll_stats_t;
 
 int pcoll_get_stats(pcoll_req_t req, pcoll_stats_t *st);

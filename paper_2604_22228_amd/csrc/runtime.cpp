@@ -364,12 +364,13 @@ int resident_groups(int dtype, int op, bool comp, bool deep, int nranks,
 }
 
 // Rows of 64 lanes x 16 bytes each lane of the launch keeps loading at once
-// (the 8-bit kernels: one; the others: the kernels' Unroll rule).
-int rows_in_flight(int dtype, int nranks, bool deep) {
+// (the 8-bit kernels: one; the others: the kernels' Unroll rule, at most 2
+// for bf16 max).
+int rows_in_flight(int dtype, int op, int nranks, bool deep) {
   if (is_fp8(dtype)) return 1;
-  if (nranks <= 2) return 4;
-  if (nranks <= 8) return deep ? 4 : 2;
-  return deep ? 2 : 1;
+  int u = nranks <= 2 ? 4 : (nranks <= 8 ? (deep ? 4 : 2) : (deep ? 2 : 1));
+  if (dtype == PCOLL_BFLOAT16 && op == PCOLL_MAX && u > 2) u = 2;
+  return u;
 }
 
 // Applies a configuration: workgroups and the signature of the launch.
@@ -1031,7 +1032,7 @@ int pcoll_start(pcoll_req_t r) {
   r->stats.epochs++;
   r->stats.groups = r->groups;
   r->stats.group_waves = r->waves;
-  r->stats.unroll = rows_in_flight(r->dtype, r->nranks, r->deep);
+  r->stats.unroll = rows_in_flight(r->dtype, r->op, r->nranks, r->deep);
   return PCOLL_SUCCESS;
 }
 

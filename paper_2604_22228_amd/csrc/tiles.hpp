@@ -16,6 +16,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "layout.hpp"
 #include "persistent.hpp"
 
@@ -390,7 +392,11 @@ struct VecTile {
     const uint32_t all = (uint32_t)((plen + kRowElems - 1) / kRowElems);
     const uint32_t rpt = (all + nt - 1) / nt;
     const RowSet rows(lt, nt, rpt, inter, full);
-    constexpr int U = Unroll<P, DEEP>::value;
+    // bf16 max holds more temporaries per value than the sums (the NaN
+    // handling of IEEE maximum): at 4 rows in flight it would spill
+    constexpr int U0 = Unroll<P, DEEP>::value;
+    constexpr bool kBf16Max = Kind == 2 && std::is_same<Acc, FMax>::value;
+    constexpr int U = kBf16Max && U0 > 2 ? 2 : U0;
     uint32_t k = wave;
     for (; k + (U - 1) * nwaves < rows.limit; k += U * nwaves) {
       uint4 x[U][P];
