@@ -633,6 +633,14 @@ __device__ __forceinline__ uint4 mx_enc16(const float (&y)[16], float scale) {
   return make_uint4(w[0], w[1], w[2], w[3]);
 }
 
+// 4 codes (a dword, first value in the low byte) scaled by the operand.
+__device__ __forceinline__ uint32_t mx_enc4(const float (&y)[4], float scale) {
+  mx_i16x2 t = __builtin_amdgcn_cvt_scalef32_pk_fp8_f32(mx_i16x2{0, 0}, y[0],
+                                                        y[1], scale, false);
+  t = __builtin_amdgcn_cvt_scalef32_pk_fp8_f32(t, y[2], y[3], scale, true);
+  return __builtin_bit_cast(uint32_t, t);
+}
+
 // Largest magnitude over a pair of lanes (2j, 2j + 1): one block.
 __device__ __forceinline__ float pair_max(float v) {
   const int o = __builtin_amdgcn_mov_dpp(__float_as_int(v), 0xb1, 0xf, 0xf,
