@@ -387,14 +387,13 @@ int apply_config(pcoll_req_t r, const pcoll_config_t& c) {
   pcoll_config_t eff = c;
   if (room && !c.groups) eff.groups_per_cu = 1;
   // Unless the count is given, no more workgroups than the device holds at
-  // once (resident_groups); and no more than the launch has tiles for
-  // sure.  So every
-  // workgroup owns a first tile (its own number), a small message does not
-  // dispatch workers that would only wait, and an epoch cannot complete
-  // before every workgroup of its launch has started; a graph replay,
-  // whose workgroups read the epoch stamp from host memory when they
-  // start, depends on that (the host writes the next stamp only after the
-  // epoch completed).
+  // once (resident_groups).  And no more than the launch has tiles for
+  // sure, so that every workgroup owns a first tile (its own number), a
+  // small message does not dispatch workers that would only wait, and an
+  // epoch cannot complete before every workgroup of its launch has
+  // started; a graph replay, whose workgroups read the epoch stamp from
+  // host memory when they start, depends on that (the host writes the next
+  // stamp only after the epoch completed).
   const bool deep = !room && c.unroll != 2;
   int groups = launch_groups(eff, r->cus, r->dtype, r->nparts_total,
                              [&](uint32_t k) { return r->parts[k].rows; });
