@@ -245,3 +245,48 @@ def test_producer_room_is_automatic_after_a_device_signal(orc):
     assert launches[2] == (cus, 4, 2)
     assert req.config().producers == -1
     req.free()
+
+
+@pytest.mark.parametrize("producers", [0, 1])
+def test_staggered_rank_marks_on_the_device(orc, producers):
+    """Stragglers, as the benchmark plays them: rank r's partition j is
+    marked on a side stream at (j + lag_r) gaps, each mark after a bounded
+    spin, while the epoch's kernel waits; every partition is reduced once
+    its last rank has marked it.  Bitwise against the oracle over two
+    epochs, in the tuned launch (producers = 0) and in the launch that
+    leaves room for producers (producers = 1)."""
+    P, n, nparts = 4, 256 * 1024 + 13, 16
+    say(f"case staggered device marks P={P} n={n} nparts={nparts} "
+        f"producers={producers}")
+    xs, dx, out = _case(P, n, nparts, 81)
+    want = as_u32(orc.sum_f32_f32([x.numpy() for x in xs]))
+    stream = torch.cuda.Stream(DEV)
+    side = independent_streams(stream, 1)[0]
+    req = new_request([n], pc.FLOAT32, pc.SUM, nparts, P, tile_elems=1024,
+                      producers=producers)
+    req.bind([dx], [out], stream=stream)
+    ids = torch.arange(nparts, dtype=torch.int32, device=DEV)
+    rng = np.random.default_rng(82)
+    lag = rng.uniform(0.0, 3.0, size=P)
+    arrivals = sorted((j + lag[r], r, j) for r in range(P)
+                      for j in range(nparts))
+    torch.cuda.synchronize()
+    for epoch in range(2):
+        out.fill_(float("nan"))
+        torch.cuda.synchronize()
+        req.start()
+        t = 0.0
+        for when, r, j in arrivals:
+            cycles = int((when - t) * 20000)  # about 10 us per gap
+            t = when
+            if cycles > 0:
+                with torch.cuda.stream(side):
+                    torch.cuda._sleep(cycles)
+            req.pready_rank_on_stream(r, ids[j:j + 1], 1, side)
+        if not _signals_ran([side]):
+            pytest.fail(f"marks did not run beside the kernel: {_launch(req)}")
+        req.wait()
+        torch.cuda.synchronize()
+        assert np.array_equal(as_u32(out.cpu().numpy()), want), epoch
+        assert all(req.parrived(p) for p in range(nparts))
+    req.free()
